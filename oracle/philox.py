@@ -1,0 +1,197 @@
+"""Oracle random numbers: Philox4x32-10, Poisson and Gaussian draws.
+
+Test infrastructure (see the package docstring).
+
+The paper adds photon noise and detector noise to the sub-aperture image
+before the centroid (Sec. 4, "noise-added image"; Sec. 5, photon-noise
+regime).  It does not say how, so the draws are keyed by counters rather
+than by consumption order (reading O8):
+
+* Philox4x32-10 is the counter-based generator of Salmon, Moraes, Dror and
+  Shaw, "Parallel Random Numbers: As Easy as 1, 2, 3" (SC'11), written
+  here from its published definition.
+* Poisson counts: sequential-search inversion for lambda < 10 and the
+  transformed-rejection method with squeeze (PTRS) of W. Hormann, "The
+  transformed rejection method for generating Poisson random variables",
+  Insurance: Mathematics and Economics 12 (1993) 39-45, for lambda >= 10.
+  Both decide an integer, so they run in FP32 arithmetic, the precision
+  the GPU path takes the same decision in.
+* Read noise: Box-Muller on words 2 and 3 of the trial-0 block.
+
+Counter of pixel p of global sub-aperture g in frame f at trial t:
+(t, p, g, f); key: (seed mod 2^32, seed div 2^32).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+M0 = 0xD2511F53
+M1 = 0xCD9E8D57
+W0 = 0x9E3779B9
+W1 = 0xBB67AE85
+MASK32 = 0xFFFFFFFF
+
+POISSON_SPLIT = 10.0
+PTRS_MAX_TRIALS = 64
+INVERSION_MAX_K = 100
+
+
+def philox4x32_10(c0, c1, c2, c3, k0, k1):
+    """Ten Philox4x32 rounds on counter (c0..c3) with key (k0, k1); uint32 arrays.
+
+    Round: multiply words 0 and 2 by the two multipliers, 64-bit product
+    split into hi/lo; new block (hi1^c1^k0, lo1, hi0^c3^k1, lo0); the key
+    is bumped by the two Weyl constants before every round but the first.
+    """
+    c0, c1, c2, c3 = (np.asarray(v, dtype=np.uint64) & MASK32 for v in (c0, c1, c2, c3))
+    k0 = np.uint64(int(k0) & MASK32)
+    k1 = np.uint64(int(k1) & MASK32)
+    m0, m1 = np.uint64(M0), np.uint64(M1)
+    s32 = np.uint64(32)
+    mask = np.uint64(MASK32)
+    for r in range(10):
+        if r:
+            k0 = np.uint64((int(k0) + W0) & MASK32)
+            k1 = np.uint64((int(k1) + W1) & MASK32)
+        p0 = m0 * c0
+        p1 = m1 * c2
+        hi0, lo0 = p0 >> s32, p0 & mask
+        hi1, lo1 = p1 >> s32, p1 & mask
+        c0, c1, c2, c3 = hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0
+    return tuple(v.astype(np.uint32) for v in (c0, c1, c2, c3))
+
+
+def uniform_f32(x):
+    """Uniform in (0, 1) from a 32-bit word: ((x >> 9) + 1/2) * 2^-23, exact in FP32."""
+    x = np.asarray(x, dtype=np.uint32)
+    return ((x >> np.uint32(9)).astype(np.float32) + np.float32(0.5)) * np.float32(2.0 ** -23)
+
+
+def noise_words(seed, trial, pix, gsub, frame):
+    k0 = seed & MASK32
+    k1 = (seed >> 32) & MASK32
+    return philox4x32_10(trial, pix, gsub, frame, k0, k1)
+
+
+def log_factorial_f32(k):
+    """ln(k!) rounded to FP32."""
+    k = np.asarray(k)
+    out = np.array([math.lgamma(float(v) + 1.0) for v in k.ravel()], dtype=np.float64)
+    return out.reshape(k.shape).astype(np.float32)
+
+
+def poisson_inversion_f32(lam, u):
+    """Sequential-search inversion: smallest k with u <= sum_{j<=k} e^-lam lam^j / j!.
+
+    FP32: p0 = exp(-lam); p_k = (p_{k-1} * lam) / k; F_k = F_{k-1} + p_k.
+    """
+    lam = np.asarray(lam, dtype=np.float32)
+    u = np.asarray(u, dtype=np.float32)
+    p = np.exp(-lam).astype(np.float32)
+    F = p.copy()
+    k = np.zeros(lam.shape, dtype=np.int64)
+    active = u > F
+    kk = 0
+    while np.any(active) and kk < INVERSION_MAX_K:
+        kk += 1
+        p = np.where(active, (p * lam) / np.float32(kk), p).astype(np.float32)
+        F = np.where(active, F + p, F).astype(np.float32)
+        k = np.where(active, kk, k)
+        active = active & (u > F)
+    return k
+
+
+def ptrs_constants_f32(lam):
+    lam = np.asarray(lam, dtype=np.float32)
+    f = np.float32
+    slam = np.sqrt(lam)
+    loglam = np.log(lam)
+    b = f(0.931) + f(2.53) * slam
+    a = f(-0.059) + f(0.02483) * b
+    invalpha = f(1.1239) + f(1.1328) / (b - f(3.4))
+    vr = f(0.9277) - f(3.6224) / (b - f(2.0))
+    return loglam, a, b, invalpha, vr
+
+
+def ptrs_trial_f32(lam, u, v):
+    """One PTRS trial in FP32: returns (k, accepted)."""
+    f = np.float32
+    lam = np.asarray(lam, dtype=np.float32)
+    loglam, a, b, invalpha, vr = ptrs_constants_f32(lam)
+    U = np.asarray(u, dtype=np.float32) - f(0.5)
+    V = np.asarray(v, dtype=np.float32)
+    us = f(0.5) - np.abs(U)
+    kf = np.floor((f(2.0) * a / us + b) * U + lam + f(0.43)).astype(np.float32)
+    quick = (us >= f(0.07)) & (V <= vr)
+    reject = (kf < 0) | ((us < f(0.013)) & (V > us))
+    kc = np.maximum(kf, 0).astype(np.int64)
+    lhs = np.log(V) + np.log(invalpha) - np.log(a / (us * us) + b)
+    rhs = -lam + kf * loglam - log_factorial_f32(kc)
+    accept = quick | (~reject & (lhs <= rhs))
+    return kc, accept
+
+
+def poisson_counts(lam, seed, pix, gsub, frame):
+    """Poisson counts for expected values lam (any shape) at the given counters."""
+    lam = np.asarray(lam, dtype=np.float32)
+    shape = lam.shape
+    lam = lam.ravel()
+    pix = np.broadcast_to(np.asarray(pix, dtype=np.uint64), shape).ravel()
+    gsub = np.broadcast_to(np.asarray(gsub, dtype=np.uint64), shape).ravel()
+    frame = np.broadcast_to(np.asarray(frame, dtype=np.uint64), shape).ravel()
+    out = np.zeros(lam.shape, dtype=np.int64)
+    w = noise_words(seed, np.zeros_like(pix), pix, gsub, frame)
+    small = (lam > 0) & (lam < POISSON_SPLIT)
+    if np.any(small):
+        out[small] = poisson_inversion_f32(lam[small], uniform_f32(w[0][small]))
+    big = np.nonzero(lam >= POISSON_SPLIT)[0]
+    done = np.zeros(big.shape, dtype=bool)
+    for t in range(PTRS_MAX_TRIALS):
+        idx = big[~done]
+        if idx.size == 0:
+            break
+        if t == 0:
+            u, v = w[0][idx], w[1][idx]
+        else:
+            wt = noise_words(seed, np.full(idx.shape, t, np.uint64), pix[idx], gsub[idx], frame[idx])
+            u, v = wt[0], wt[1]
+        k, acc = ptrs_trial_f32(lam[idx], uniform_f32(u), uniform_f32(v))
+        out[idx[acc]] = k[acc]
+        sel = np.nonzero(~done)[0]
+        done[sel[acc]] = True
+    if not np.all(done):
+        rest = big[~done]
+        out[rest] = np.floor(lam[rest] + np.float32(0.5)).astype(np.int64)
+    return out.reshape(shape)
+
+
+def read_noise(seed, pix, gsub, frame):
+    """Standard normal per pixel: sqrt(-2 ln u1) cos(2 pi u2) from words 2, 3 of trial 0 (FP64)."""
+    pix = np.asarray(pix, dtype=np.uint64)
+    shape = np.broadcast_shapes(pix.shape, np.shape(gsub), np.shape(frame))
+    pix = np.broadcast_to(pix, shape).ravel()
+    gsub = np.broadcast_to(np.asarray(gsub, dtype=np.uint64), shape).ravel()
+    frame = np.broadcast_to(np.asarray(frame, dtype=np.uint64), shape).ravel()
+    w = noise_words(seed, np.zeros_like(pix), pix, gsub, frame)
+    u1 = uniform_f32(w[2]).astype(np.float64)
+    u2 = uniform_f32(w[3]).astype(np.float64)
+    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    return z.reshape(shape)
+
+
+def inversion_margin(lam, u):
+    """FP64 distance from u to the nearest CDF boundary of Poisson(lam) (tie test)."""
+    lam = float(lam)
+    u = float(u)
+    p = math.exp(-lam)
+    F = p
+    best = abs(u - F)
+    for k in range(1, INVERSION_MAX_K):
+        p *= lam / k
+        F += p
+        best = min(best, abs(u - F))
+        if F > u + 0.01:
+            break
+    return best
