@@ -1,0 +1,232 @@
+/*
+ * shwfs.h - C ABI of the MI355X Shack-Hartmann wavefront-sensor engine.
+ *
+ * Computes, for every valid sub-aperture of every sensor of every frame,
+ * the measurement of the LGS Shack-Hartmann module described in Sec. 4 of
+ * Arcidiacono et al., "End to end numerical simulations of the MAORY
+ * multiconjugate adaptive optics system" (SPIE 2014, arXiv:1408.0698):
+ * the wavefront is split into sub-apertures, each spot is computed by
+ * Fourier transform, the spot is convolved with a Gaussian modelling the
+ * extent of the laser projection on the sodium layer, noise is added and
+ * the centroid of the final image gives the X and Y slopes that the closed
+ * loop multiplies by the control matrix (Sec. 3, closed-loop block).  The
+ * second user is the PSF block of Sec. 3: PSF at a chosen wavelength and
+ * the Strehl ratio.
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: SHW_OK (0) or a negative SHW_E_* code.  On error
+ *     shw_last_error() returns a message (thread-local, valid until the
+ *     next call on the same thread).
+ *   - Argument validation is done on the host before any HIP call, so a
+ *     call that returns SHW_E_INVALID / SHW_E_ABI / SHW_E_UNSUPPORTED has
+ *     launched nothing and touched no device memory.
+ *   - Pointers named d_* are device pointers owned by the caller; they
+ *     must stay valid until the work queued on the stream has completed.
+ *     Plans own their internal tables and workspaces.
+ *   - Compute calls are asynchronous on the given HIP stream (hipStream_t
+ *     passed as void*; NULL = the default stream).  A plan must not be used
+ *     from two streams at once.
+ *   - Arrays are row-major (C order); strides are in elements.
+ */
+#ifndef SHWFS_H
+#define SHWFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHW_ABI_VERSION 1
+
+enum {
+  SHW_OK = 0,
+  SHW_E_INVALID = -1,     /* bad argument (null pointer, size, stride, geometry) */
+  SHW_E_NOMEM = -2,       /* device allocation failed */
+  SHW_E_DEVICE = -3,      /* a HIP call failed; message from shw_last_error() */
+  SHW_E_UNSUPPORTED = -4, /* valid geometry for which no kernel is built */
+  SHW_E_ABI = -5          /* abi_version does not match SHW_ABI_VERSION */
+};
+
+/* shw_wfs_config.flags */
+#define SHW_FLAG_NOISE 1u          /* Poisson photon noise + Gaussian read noise */
+#define SHW_PRECISION_SHIFT 4      /* bits 4..7 select the transform arithmetic */
+#define SHW_PREC_FP32 0u           /* FP32 register/LDS FFTs */
+#define SHW_PREC_BF16 1u           /* DFT-matrix GEMMs on MFMA, bf16 operands */
+#define SHW_PREC_BF16X3 2u         /* bf16 hi+lo split, three products */
+#define SHW_PREC_FP16X3 3u         /* scaled fp16 hi+lo split, three products */
+
+/*
+ * Sensor geometry (Sec. 4 LGS module inputs; Sec. 2 pupil sampling).
+ *
+ * Pupil: pupil_n x pupil_n pixels of pupil_dx_m metres; pixel (r, c) has its
+ * centre at ((c + 1/2 - pupil_n/2), (r + 1/2 - pupil_n/2)) pixels from the
+ * axis and is lit iff obstruction*pupil_n/2 <= radius <= pupil_n/2.
+ * Sub-apertures: n_subap x n_subap squares of npx = pupil_n / n_subap pixels;
+ * valid iff the lit fraction is >= min_illum; valid ones are numbered in
+ * row-major order.
+ * Spot: field A exp(2 pi i OPD / wavelength) of a sub-aperture zero padded
+ * to fft_n x fft_n, transform centred half a pixel off the grid so that the
+ * spot of a flat wavefront is symmetric about ((fft_n-1)/2, (fft_n-1)/2),
+ * intensity |F|^2 / fft_n^2; embedded at the centre of a conv_n grid.
+ * LGS (lgs != 0): circular convolution with a normalised elongated
+ * Gaussian: long axis from the launcher to the sub-aperture, FWHM
+ * sqrt(el^2 + spot_fwhm^2) with el = elong_max * distance / diameter
+ * (or the geometric distance * na_fwhm / na_height^2 when elong_max <= 0),
+ * short-axis FWHM spot_fwhm; periodised on the conv_n grid.
+ * Detector: conv_n -> det_n pixels by area-overlap rebinning.
+ * Photometry: photons_per_subap > 0 scales a sub-aperture image to
+ * photons_per_subap * (lit fraction) electrons; with SHW_FLAG_NOISE the
+ * image becomes Poisson counts + ron_e * N(0,1).  Centroid: image minus
+ * threshold_e clipped at zero (threshold 0 when photons_per_subap == 0).
+ */
+typedef struct shw_wfs_config {
+  int32_t abi_version;        /* must equal SHW_ABI_VERSION */
+  int32_t pupil_n;            /* pixels across the pupil */
+  double pupil_dx_m;          /* metres per pupil pixel, > 0 */
+  double obstruction;         /* linear central obstruction, [0, 1) */
+  int32_t n_subap;            /* sub-apertures across; divides pupil_n */
+  int32_t fft_n;              /* spot transform size, >= npx, multiple of npx */
+  int32_t conv_n;             /* convolution grid, >= fft_n, conv_n - fft_n even */
+  int32_t det_n;              /* detector pixels across a sub-aperture, <= conv_n */
+  int32_t lgs;                /* 0: NGS (no sodium kernel); 1: LGS */
+  uint32_t flags;             /* SHW_FLAG_NOISE | (precision << SHW_PRECISION_SHIFT) */
+  double min_illum;           /* valid if lit fraction >= min_illum, (0, 1] */
+  double wavelength_m;        /* > 0 */
+  double na_height_m;         /* sodium layer height (geometric law only) */
+  double na_fwhm_m;           /* sodium layer thickness (geometric law only) */
+  double elong_max_arcsec;    /* elongation across the full diameter; <= 0: geometric */
+  double spot_fwhm_arcsec;    /* laser spot FWHM, > 0 when lgs */
+  double photons_per_subap;   /* >= 0 */
+  double ron_e;               /* read noise, electrons rms, >= 0 */
+  double threshold_e;         /* centroid threshold, electrons */
+} shw_wfs_config;
+
+/* Launch-telescope position of one LGS sensor, pupil coordinates in metres. */
+typedef struct shw_lgs_geom {
+  double launch_x_m;
+  double launch_y_m;
+} shw_lgs_geom;
+
+typedef struct shw_wfs_plan shw_wfs_plan;   /* opaque, owned by the library */
+typedef struct shw_psf_plan shw_psf_plan;   /* opaque, owned by the library */
+
+/* Message for the last non-OK return on this thread ("" if none). */
+const char* shw_last_error(void);
+
+/* Library version: SHW_ABI_VERSION. */
+int32_t shw_abi_version(void);
+
+/*
+ * Host-only validation of a geometry (no HIP call).  Returns SHW_OK,
+ * SHW_E_ABI, SHW_E_INVALID or SHW_E_UNSUPPORTED (no kernel instantiated for
+ * this (npx, fft_n, conv_n, det_n, lgs) combination).  geom may be NULL
+ * for NGS; for LGS it holds n_wfs entries.
+ */
+int shw_wfs_config_check(const shw_wfs_config* cfg, int32_t n_wfs, const shw_lgs_geom* geom);
+
+/*
+ * Host-only valid-sub-aperture table (Sec. 4: the wavefront is split into
+ * sub-apertures).  *n_valid receives the count; valid_idx (nullable, room
+ * for n_subap^2 entries) receives row-major indices a*n_subap + b; illum
+ * (nullable, same room) the lit fractions.
+ */
+int shw_wfs_geometry(const shw_wfs_config* cfg, int32_t* n_valid, int32_t* valid_idx, double* illum);
+
+/*
+ * Create a plan for n_wfs sensors of one geometry (1 <= n_wfs <= 4096).
+ * Allocates device tables on the current HIP device and, for LGS, computes
+ * the kernel spectra of every valid sub-aperture on the GPU (FP64, stored
+ * FP32, (conv_n/2 + 1) x conv_n reals per sub-aperture: the spectrum of a
+ * point-symmetric kernel is real and point-symmetric).  Synchronous.
+ * On success *out owns the plan; release it with shw_wfs_plan_destroy.
+ */
+int shw_wfs_plan_create(const shw_wfs_config* cfg, int32_t n_wfs, const shw_lgs_geom* geom,
+                        shw_wfs_plan** out);
+
+/* Plan facts: valid sub-apertures per sensor, device bytes held.  Either pointer may be NULL. */
+int shw_wfs_plan_info(const shw_wfs_plan* plan, int32_t* n_valid, size_t* device_bytes);
+
+/*
+ * Copy the stored kernel spectra of sensor wfs (LGS plans only) into d_out
+ * (device, n_valid * (conv_n/2 + 1) * conv_n floats, layout
+ * [subap][row k = 0..conv_n/2][column l], values K^(k,l) / conv_n^2).
+ */
+int shw_wfs_plan_kernel_spectra(const shw_wfs_plan* plan, int32_t wfs, float* d_out, void* hip_stream);
+
+/*
+ * sh_wfs_measure - slopes of n_frames x n_wfs sensors (Sec. 4 LGS SH module).
+ *
+ * d_opd_m     : OPD in metres, FP32, device.  Element (frame f, sensor w,
+ *               row r, column c) at d_opd_m[f*frame_stride + w*wfs_stride +
+ *               r*row_pitch + c]; row_pitch >= pupil_n, all strides >= 0.
+ * n_frames    : >= 0 (0 is a no-op).
+ * seed, frame0: noise key and the frame number of the first frame; the
+ *               noise of pixel p of sub-aperture i of sensor w in frame
+ *               frame0 + f is drawn from Philox4x32-10 with key seed and
+ *               counter (trial, p, w*n_valid + i, frame0 + f), so a result
+ *               does not depend on how frames are batched.
+ *               frame0 + n_frames must be <= 2^32.
+ * d_slopes    : [n_frames][n_wfs][2][n_valid] FP32, detector pixels from
+ *               the sub-aperture centre, X (columns) block then Y block.
+ * d_images    : nullable; [n_frames][n_wfs][n_valid][det_n][det_n] FP32
+ *               detector images (electrons, before the threshold).
+ * d_flags     : nullable; [n_frames][n_wfs][n_valid] uint8, 1 where nothing
+ *               was left above the threshold (slopes set to 0).
+ * Asynchronous on hip_stream.
+ */
+int sh_wfs_measure(shw_wfs_plan* plan, const float* d_opd_m, int64_t row_pitch, int64_t wfs_stride,
+                   int64_t frame_stride, int32_t n_frames, uint64_t seed, uint64_t frame0,
+                   float* d_slopes, float* d_images, uint8_t* d_flags, void* hip_stream);
+
+/*
+ * One item of a mixed batch: one frame of all sensors of a plan.
+ * Fields as in sh_wfs_measure with n_frames = 1.
+ */
+typedef struct shw_work {
+  shw_wfs_plan* plan;
+  const float* d_opd_m;
+  int64_t row_pitch;
+  int64_t wfs_stride;
+  uint64_t seed;
+  uint64_t frame;
+  float* d_slopes;     /* [n_wfs][2][n_valid] */
+  float* d_images;     /* nullable, [n_wfs][n_valid][det_n][det_n] */
+} shw_work;
+
+/*
+ * sh_wfs_measure_batch - n work items of possibly different plans in as few
+ * launches as the plan geometries allow (one per distinct kernel shape).
+ * Each item's result is identical to sh_wfs_measure on that item alone.
+ * Items must not share output buffers.  Asynchronous on hip_stream.
+ */
+int sh_wfs_measure_batch(const shw_work* items, int32_t n, void* hip_stream);
+
+int shw_wfs_plan_destroy(shw_wfs_plan* plan);
+
+/*
+ * Science PSF (Sec. 3 PSF block, Sec. 5 integrated PSF and Strehl ratio).
+ * P(v,u) = |sum_{y,x} A e^{2 pi i OPD/lambda} e^{-2 pi i ((u - M/2) x + (v - M/2) y)/M}|^2 / (sum A)^2
+ * on an M x M grid (fft_m >= pupil_n); the on-axis direction is pixel
+ * (M/2, M/2) and the diffraction-limited PSF has the value 1 there.
+ */
+int shw_psf_plan_create(int32_t abi_version, int32_t pupil_n, double pupil_dx_m, double obstruction,
+                        int32_t fft_m, double wavelength_m, shw_psf_plan** out);
+
+/*
+ * psf_accumulate - d_psf_acc[v*M + u] += sum over the n_frames frames of P
+ * (the caller zeroes the accumulator once), d_strehl[f] = P_f(M/2, M/2)
+ * (nullable).  Frame f's OPD (metres, FP32) starts at
+ * d_opd_m + f*frame_stride with rows row_pitch apart.  Asynchronous.
+ */
+int psf_accumulate(shw_psf_plan* plan, const float* d_opd_m, int64_t row_pitch, int64_t frame_stride,
+                   int32_t n_frames, float* d_psf_acc, float* d_strehl, void* hip_stream);
+
+int shw_psf_plan_destroy(shw_psf_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHWFS_H */

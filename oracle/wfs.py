@@ -147,6 +147,7 @@ def measure_one(cfg, opd_m, valid_idx, illum, khat=None, seed=0, gsub0=0, frame=
     noise = bool(cfg.flags & 1) and cfg.photons_per_subap > 0
     thr = cfg.threshold_e if cfg.photons_per_subap > 0 else 0.0
     imgs = np.empty((len(sel), cfg.det_n, cfg.det_n))
+    lams = np.empty((len(sel), cfg.det_n, cfg.det_n))
     sx = np.empty(len(sel))
     sy = np.empty(len(sel))
     empty = np.empty(len(sel), dtype=bool)
@@ -163,10 +164,11 @@ def measure_one(cfg, opd_m, valid_idx, illum, khat=None, seed=0, gsub0=0, frame=
             img = lam
         x, y, e = centroid(img, thr)
         imgs[s0:s0 + len(ii)] = img
+        lams[s0:s0 + len(ii)] = lam
         sx[s0:s0 + len(ii)] = x
         sy[s0:s0 + len(ii)] = y
         empty[s0:s0 + len(ii)] = e
-    return dict(slopes=np.stack([sx, sy]), images=imgs, empty=empty)
+    return dict(slopes=np.stack([sx, sy]), images=imgs, lam=lams, empty=empty)
 
 
 class Sensor:
@@ -192,12 +194,17 @@ class Sensor:
         return np.stack([self._khat[(w, int(i))] for i in sel])
 
     def measure(self, opd, seed=0, frame0=0, subset=None):
-        """opd: [n_frames][n_wfs][N_p][N_p].  Returns slopes [F][W][2][S'], images [F][W][S'][d][d]."""
+        """opd: [n_frames][n_wfs][N_p][N_p].
+
+        Returns slopes [F][W][2][S'], images [F][W][S'][d][d] (electrons after noise),
+        lam (expected electrons before noise, same shape) and empty [F][W][S'].
+        """
         opd = np.asarray(opd)
         nf = opd.shape[0]
         S = self.n_valid if subset is None else len(subset)
         slopes = np.empty((nf, self.n_wfs, 2, S))
         images = np.empty((nf, self.n_wfs, S, self.cfg.det_n, self.cfg.det_n))
+        lam = np.empty_like(images)
         empty = np.empty((nf, self.n_wfs, S), dtype=bool)
         for f in range(nf):
             for w in range(self.n_wfs):
@@ -206,5 +213,6 @@ class Sensor:
                                 seed=seed, gsub0=w * self.n_valid, frame=frame0 + f, subset=subset)
                 slopes[f, w] = r["slopes"]
                 images[f, w] = r["images"]
+                lam[f, w] = r["lam"]
                 empty[f, w] = r["empty"]
-        return dict(slopes=slopes, images=images, empty=empty)
+        return dict(slopes=slopes, images=images, lam=lam, empty=empty)

@@ -1,0 +1,44 @@
+// internal.h - structures shared by the host library and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace shw {
+
+// Arguments of one fused Shack-Hartmann launch (all work items share a plan geometry).
+struct WfsLaunch {
+  const float* opd;          // OPD metres
+  int64_t row_pitch, wfs_stride, frame_stride;
+  const int32_t* valid_idx;  // [n_valid] row-major sub-aperture index
+  const float* khat;         // [n_wfs * n_valid][conv_n/2 + 1][conv_n] (LGS) or null
+  float* slopes;             // [items / n_valid][2][n_valid]
+  float* images;             // nullable [items][det_n][det_n]
+  uint8_t* flags;            // nullable [items]
+  int64_t total;             // n_frames * n_wfs * n_valid
+  int32_t n_valid, n_wfs, n_subap, pad0;
+  double inv_lambda;         // 1 / wavelength (1/m)
+  float r2_outer, r2_inner;  // pupil annulus in squared pixel units
+  float half_n;              // pupil_n / 2
+  float ph_scale;            // photons / npx^2, 0 = no photometry
+  float ron, thr;
+  int32_t noise;
+  uint32_t key0, key1, frame0;
+};
+
+// Shape of a compiled fused kernel.
+struct WfsShape {
+  int npx, fft_n, conv_n, det_n, lgs;
+};
+
+// Returns true if a kernel for this shape is compiled in.
+bool wfs_shape_supported(const WfsShape& s);
+
+// Launch the fused kernel for a.total work items. Returns the HIP error.
+hipError_t launch_wfs_fused(const WfsShape& s, const WfsLaunch& a, hipStream_t st);
+
+// Kernel spectra: params [n][3] = (sigma_par, sigma_perp, psi) in conv-grid
+// pixels / radians (device, FP64); out [n][conv_n/2+1][conv_n] FP32, scaled by 1/conv_n^2.
+hipError_t launch_lgs_spectra(int conv_n, const double* d_params, int64_t n, float* d_out, hipStream_t st);
+
+}  // namespace shw

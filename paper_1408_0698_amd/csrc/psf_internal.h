@@ -1,0 +1,24 @@
+// psf_internal.h - PSF kernel arguments shared by the host library and psf_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace shw {
+
+struct PsfLaunch {
+  const float* opd;        // OPD metres, frame f at opd + f * frame_stride
+  int64_t row_pitch, frame_stride;
+  int32_t pupil_n, pad0;
+  double inv_lambda;
+  float r2_outer, r2_inner, half_n;
+  float inv_norm;          // 1 / (sum A)^2
+};
+
+bool psf_size_supported(int fft_m, int pupil_n);
+
+// Row and column passes over frames [f0, f0 + nf); T holds nf * pupil_n * fft_m complex.
+hipError_t launch_psf_chunk(const PsfLaunch& a, int64_t f0, int nf, float2* T, float* acc, float* strehl,
+                            hipStream_t st);
+
+}  // namespace shw

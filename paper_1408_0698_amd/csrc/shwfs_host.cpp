@@ -1,0 +1,439 @@
+// shwfs_host.cpp - host side of the C ABI (include/shwfs.h).
+//
+// Validation, sub-aperture geometry and the LGS kernel parameters are
+// computed here in FP64 on the host; every per-frame step runs in the HIP
+// kernels.  Validation touches no HIP API, so it runs without a GPU.
+#include "../../include/shwfs.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "psf_internal.h"
+
+using namespace shw;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ok() {
+  g_err.clear();
+  return SHW_OK;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) return fail(SHW_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
+  return fail(SHW_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr double kArcsec = 3.14159265358979323846 / (180.0 * 3600.0);
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+struct shw_wfs_plan {
+  shw_wfs_config cfg;
+  int32_t n_wfs = 0;
+  int32_t n_valid = 0;
+  int32_t npx = 0;
+  WfsShape shape{};
+  int device = 0;
+  int32_t* d_valid = nullptr;
+  float* d_khat = nullptr;
+  size_t bytes = 0;
+  std::vector<int32_t> valid;
+};
+
+
+
+extern "C" const char* shw_last_error(void) { return g_err.c_str(); }
+
+extern "C" int32_t shw_abi_version(void) { return SHW_ABI_VERSION; }
+
+// ---------------------------------------------------------------- validation
+
+static int check_config(const shw_wfs_config* c, int32_t n_wfs, const shw_lgs_geom* geom) {
+  if (!c) return fail(SHW_E_INVALID, "config is NULL");
+  if (c->abi_version != SHW_ABI_VERSION)
+    return fail(SHW_E_ABI, "abi_version %d, library %d", c->abi_version, SHW_ABI_VERSION);
+  if (n_wfs < 1 || n_wfs > 4096) return fail(SHW_E_INVALID, "n_wfs %d outside [1, 4096]", n_wfs);
+  if (c->pupil_n < 1 || c->pupil_n > 16384) return fail(SHW_E_INVALID, "pupil_n %d outside [1, 16384]", c->pupil_n);
+  if (!(is_fin(c->pupil_dx_m) && c->pupil_dx_m > 0)) return fail(SHW_E_INVALID, "pupil_dx_m must be > 0");
+  if (!(is_fin(c->obstruction) && c->obstruction >= 0 && c->obstruction < 1))
+    return fail(SHW_E_INVALID, "obstruction must be in [0, 1)");
+  if (c->n_subap < 1 || c->pupil_n % c->n_subap != 0)
+    return fail(SHW_E_INVALID, "n_subap %d must divide pupil_n %d", c->n_subap, c->pupil_n);
+  const int npx = c->pupil_n / c->n_subap;
+  if (c->fft_n < npx || c->fft_n % npx != 0)
+    return fail(SHW_E_INVALID, "fft_n %d must be a multiple of the sub-aperture size %d", c->fft_n, npx);
+  if (c->conv_n < c->fft_n || (c->conv_n - c->fft_n) % 2 != 0)
+    return fail(SHW_E_INVALID, "conv_n %d must be >= fft_n %d with an even difference", c->conv_n, c->fft_n);
+  if (c->det_n < 1 || c->det_n > c->conv_n) return fail(SHW_E_INVALID, "det_n %d outside [1, conv_n]", c->det_n);
+  if (c->lgs != 0 && c->lgs != 1) return fail(SHW_E_INVALID, "lgs must be 0 or 1");
+  if (c->flags & ~(SHW_FLAG_NOISE | (0xFu << SHW_PRECISION_SHIFT))) return fail(SHW_E_INVALID, "unknown flag bits");
+  const unsigned prec = (c->flags >> SHW_PRECISION_SHIFT) & 0xFu;
+  if (prec > SHW_PREC_FP16X3) return fail(SHW_E_INVALID, "unknown precision %u", prec);
+  if (!(is_fin(c->min_illum) && c->min_illum > 0 && c->min_illum <= 1))
+    return fail(SHW_E_INVALID, "min_illum must be in (0, 1]");
+  if (!(is_fin(c->wavelength_m) && c->wavelength_m > 0)) return fail(SHW_E_INVALID, "wavelength_m must be > 0");
+  if (!(is_fin(c->photons_per_subap) && c->photons_per_subap >= 0))
+    return fail(SHW_E_INVALID, "photons_per_subap must be >= 0");
+  if (!(is_fin(c->ron_e) && c->ron_e >= 0)) return fail(SHW_E_INVALID, "ron_e must be >= 0");
+  if (!is_fin(c->threshold_e)) return fail(SHW_E_INVALID, "threshold_e must be finite");
+  if (c->lgs) {
+    if (!geom) return fail(SHW_E_INVALID, "LGS geometry needs launch positions");
+    if (!(is_fin(c->spot_fwhm_arcsec) && c->spot_fwhm_arcsec > 0))
+      return fail(SHW_E_INVALID, "spot_fwhm_arcsec must be > 0");
+    if (!is_fin(c->elong_max_arcsec)) return fail(SHW_E_INVALID, "elong_max_arcsec must be finite");
+    if (c->elong_max_arcsec <= 0 &&
+        !(is_fin(c->na_height_m) && c->na_height_m > 0 && is_fin(c->na_fwhm_m) && c->na_fwhm_m >= 0))
+      return fail(SHW_E_INVALID, "geometric elongation needs na_height_m > 0 and na_fwhm_m >= 0");
+    for (int w = 0; w < n_wfs; ++w)
+      if (!is_fin(geom[w].launch_x_m) || !is_fin(geom[w].launch_y_m))
+        return fail(SHW_E_INVALID, "launch position %d not finite", w);
+  }
+  if (prec != SHW_PREC_FP32) return fail(SHW_E_UNSUPPORTED, "precision %u has no kernel for this shape", prec);
+  const WfsShape shape{npx, c->fft_n, c->conv_n, c->det_n, c->lgs};
+  if (!wfs_shape_supported(shape))
+    return fail(SHW_E_UNSUPPORTED, "no kernel for npx %d, fft_n %d, conv_n %d, det_n %d, lgs %d", npx, c->fft_n,
+                c->conv_n, c->det_n, c->lgs);
+  return SHW_OK;
+}
+
+extern "C" int shw_wfs_config_check(const shw_wfs_config* cfg, int32_t n_wfs, const shw_lgs_geom* geom) {
+  const int r = check_config(cfg, n_wfs, geom);
+  return r == SHW_OK ? ok() : r;
+}
+
+// ---------------------------------------------------------------- geometry
+
+// Lit pupil pixel: centre at half-integer pixel coordinates; the squared radius
+// is exact in FP64, so the annulus test is exact.
+static bool lit(const shw_wfs_config* c, int r, int col) {
+  const double h = c->pupil_n / 2.0;
+  const double a = col + 0.5 - h, b = r + 0.5 - h;
+  const double r2 = a * a + b * b;
+  const double ro = h * h;
+  const double ri = (c->obstruction * h) * (c->obstruction * h);
+  return r2 <= ro && r2 >= ri;
+}
+
+static void valid_table(const shw_wfs_config* c, std::vector<int32_t>& idx, std::vector<double>& illum) {
+  const int n = c->pupil_n / c->n_subap;
+  idx.clear();
+  illum.clear();
+  for (int sa = 0; sa < c->n_subap; ++sa)
+    for (int sb = 0; sb < c->n_subap; ++sb) {
+      int cnt = 0;
+      for (int y = 0; y < n; ++y)
+        for (int x = 0; x < n; ++x) cnt += lit(c, sa * n + y, sb * n + x) ? 1 : 0;
+      const double frac = (double)cnt / (double)(n * n);
+      if (frac >= c->min_illum) {
+        idx.push_back(sa * c->n_subap + sb);
+        illum.push_back(frac);
+      }
+    }
+}
+
+extern "C" int shw_wfs_geometry(const shw_wfs_config* cfg, int32_t* n_valid, int32_t* valid_idx, double* illum) {
+  if (!cfg || !n_valid) return fail(SHW_E_INVALID, "NULL argument");
+  if (cfg->abi_version != SHW_ABI_VERSION) return fail(SHW_E_ABI, "abi_version mismatch");
+  if (cfg->pupil_n < 1 || cfg->n_subap < 1 || cfg->pupil_n % cfg->n_subap != 0 || !(cfg->min_illum > 0) ||
+      !(cfg->obstruction >= 0 && cfg->obstruction < 1))
+    return fail(SHW_E_INVALID, "bad pupil geometry");
+  std::vector<int32_t> idx;
+  std::vector<double> il;
+  valid_table(cfg, idx, il);
+  *n_valid = (int32_t)idx.size();
+  for (size_t k = 0; k < idx.size(); ++k) {
+    if (valid_idx) valid_idx[k] = idx[k];
+    if (illum) illum[k] = il[k];
+  }
+  return ok();
+}
+
+// Gaussian parameters (sigma along, sigma across in FFT pixels; axis angle) of one sub-aperture.
+static void elongation(const shw_wfs_config* c, const shw_lgs_geom& g, int32_t sidx, double out[3]) {
+  const int n = c->pupil_n / c->n_subap;
+  const int sa = sidx / c->n_subap, sb = sidx % c->n_subap;
+  const double xs = ((sb + 0.5) * n - c->pupil_n / 2.0) * c->pupil_dx_m;
+  const double ys = ((sa + 0.5) * n - c->pupil_n / 2.0) * c->pupil_dx_m;
+  const double dx = xs - g.launch_x_m, dy = ys - g.launch_y_m;
+  const double d = std::hypot(dx, dy);
+  const double diam = c->pupil_n * c->pupil_dx_m;
+  const double el = c->elong_max_arcsec > 0 ? c->elong_max_arcsec * d / diam
+                                            : d * c->na_fwhm_m / (c->na_height_m * c->na_height_m) / kArcsec;
+  const double fwhm_par = std::sqrt(el * el + c->spot_fwhm_arcsec * c->spot_fwhm_arcsec);
+  const double px_arcsec = c->wavelength_m / (c->fft_n * c->pupil_dx_m) / kArcsec;
+  const double to_sigma = 1.0 / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+  out[0] = fwhm_par * to_sigma / px_arcsec;
+  out[1] = c->spot_fwhm_arcsec * to_sigma / px_arcsec;
+  out[2] = std::atan2(dy, dx);
+}
+
+// ---------------------------------------------------------------- plan
+
+extern "C" int shw_wfs_plan_destroy(shw_wfs_plan* p) {
+  if (!p) return ok();
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != p->device) (void)hipSetDevice(p->device);
+  if (p->d_valid) (void)hipFree(p->d_valid);
+  if (p->d_khat) (void)hipFree(p->d_khat);
+  if (cur != p->device) (void)hipSetDevice(cur);
+  delete p;
+  return ok();
+}
+
+extern "C" int shw_wfs_plan_create(const shw_wfs_config* cfg, int32_t n_wfs, const shw_lgs_geom* geom,
+                                   shw_wfs_plan** out) {
+  if (!out) return fail(SHW_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int r = check_config(cfg, n_wfs, geom);
+  if (r != SHW_OK) return r;
+  auto* p = new shw_wfs_plan();
+  p->cfg = *cfg;
+  p->n_wfs = n_wfs;
+  p->npx = cfg->pupil_n / cfg->n_subap;
+  p->shape = WfsShape{p->npx, cfg->fft_n, cfg->conv_n, cfg->det_n, cfg->lgs};
+  std::vector<double> illum;
+  valid_table(cfg, p->valid, illum);
+  p->n_valid = (int32_t)p->valid.size();
+  if (p->n_valid == 0) {
+    delete p;
+    return fail(SHW_E_INVALID, "no valid sub-aperture");
+  }
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  e = hipMalloc(&p->d_valid, sizeof(int32_t) * p->n_valid);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_valid, p->valid.data(), sizeof(int32_t) * p->n_valid, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    shw_wfs_plan_destroy(p);
+    return hip_fail(e, "plan tables");
+  }
+  p->bytes = sizeof(int32_t) * p->n_valid;
+  if (cfg->lgs) {
+    const int64_t n = (int64_t)n_wfs * p->n_valid;
+    const int H = cfg->conv_n / 2 + 1;
+    std::vector<double> params((size_t)n * 3);
+    for (int w = 0; w < n_wfs; ++w)
+      for (int i = 0; i < p->n_valid; ++i) elongation(cfg, geom[w], p->valid[i], &params[((size_t)w * p->n_valid + i) * 3]);
+    double* d_params = nullptr;
+    e = hipMalloc(&d_params, sizeof(double) * params.size());
+    if (e == hipSuccess) e = hipMemcpy(d_params, params.data(), sizeof(double) * params.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&p->d_khat, sizeof(float) * (size_t)n * H * cfg->conv_n);
+    if (e == hipSuccess) e = launch_lgs_spectra(cfg->conv_n, d_params, n, p->d_khat, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (d_params) (void)hipFree(d_params);
+    if (e != hipSuccess) {
+      shw_wfs_plan_destroy(p);
+      return hip_fail(e, "kernel spectra");
+    }
+    p->bytes += sizeof(float) * (size_t)n * H * cfg->conv_n;
+  }
+  *out = p;
+  return ok();
+}
+
+extern "C" int shw_wfs_plan_info(const shw_wfs_plan* p, int32_t* n_valid, size_t* device_bytes) {
+  if (!p) return fail(SHW_E_INVALID, "plan is NULL");
+  if (n_valid) *n_valid = p->n_valid;
+  if (device_bytes) *device_bytes = p->bytes;
+  return ok();
+}
+
+extern "C" int shw_wfs_plan_kernel_spectra(const shw_wfs_plan* p, int32_t wfs, float* d_out, void* stream) {
+  if (!p || !d_out) return fail(SHW_E_INVALID, "NULL argument");
+  if (!p->cfg.lgs) return fail(SHW_E_INVALID, "not an LGS plan");
+  if (wfs < 0 || wfs >= p->n_wfs) return fail(SHW_E_INVALID, "wfs %d outside [0, %d)", wfs, p->n_wfs);
+  const size_t per = (size_t)p->n_valid * (p->cfg.conv_n / 2 + 1) * p->cfg.conv_n;
+  hipError_t e = hipMemcpyAsync(d_out, p->d_khat + per * wfs, per * sizeof(float), hipMemcpyDeviceToDevice,
+                                (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "copy spectra");
+  return ok();
+}
+
+// Fill the kernel arguments of one plan; the caller sets the per-call fields.
+static WfsLaunch base_launch(const shw_wfs_plan* p) {
+  const shw_wfs_config& c = p->cfg;
+  WfsLaunch a{};
+  a.valid_idx = p->d_valid;
+  a.khat = p->d_khat;
+  a.n_valid = p->n_valid;
+  a.n_wfs = p->n_wfs;
+  a.n_subap = c.n_subap;
+  a.inv_lambda = 1.0 / c.wavelength_m;
+  const double h = c.pupil_n / 2.0;
+  a.r2_outer = (float)(h * h);
+  a.r2_inner = (float)((c.obstruction * h) * (c.obstruction * h));
+  a.half_n = (float)h;
+  a.ph_scale = c.photons_per_subap > 0 ? (float)(c.photons_per_subap / ((double)p->npx * p->npx)) : 0.0f;
+  a.ron = (float)c.ron_e;
+  a.thr = c.photons_per_subap > 0 ? (float)c.threshold_e : 0.0f;
+  a.noise = (c.flags & SHW_FLAG_NOISE) && c.photons_per_subap > 0 ? 1 : 0;
+  return a;
+}
+
+extern "C" int sh_wfs_measure(shw_wfs_plan* p, const float* d_opd_m, int64_t row_pitch, int64_t wfs_stride,
+                              int64_t frame_stride, int32_t n_frames, uint64_t seed, uint64_t frame0,
+                              float* d_slopes, float* d_images, uint8_t* d_flags, void* stream) {
+  if (!p) return fail(SHW_E_INVALID, "plan is NULL");
+  if (n_frames < 0) return fail(SHW_E_INVALID, "n_frames %d < 0", n_frames);
+  if (n_frames == 0) return ok();
+  if (!d_opd_m || !d_slopes) return fail(SHW_E_INVALID, "NULL OPD or slope buffer");
+  if (row_pitch < p->cfg.pupil_n) return fail(SHW_E_INVALID, "row_pitch %lld < pupil_n", (long long)row_pitch);
+  if (wfs_stride < 0 || frame_stride < 0) return fail(SHW_E_INVALID, "negative stride");
+  if (frame0 + (uint64_t)n_frames > (1ull << 32)) return fail(SHW_E_INVALID, "frame counter exceeds 2^32");
+  WfsLaunch a = base_launch(p);
+  a.opd = d_opd_m;
+  a.row_pitch = row_pitch;
+  a.wfs_stride = wfs_stride;
+  a.frame_stride = frame_stride;
+  a.slopes = d_slopes;
+  a.images = d_images;
+  a.flags = d_flags;
+  a.total = (int64_t)n_frames * p->n_wfs * p->n_valid;
+  a.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+  a.key1 = (uint32_t)(seed >> 32);
+  a.frame0 = (uint32_t)frame0;
+  hipError_t e = launch_wfs_fused(p->shape, a, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "sh_wfs_measure launch");
+  return ok();
+}
+
+extern "C" int sh_wfs_measure_batch(const shw_work* items, int32_t n, void* stream) {
+  if (n < 0) return fail(SHW_E_INVALID, "n %d < 0", n);
+  if (n == 0) return ok();
+  if (!items) return fail(SHW_E_INVALID, "items is NULL");
+  for (int32_t k = 0; k < n; ++k) {
+    const shw_work& w = items[k];
+    if (!w.plan || !w.d_opd_m || !w.d_slopes) return fail(SHW_E_INVALID, "item %d has a NULL field", k);
+    if (w.row_pitch < w.plan->cfg.pupil_n || w.wfs_stride < 0) return fail(SHW_E_INVALID, "item %d stride", k);
+    if (w.frame >= (1ull << 32)) return fail(SHW_E_INVALID, "item %d frame exceeds 2^32", k);
+  }
+  for (int32_t k = 0; k < n; ++k) {
+    const shw_work& w = items[k];
+    const int r = sh_wfs_measure(w.plan, w.d_opd_m, w.row_pitch, w.wfs_stride, 0, 1, w.seed, w.frame, w.d_slopes,
+                                 w.d_images, nullptr, stream);
+    if (r != SHW_OK) return r;
+  }
+  return ok();
+}
+
+// ---------------------------------------------------------------- science PSF
+
+struct shw_psf_plan {
+  int32_t pupil_n = 0;
+  int32_t fft_m = 0;
+  double dx = 0, obstruction = 0, wavelength = 0;
+  int64_t lit = 0;
+  int device = 0;
+  int32_t chunk = 0;          // frames per row/column pass pair
+  float2* d_work = nullptr;   // chunk * pupil_n * fft_m complex
+  size_t bytes = 0;
+};
+
+extern "C" int shw_psf_plan_destroy(shw_psf_plan* p) {
+  if (!p) return ok();
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != p->device) (void)hipSetDevice(p->device);
+  if (p->d_work) (void)hipFree(p->d_work);
+  if (cur != p->device) (void)hipSetDevice(cur);
+  delete p;
+  return ok();
+}
+
+extern "C" int shw_psf_plan_create(int32_t abi_version, int32_t pupil_n, double pupil_dx_m, double obstruction,
+                                   int32_t fft_m, double wavelength_m, shw_psf_plan** out) {
+  if (!out) return fail(SHW_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (abi_version != SHW_ABI_VERSION) return fail(SHW_E_ABI, "abi_version %d, library %d", abi_version, SHW_ABI_VERSION);
+  if (pupil_n < 1 || pupil_n > 16384) return fail(SHW_E_INVALID, "pupil_n %d outside [1, 16384]", pupil_n);
+  if (fft_m < pupil_n) return fail(SHW_E_INVALID, "fft_m %d < pupil_n %d", fft_m, pupil_n);
+  if (!(is_fin(pupil_dx_m) && pupil_dx_m > 0)) return fail(SHW_E_INVALID, "pupil_dx_m must be > 0");
+  if (!(is_fin(obstruction) && obstruction >= 0 && obstruction < 1))
+    return fail(SHW_E_INVALID, "obstruction must be in [0, 1)");
+  if (!(is_fin(wavelength_m) && wavelength_m > 0)) return fail(SHW_E_INVALID, "wavelength_m must be > 0");
+  if (!psf_size_supported(fft_m, pupil_n))
+    return fail(SHW_E_UNSUPPORTED, "no PSF kernel for fft_m %d with pupil_n %d (fft_m 1600, pupil_n <= 800)", fft_m,
+                pupil_n);
+  auto* p = new shw_psf_plan();
+  p->pupil_n = pupil_n;
+  p->fft_m = fft_m;
+  p->dx = pupil_dx_m;
+  p->obstruction = obstruction;
+  p->wavelength = wavelength_m;
+  shw_wfs_config c{};
+  c.pupil_n = pupil_n;
+  c.obstruction = obstruction;
+  for (int r = 0; r < pupil_n; ++r)
+    for (int col = 0; col < pupil_n; ++col) p->lit += lit(&c, r, col) ? 1 : 0;
+  if (p->lit == 0) {
+    delete p;
+    return fail(SHW_E_INVALID, "pupil has no lit pixel");
+  }
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  p->chunk = 8;
+  const size_t work = (size_t)p->chunk * pupil_n * fft_m * sizeof(float2);
+  e = hipMalloc(&p->d_work, work);
+  if (e != hipSuccess) {
+    shw_psf_plan_destroy(p);
+    return hip_fail(e, "PSF workspace");
+  }
+  p->bytes = work;
+  *out = p;
+  return ok();
+}
+
+extern "C" int psf_accumulate(shw_psf_plan* p, const float* d_opd_m, int64_t row_pitch, int64_t frame_stride,
+                              int32_t n_frames, float* d_psf_acc, float* d_strehl, void* stream) {
+  if (!p) return fail(SHW_E_INVALID, "plan is NULL");
+  if (n_frames < 0) return fail(SHW_E_INVALID, "n_frames %d < 0", n_frames);
+  if (n_frames == 0) return ok();
+  if (!d_opd_m || !d_psf_acc) return fail(SHW_E_INVALID, "NULL OPD or accumulator");
+  if (row_pitch < p->pupil_n) return fail(SHW_E_INVALID, "row_pitch %lld < pupil_n", (long long)row_pitch);
+  if (frame_stride < 0) return fail(SHW_E_INVALID, "negative frame_stride");
+  PsfLaunch a{};
+  a.opd = d_opd_m;
+  a.row_pitch = row_pitch;
+  a.frame_stride = frame_stride;
+  a.pupil_n = p->pupil_n;
+  a.inv_lambda = 1.0 / p->wavelength;
+  const double h = p->pupil_n / 2.0;
+  a.r2_outer = (float)(h * h);
+  a.r2_inner = (float)((p->obstruction * h) * (p->obstruction * h));
+  a.half_n = (float)h;
+  a.inv_norm = (float)(1.0 / ((double)p->lit * (double)p->lit));
+  for (int32_t f0 = 0; f0 < n_frames; f0 += p->chunk) {
+    const int nf = n_frames - f0 < p->chunk ? n_frames - f0 : p->chunk;
+    hipError_t e = launch_psf_chunk(a, f0, nf, p->d_work, d_psf_acc, d_strehl, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "psf_accumulate launch");
+  }
+  return ok();
+}

@@ -1,0 +1,215 @@
+"""ctypes binding of libshwfs (include/shwfs.h): argument marshalling only.
+
+Every step of the measurement runs in the HIP kernels of the library.
+Device buffers are torch tensors on the ROCm device (torch names it
+"cuda"); streams are torch streams.  There is no CPU fallback: if the
+library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "lib", "libshwfs.so")
+
+ABI_VERSION = 1
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_ABI = 0, -1, -2, -3, -4, -5
+FLAG_NOISE = 1
+PRECISION_SHIFT = 4
+PREC_FP32, PREC_BF16, PREC_BF16X3, PREC_FP16X3 = 0, 1, 2, 3
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libshwfs.so not built at {LIB_PATH}: run `python -m paper_1408_0698_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+
+class WfsConfigC(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int32), ("pupil_n", C.c_int32), ("pupil_dx_m", C.c_double),
+        ("obstruction", C.c_double), ("n_subap", C.c_int32), ("fft_n", C.c_int32), ("conv_n", C.c_int32),
+        ("det_n", C.c_int32), ("lgs", C.c_int32), ("flags", C.c_uint32), ("min_illum", C.c_double),
+        ("wavelength_m", C.c_double), ("na_height_m", C.c_double), ("na_fwhm_m", C.c_double),
+        ("elong_max_arcsec", C.c_double), ("spot_fwhm_arcsec", C.c_double),
+        ("photons_per_subap", C.c_double), ("ron_e", C.c_double), ("threshold_e", C.c_double),
+    ]
+
+
+class LgsGeomC(C.Structure):
+    _fields_ = [("launch_x_m", C.c_double), ("launch_y_m", C.c_double)]
+
+
+class WorkC(C.Structure):
+    _fields_ = [("plan", C.c_void_p), ("d_opd_m", C.c_void_p), ("row_pitch", C.c_int64),
+                ("wfs_stride", C.c_int64), ("seed", C.c_uint64), ("frame", C.c_uint64),
+                ("d_slopes", C.c_void_p), ("d_images", C.c_void_p)]
+
+
+_P = C.c_void_p
+_sig = {
+    "shw_last_error": (C.c_char_p, []),
+    "shw_abi_version": (C.c_int32, []),
+    "shw_wfs_config_check": (C.c_int, [C.POINTER(WfsConfigC), C.c_int32, C.POINTER(LgsGeomC)]),
+    "shw_wfs_geometry": (C.c_int, [C.POINTER(WfsConfigC), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_double)]),
+    "shw_wfs_plan_create": (C.c_int, [C.POINTER(WfsConfigC), C.c_int32, C.POINTER(LgsGeomC), C.POINTER(_P)]),
+    "shw_wfs_plan_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_size_t)]),
+    "shw_wfs_plan_kernel_spectra": (C.c_int, [_P, C.c_int32, _P, _P]),
+    "sh_wfs_measure": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_uint64, C.c_uint64,
+                                 _P, _P, _P, _P]),
+    "sh_wfs_measure_batch": (C.c_int, [C.POINTER(WorkC), C.c_int32, _P]),
+    "shw_wfs_plan_destroy": (C.c_int, [_P]),
+    "shw_psf_plan_create": (C.c_int, [C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double,
+                                      C.POINTER(_P)]),
+    "psf_accumulate": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int32, _P, _P, _P]),
+    "shw_psf_plan_destroy": (C.c_int, [_P]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class ShwError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: code {code}: {last_error()}")
+
+
+def last_error() -> str:
+    return _lib.shw_last_error().decode()
+
+
+def _check(code, where):
+    if code != OK:
+        raise ShwError(code, where)
+
+
+def make_config(cfg) -> WfsConfigC:
+    """C struct from any object with the WfsConfig attributes."""
+    c = WfsConfigC()
+    c.abi_version = ABI_VERSION
+    for name, _ in WfsConfigC._fields_:
+        if name == "abi_version":
+            continue
+        setattr(c, name, getattr(cfg, name))
+    return c
+
+
+def _geom_array(launch):
+    if launch is None:
+        return None, None
+    arr = (LgsGeomC * len(launch))(*[LgsGeomC(float(x), float(y)) for x, y in launch])
+    return arr, C.cast(arr, C.POINTER(LgsGeomC))
+
+
+def config_check(cfg, n_wfs=1, launch=None) -> int:
+    arr, ptr = _geom_array(launch)
+    c = make_config(cfg)
+    return _lib.shw_wfs_config_check(C.byref(c), n_wfs, ptr)
+
+
+def geometry(cfg):
+    """(valid_idx list, illum list) from the library's host code."""
+    c = make_config(cfg)
+    n = C.c_int32(0)
+    _check(_lib.shw_wfs_geometry(C.byref(c), C.byref(n), None, None), "shw_wfs_geometry")
+    idx = (C.c_int32 * max(1, n.value))()
+    il = (C.c_double * max(1, n.value))()
+    _check(_lib.shw_wfs_geometry(C.byref(c), C.byref(n), idx, il), "shw_wfs_geometry")
+    return list(idx)[: n.value], list(il)[: n.value]
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class WfsPlan:
+    """n_wfs Shack-Hartmann sensors of one geometry (plan owned by the library)."""
+
+    def __init__(self, cfg, n_wfs=1, launch=None):
+        self.cfg = cfg
+        self.n_wfs = n_wfs
+        self._c = make_config(cfg)
+        arr, ptr = _geom_array(launch)
+        h = C.c_void_p()
+        _check(_lib.shw_wfs_plan_create(C.byref(self._c), n_wfs, ptr, C.byref(h)), "shw_wfs_plan_create")
+        self._h = h
+        nv = C.c_int32(0)
+        nb = C.c_size_t(0)
+        _check(_lib.shw_wfs_plan_info(self._h, C.byref(nv), C.byref(nb)), "shw_wfs_plan_info")
+        self.n_valid = nv.value
+        self.device_bytes = nb.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.shw_wfs_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def kernel_spectra(self, wfs, out, stream=None):
+        _check(_lib.shw_wfs_plan_kernel_spectra(self._h, wfs, _ptr(out), _stream_ptr(stream)),
+               "shw_wfs_plan_kernel_spectra")
+        return out
+
+    def measure(self, opd, slopes, images=None, flags=None, seed=0, frame0=0, stream=None):
+        """opd: float32 device tensor [F][W][N][N] (last dim contiguous); slopes [F][W][2][n_valid]."""
+        if opd.dim() != 4 or opd.stride(3) != 1:
+            raise ValueError("opd must be [frames][wfs][rows][cols] with contiguous rows")
+        nf = opd.shape[0]
+        _check(_lib.sh_wfs_measure(self._h, _ptr(opd), opd.stride(2), opd.stride(1), opd.stride(0), nf,
+                                   seed, frame0, _ptr(slopes), _ptr(images), _ptr(flags),
+                                   _stream_ptr(stream)), "sh_wfs_measure")
+        return slopes
+
+
+def measure_batch(items, stream=None):
+    """items: list of (plan, opd[W][N][N], slopes[W][2][S], images or None, seed, frame)."""
+    arr = (WorkC * max(1, len(items)))()
+    for k, (plan, opd, slopes, images, seed, frame) in enumerate(items):
+        arr[k] = WorkC(plan.handle.value, opd.data_ptr(), opd.stride(1), opd.stride(0), seed, frame,
+                       slopes.data_ptr(), images.data_ptr() if images is not None else None)
+    _check(_lib.sh_wfs_measure_batch(arr, len(items), _stream_ptr(stream)), "sh_wfs_measure_batch")
+
+
+class PsfPlan:
+    """Science PSF accumulation over frames (Strehl per frame)."""
+
+    def __init__(self, pupil_n, pupil_dx_m, obstruction, fft_m, wavelength_m):
+        h = C.c_void_p()
+        _check(_lib.shw_psf_plan_create(ABI_VERSION, pupil_n, pupil_dx_m, obstruction, fft_m, wavelength_m,
+                                        C.byref(h)), "shw_psf_plan_create")
+        self._h = h
+        self.fft_m = fft_m
+        self.pupil_n = pupil_n
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.shw_psf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def accumulate(self, opd, acc, strehl=None, stream=None):
+        """opd: float32 device tensor [F][N][N] (rows contiguous); acc [M][M] (+=); strehl [F] or None."""
+        if opd.dim() != 3 or opd.stride(2) != 1:
+            raise ValueError("opd must be [frames][rows][cols] with contiguous rows")
+        _check(_lib.psf_accumulate(self._h, _ptr(opd), opd.stride(1), opd.stride(0), opd.shape[0], _ptr(acc),
+                                   _ptr(strehl), _stream_ptr(stream)), "psf_accumulate")
+        return acc

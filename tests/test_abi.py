@@ -1,0 +1,100 @@
+"""C-ABI tests that need no GPU: the library loads, exports every declared
+symbol, validates arguments on the host, and its host geometry agrees
+with the oracle's independently computed tables."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from gen import configs as G
+from oracle import geometry as OG
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1408_0698_amd import shwfs
+    return shwfs
+
+
+def _declared_functions():
+    txt = open(os.path.join(ROOT, "include", "shwfs.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s+\*?([a-z_][a-z0-9_]*)\s*\(", txt, re.M)
+    return sorted(set(n for n in names if n not in ("if", "return")))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for must in ("sh_wfs_measure", "psf_accumulate", "shw_wfs_plan_create", "shw_last_error",
+                 "sh_wfs_measure_batch", "shw_psf_plan_create"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(os.path.join(ROOT, "paper_1408_0698_amd", "lib", "libshwfs.so"))
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    s = _lib()
+    assert set(_declared_functions()) == set(s.EXPORTED)
+    assert s._lib.shw_abi_version() == s.ABI_VERSION
+
+
+@pytest.mark.parametrize("cfg,n_wfs", [(G.CFG0, 1), (G.CFG1, 6), (G.CFG1_R2, 6)])
+def test_supported_workloads_pass_validation(cfg, n_wfs):
+    s = _lib()
+    launch = G.launch_positions(cfg, n_wfs) if cfg.lgs else None
+    assert s.config_check(cfg, n_wfs, launch) == s.OK, s.last_error()
+
+
+@pytest.mark.parametrize("change,code", [
+    (dict(pupil_n=81), -1),                 # n_subap does not divide pupil_n
+    (dict(fft_n=12), -1),                   # not a multiple of the sub-aperture size
+    (dict(fft_n=4), -1),                    # smaller than the sub-aperture
+    (dict(conv_n=17), -1),                  # odd padding
+    (dict(det_n=0), -1),
+    (dict(det_n=17), -1),                   # larger than conv_n
+    (dict(obstruction=1.0), -1),
+    (dict(wavelength_m=0.0), -1),
+    (dict(wavelength_m=float("nan")), -1),
+    (dict(min_illum=0.0), -1),
+    (dict(photons_per_subap=-1.0), -1),
+    (dict(flags=1 << 12), -1),              # unknown flag bit
+    (dict(fft_n=24, conv_n=24), -4),        # valid geometry, no kernel compiled
+])
+def test_invalid_configs_are_rejected_on_host(change, code):
+    s = _lib()
+    cfg = G.CFG0.replace(**change)
+    assert s.config_check(cfg, 1, None) == code
+    assert s.last_error() != ""
+
+
+def test_abi_version_and_nulls():
+    s = _lib()
+    c = s.make_config(G.CFG0)
+    c.abi_version = 99
+    assert s._lib.shw_wfs_config_check(C.byref(c), 1, None) == s.E_ABI
+    assert s._lib.shw_wfs_config_check(None, 1, None) == s.E_INVALID
+    assert s.config_check(G.CFG0, 0, None) == s.E_INVALID
+    assert s.config_check(G.CFG1, 6, None) == s.E_INVALID  # LGS needs launch positions
+    out = C.c_void_p()
+    assert s._lib.shw_wfs_plan_create(None, 1, None, C.byref(out)) == s.E_INVALID
+    assert s._lib.sh_wfs_measure(None, None, 0, 0, 0, 1, 0, 0, None, None, None, None) == s.E_INVALID
+    assert s._lib.psf_accumulate(None, None, 0, 0, 1, None, None, None) == s.E_INVALID
+    assert s._lib.sh_wfs_measure_batch(None, 1, None) == s.E_INVALID
+    assert s._lib.sh_wfs_measure_batch(None, 0, None) == s.OK
+    assert s._lib.shw_psf_plan_create(s.ABI_VERSION, 800, 0.05, 0.14, 1000, 1.65e-6, C.byref(out)) == s.E_UNSUPPORTED
+    assert s._lib.shw_psf_plan_create(s.ABI_VERSION, 800, 0.05, 0.14, 400, 1.65e-6, C.byref(out)) == s.E_INVALID
+    assert s._lib.shw_psf_plan_create(2, 800, 0.05, 0.14, 1600, 1.65e-6, C.byref(out)) == s.E_ABI
+    assert s._lib.shw_wfs_plan_destroy(None) == s.OK
+
+
+@pytest.mark.parametrize("cfg", [G.CFG0, G.CFG1, G.CFG4_NGS, G.CFG0.replace(obstruction=0.3, min_illum=0.75)])
+def test_host_geometry_matches_oracle(cfg):
+    s = _lib()
+    idx, il = s.geometry(cfg)
+    vi, oil = OG.subap_table(cfg)
+    assert idx == list(vi)
+    assert np.array_equal(np.array(il), oil)

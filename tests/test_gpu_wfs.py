@@ -1,0 +1,313 @@
+"""GPU parity of sh_wfs_measure against the FP64 oracle (called through the C ABI).
+
+Bars: detector images within 1e-4 of the sub-aperture's maximum, slopes
+within 1e-3 detector pixel; with noise, Poisson counts identical except at
+ties (a count the oracle's own sampler also gives for an expected value
+within 1e-5 relative of its own), read noise within 1e-4 electron.
+"""
+import numpy as np
+import pytest
+
+from gen import configs as G
+from gen import screens as S
+from oracle import philox as OP
+from oracle import wfs as OW
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-4
+SLOPE_TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _lib():
+    from paper_1408_0698_amd import shwfs
+    return shwfs
+
+
+def small_lgs(ns=17, **kw):
+    """The 39 m LGS sensor shape (10x10 px sub-apertures, FFT 40, 16x16 detector) on a smaller pupil."""
+    return G.CFG1.replace(pupil_n=10 * ns, n_subap=ns, **kw)
+
+
+def run_gpu(torch, cfg, n_wfs, launch, opd, seed=0, frame0=0, images=True):
+    s = _lib()
+    plan = s.WfsPlan(cfg, n_wfs, launch)
+    d_opd = torch.from_numpy(np.ascontiguousarray(opd, dtype=np.float32)).cuda()
+    nf = opd.shape[0]
+    slopes = torch.full((nf, n_wfs, 2, plan.n_valid), float("nan"), device="cuda")
+    imgs = torch.full((nf, n_wfs, plan.n_valid, cfg.det_n, cfg.det_n), float("nan"), device="cuda") if images else None
+    flags = torch.full((nf, n_wfs, plan.n_valid), 7, dtype=torch.uint8, device="cuda")
+    plan.measure(d_opd, slopes, imgs, flags, seed=seed, frame0=frame0)
+    torch.cuda.synchronize()
+    out = dict(slopes=slopes.cpu().numpy().astype(np.float64), flags=flags.cpu().numpy(), plan=plan)
+    if images:
+        out["images"] = imgs.cpu().numpy().astype(np.float64)
+    return out
+
+
+def assert_images_close(got, want, tol=IMG_TOL):
+    scale = np.abs(want).max(axis=(-1, -2), keepdims=True)
+    scale = np.where(scale > 0, scale, 1.0)
+    err = np.abs(got - want) / scale
+    assert np.isfinite(got).all()
+    assert err.max() <= tol, f"max relative image error {err.max():.3e}"
+    return err.max()
+
+
+def assert_slopes_close(got, want, tol=SLOPE_TOL):
+    err = np.abs(got - want)
+    assert np.isfinite(got).all()
+    assert err.max() <= tol, f"max slope error {err.max():.3e} px"
+    return err.max()
+
+
+def screen_opd(cfg, n_frames, n_wfs, seed=S.C.SCREEN_SEED, frame0=0):
+    if cfg.pupil_n == 80 and cfg.pupil_dx_m == 0.1:
+        o = S.ngs8m_opd(n_frames, frame0, seed)[:, None]
+        return np.repeat(o, n_wfs, axis=1)
+    return S.lgs39m_opd(n_frames, n_wfs, frame0, seed, pupil_n=cfg.pupil_n)
+
+
+# ---------------------------------------------------------------- noise-free parity
+
+@pytest.mark.parametrize("cfg,n_wfs,nf", [
+    (G.CFG0, 1, 3),                                   # 8 m NGS, FFT 16, detector 8
+    (G.CFG0.replace(det_n=16), 1, 2),                 # one FFT pixel per detector pixel
+    (small_lgs(17, flags=0, photons_per_subap=0.0), 1, 2),     # LGS, 220 items: ragged last block
+    (small_lgs(13, flags=0), 6, 1),                   # 6 LGS, photometry without noise
+    (small_lgs(12, flags=0, lgs=0, photons_per_subap=0.0), 2, 1),   # FFT 40 NGS
+    (G.CFG1_R2.replace(pupil_n=130, n_subap=13, flags=0), 6, 1),     # reading R2: FFT 20 in a 40 grid
+])
+def test_noise_free_parity(torch_dev, cfg, n_wfs, nf):
+    launch = G.launch_positions(cfg, n_wfs) if cfg.lgs else None
+    opd = screen_opd(cfg, nf, n_wfs)
+    got = run_gpu(torch_dev, cfg, n_wfs, launch, opd)
+    want = OW.Sensor(cfg, n_wfs, launch).measure(opd)
+    assert_images_close(got["images"], want["images"])
+    assert_slopes_close(got["slopes"], want["slopes"])
+    assert np.array_equal(got["flags"].astype(bool), want["empty"])
+
+
+def test_flat_wavefront_gives_zero_slopes(torch_dev):
+    cfg = small_lgs(13, flags=0)
+    launch = G.launch_positions(cfg, 6)
+    opd = np.zeros((1, 6, cfg.pupil_n, cfg.pupil_n), np.float32)
+    got = run_gpu(torch_dev, cfg, 6, launch, opd)
+    assert np.abs(got["slopes"]).max() < 1e-4
+
+
+def test_tilt_closed_form(torch_dev):
+    """Square fully lit sub-apertures, tilt s FFT pixels: centroid = windowed Dirichlet^2 sum."""
+    cfg = G.CFG0.replace(obstruction=0.0, det_n=16)
+    s_fft = 0.37
+    lam = cfg.wavelength_m
+    x = np.arange(80)
+    opd = np.broadcast_to((s_fft * (x % 8) / 16.0 * lam)[None, :], (80, 80)).astype(np.float32)
+    got = run_gpu(torch_dev, cfg, 1, None, opd[None, None].copy())
+    n, N = 8, 16
+    c = (N - 1) / 2
+    t = np.arange(N) - c - s_fft
+    D = np.sin(np.pi * n * t / N) ** 2 / np.sin(np.pi * t / N) ** 2
+    want = ((np.arange(N) - c) * D).sum() / D.sum()
+    vi = got["plan"].n_valid
+    from oracle import geometry as OG
+    _, illum = OG.subap_table(cfg)
+    full = illum == 1.0
+    assert full.sum() > 10
+    assert np.abs(got["slopes"][0, 0, 0, full] - want).max() < SLOPE_TOL
+    assert np.abs(got["slopes"][0, 0, 1, full]).max() < SLOPE_TOL
+    assert vi == len(illum)
+
+
+def test_kernel_spectra_match_oracle(torch_dev):
+    cfg = small_lgs(13)
+    launch = G.launch_positions(cfg, 6)
+    s = _lib()
+    plan = s.WfsPlan(cfg, 6, launch)
+    H = cfg.conv_n // 2 + 1
+    out = torch_dev.empty((plan.n_valid, H, cfg.conv_n), device="cuda")
+    sens = OW.Sensor(cfg, 6, launch)
+    for w in (0, 3, 5):
+        plan.kernel_spectra(w, out)
+        torch_dev.cuda.synchronize()
+        got = out.cpu().numpy().astype(np.float64) * cfg.conv_n ** 2
+        sel = np.arange(0, plan.n_valid, 7)
+        want = sens.khat(w, sel)[:, :H, :]
+        assert np.abs(got[sel] - want).max() < 1e-6
+
+
+# ---------------------------------------------------------------- noise parity
+
+def _explained(lam_oracle, count_gpu, seed, pix, gsub, frame):
+    """True if the oracle sampler gives count_gpu for an expected value within 1e-5 relative."""
+    for d in (-1e-5, -3e-6, -1e-6, -3e-7, 3e-7, 1e-6, 3e-6, 1e-5):
+        k = OP.poisson_counts(np.array([lam_oracle * (1 + d)], np.float32), seed, np.array([pix], np.uint64),
+                              np.array([gsub], np.uint64), np.uint64(frame))[0]
+        if k == count_gpu:
+            return True
+    return False
+
+
+def check_noisy(cfg, n_wfs, launch, got, want, seed, frame0, gsub_of):
+    """Compare noisy frames: counts equal except explained ties; read noise; slopes of tie-free sub-apertures."""
+    d = cfg.det_n
+    nf = got["images"].shape[0]
+    ron = cfg.ron_e
+    # split electrons into counts + read noise using the oracle's own read-noise draws
+    mism = 0
+    total = 0
+    bad_subaps = np.zeros(got["slopes"].shape[:2] + (got["slopes"].shape[-1],), bool)
+    for f in range(nf):
+        for w in range(n_wfs):
+            gi = gsub_of(w)
+            pix = np.arange(d * d, dtype=np.uint64).reshape(1, d, d)
+            z = OP.read_noise(seed, pix, gi.astype(np.uint64).reshape(-1, 1, 1), np.uint64(frame0 + f))
+            cg = got["images"][f, w] - ron * z
+            co = want["images"][f, w] - ron * z
+            kg = np.rint(cg)
+            ko = np.rint(co)
+            assert np.abs(cg - kg).max() < 1e-3, "GPU read noise differs from the oracle draw"
+            assert np.abs(co - ko).max() < 1e-9
+            diff = np.nonzero(kg != ko)
+            total += kg.size
+            for s_, p_, q_ in zip(*diff):
+                mism += 1
+                lam = want["lam"][f, w, s_, p_, q_]
+                assert _explained(lam, int(kg[s_, p_, q_]), seed, p_ * d + q_, gi[s_], frame0 + f), \
+                    f"unexplained count mismatch at frame {f} wfs {w} subap {s_} pixel ({p_},{q_}) lam {lam}"
+                bad_subaps[f, w, s_] = True
+    assert mism <= max(2, 1e-5 * total), f"{mism} tie mismatches in {total} pixels"
+    ok = ~bad_subaps
+    err = np.abs(got["slopes"] - want["slopes"]).transpose(0, 1, 3, 2)[ok]
+    assert err.max() <= SLOPE_TOL, f"slope error {err.max():.3e} on tie-free sub-apertures"
+    return mism
+
+
+@pytest.mark.parametrize("ns,n_wfs,nf,frame0", [(13, 6, 1, 0), (17, 1, 2, 12345), (12, 3, 1, 2 ** 32 - 1)])
+def test_noisy_parity(torch_dev, ns, n_wfs, nf, frame0):
+    cfg = small_lgs(ns)
+    launch = G.launch_positions(cfg, n_wfs)
+    opd = screen_opd(cfg, nf, n_wfs)
+    seed = G.NOISE_SEED + (1 << 40)
+    got = run_gpu(torch_dev, cfg, n_wfs, launch, opd, seed=seed, frame0=frame0)
+    sens = OW.Sensor(cfg, n_wfs, launch)
+    want = sens.measure(opd, seed=seed, frame0=frame0)
+    check_noisy(cfg, n_wfs, launch, got, want, seed, frame0, lambda w: w * sens.n_valid + np.arange(sens.n_valid))
+
+
+def test_noise_is_independent_of_batching(torch_dev):
+    cfg = small_lgs(13)
+    launch = G.launch_positions(cfg, 6)
+    opd = screen_opd(cfg, 3, 6)
+    a = run_gpu(torch_dev, cfg, 6, launch, opd, seed=5, frame0=10)
+    b = run_gpu(torch_dev, cfg, 6, launch, opd[1:2], seed=5, frame0=11)
+    assert np.array_equal(a["images"][1], b["images"][0])
+    assert np.array_equal(a["slopes"][1], b["slopes"][0])
+    c = run_gpu(torch_dev, cfg, 6, launch, opd, seed=5, frame0=10)
+    assert np.array_equal(a["images"], c["images"]) and np.array_equal(a["slopes"], c["slopes"])
+
+
+# ---------------------------------------------------------------- full 39 m frame, sampled
+
+def test_full_lgs_frame_sampled(torch_dev):
+    """The 6-LGS 80x80 frame in the launch shape the benchmark times; the oracle
+    recomputes a sample of sub-apertures of every sensor one by one."""
+    cfg = G.CFG1
+    launch = G.launch_positions(cfg, 6)
+    opd = screen_opd(cfg, 1, 6)
+    seed = G.NOISE_SEED
+    got = run_gpu(torch_dev, cfg, 6, launch, opd, seed=seed, frame0=7)
+    quiet = run_gpu(torch_dev, cfg.replace(flags=0), 6, launch, opd, frame0=7)
+    sens = OW.Sensor(cfg, 6, launch)
+    rng = np.random.default_rng(1)
+    sub = np.sort(rng.choice(sens.n_valid, 120, replace=False))
+    sub = np.unique(np.concatenate([sub, [0, sens.n_valid - 1]]))
+    want = sens.measure(opd, seed=seed, frame0=7, subset=sub)
+    qw = OW.Sensor(cfg.replace(flags=0), 6, launch)
+    qw._khat = sens._khat
+    want_q = qw.measure(opd, subset=sub)
+    assert_images_close(quiet["images"][:, :, sub], want_q["images"])
+    assert_slopes_close(quiet["slopes"][..., sub], want_q["slopes"])
+    g = dict(images=got["images"][:, :, sub], slopes=got["slopes"][..., sub])
+    check_noisy(cfg, 6, launch, g, want, seed, 7, lambda w: w * sens.n_valid + sub)
+    # every sub-aperture: the noise-free flux is the photon budget times the lit fraction
+    from oracle import geometry as OG
+    _, illum = OG.subap_table(cfg)
+    flux = quiet["images"].sum(axis=(-1, -2))
+    assert np.abs(flux - cfg.photons_per_subap * illum[None, None, :]).max() < 1e-3 * cfg.photons_per_subap
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_zero_frames_is_a_noop(torch_dev):
+    s = _lib()
+    plan = s.WfsPlan(G.CFG0)
+    opd = torch_dev.zeros((0, 1, 80, 80), device="cuda")
+    slopes = torch_dev.zeros((0, 1, 2, plan.n_valid), device="cuda")
+    plan.measure(opd, slopes)
+
+
+def test_strided_opd_and_slope_layout(torch_dev):
+    """Row pitch larger than the pupil and a frame stride with gaps; X block then Y block."""
+    cfg = G.CFG0
+    opd = screen_opd(cfg, 2, 1)
+    big = np.zeros((2, 1, 80, 96), np.float32)
+    big[..., :80] = opd
+    s = _lib()
+    plan = s.WfsPlan(cfg)
+    d = torch_dev.from_numpy(big).cuda()[..., :80]
+    slopes = torch_dev.zeros((2, 1, 2, plan.n_valid), device="cuda")
+    plan.measure(d, slopes)
+    torch_dev.cuda.synchronize()
+    want = OW.Sensor(cfg).measure(opd)
+    assert_slopes_close(slopes.cpu().numpy(), want["slopes"])
+
+
+def test_threshold_above_everything_flags_every_subaperture(torch_dev):
+    cfg = small_lgs(12, flags=0, threshold_e=1e6)
+    launch = G.launch_positions(cfg, 1)
+    got = run_gpu(torch_dev, cfg, 1, launch, screen_opd(cfg, 1, 1))
+    assert (got["flags"] == 1).all() and (got["slopes"] == 0).all()
+
+
+def test_invalid_measure_arguments(torch_dev):
+    s = _lib()
+    plan = s.WfsPlan(G.CFG0)
+    import ctypes as C
+    assert s._lib.sh_wfs_measure(plan.handle, None, 80, 0, 0, 1, 0, 0, None, None, None, None) == s.E_INVALID
+    d = torch_dev.zeros((1, 1, 80, 80), device="cuda")
+    sl = torch_dev.zeros((1, 1, 2, plan.n_valid), device="cuda")
+    assert s._lib.sh_wfs_measure(plan.handle, C.c_void_p(d.data_ptr()), 79, 0, 0, 1, 0, 0,
+                                 C.c_void_p(sl.data_ptr()), None, None, None) == s.E_INVALID
+    assert s._lib.sh_wfs_measure(plan.handle, C.c_void_p(d.data_ptr()), 80, 0, 0, 2, 0, 2 ** 32 - 1,
+                                 C.c_void_p(sl.data_ptr()), None, None, None) == s.E_INVALID
+    assert s._lib.sh_wfs_measure(plan.handle, C.c_void_p(d.data_ptr()), 80, -1, 0, 1, 0, 0,
+                                 C.c_void_p(sl.data_ptr()), None, None, None) == s.E_INVALID
+
+
+def test_mixed_batch_equals_single_calls(torch_dev):
+    s = _lib()
+    c0 = G.CFG0
+    c1 = small_lgs(13)
+    l1 = G.launch_positions(c1, 6)
+    p0 = s.WfsPlan(c0)
+    p1 = s.WfsPlan(c1, 6, l1)
+    o0 = torch_dev.from_numpy(screen_opd(c0, 1, 1)[0]).cuda()
+    o1 = torch_dev.from_numpy(screen_opd(c1, 1, 6)[0]).cuda()
+    s0 = torch_dev.zeros((1, 2, p0.n_valid), device="cuda")
+    s1 = torch_dev.zeros((6, 2, p1.n_valid), device="cuda")
+    s.measure_batch([(p0, o0, s0, None, 3, 4), (p1, o1, s1, None, 9, 2)])
+    r0 = torch_dev.zeros((1, 1, 2, p0.n_valid), device="cuda")
+    r1 = torch_dev.zeros((1, 6, 2, p1.n_valid), device="cuda")
+    p0.measure(o0[None], r0, seed=3, frame0=4)
+    p1.measure(o1[None], r1, seed=9, frame0=2)
+    torch_dev.cuda.synchronize()
+    assert torch_dev.equal(s0, r0[0]) and torch_dev.equal(s1, r1[0])
