@@ -23,6 +23,31 @@ if ROOT not in sys.path:
 # nominal FFT flops of one 40x40 complex 2-D transform: 5 N^2 log2(N^2); three per sub-aperture
 FLOP_PER_SUBAP = 3 * 5 * 40 * 40 * math.log2(40 * 40)
 PEAK_FP32_TFLOPS = 157.3
+CSRC = os.path.join(ROOT, "paper_1408_0698_amd", "csrc")
+TRAFFIC = os.path.join(ROOT, "profiles", "wfs_fused_lgs39m_traffic.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("wfs_kernels.hip", "regfft.h", "noise.h", "internal.h"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(frames_per_launch):
+    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary, or None if the
+    kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC) as fh:
+            t = json.load(fh)
+    except OSError:
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    per_frame = (t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]) / t["frames_per_launch"]
+    return per_frame * frames_per_launch
 
 
 def cpu_baseline(cfg, launch, opd, min_seconds=10.0):
@@ -61,6 +86,8 @@ def main():
     ap.add_argument("--frames-per-step", type=int, default=1)
     ap.add_argument("--resident-frames", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="before timing, run 5 plain device copies of this many MB (profiler counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note",
@@ -84,6 +111,15 @@ def main():
     opd = torch.from_numpy(opd_host).cuda()
     slopes = torch.zeros((B, 6, 2, plan.n_valid), device="cuda")
     stream = torch.cuda.current_stream()
+
+    if args.calibrate_copy_mb > 0:
+        n = args.calibrate_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(k):
         f0 = (k * B) % (nres - B + 1)
@@ -126,7 +162,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "per": f"launch of {B} frame(s), HIP events on the launch stream"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(B),
                      "kernel": "wfs_fused_kernel<10,40,40,16,lgs>",
                      "avg_launch_ms": avg_launch_ms},
     }
