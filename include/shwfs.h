@@ -225,6 +225,61 @@ int psf_accumulate(shw_psf_plan* plan, const float* d_opd_m, int64_t row_pitch, 
 
 int shw_psf_plan_destroy(shw_psf_plan* plan);
 
+
+/*
+ * Deformable mirrors and residual OPD (Sec. 3 closed-loop block: the residual
+ * phase is the open-loop wavefront minus the DM; Sec. 2: ~5000 / ~1400 /
+ * ~1800 modes on the ground and two post-focal DMs with 1 m pitch; Sec. 3
+ * influence-function block: analytic influence functions when none are
+ * supplied).
+ *
+ * A DM conjugated at altitude alt_m has actuators on a square grid of pitch
+ * pitch_px pupil pixels, centred on the axis, kept where the actuator lies
+ * within the metapupil radius pupil_n/2 + alt_m * field_radius / dx (pixels).
+ * Its surface is a size x size grid, size = 2 * ceil(metapupil radius), with
+ * pixel centres at (j + 1/2 - size/2) pixels from the axis.  Influence
+ * function: exp(-r^2 / (2 sigma^2)) with exp(-pitch^2 / (2 sigma^2)) =
+ * coupling, on the patch x patch pixels nearest to the actuator.
+ * Actuators are numbered row-major (y, then x).
+ */
+typedef struct shw_dm_plan shw_dm_plan;
+
+int shw_dm_plan_create(int32_t abi_version, int32_t pupil_n, double pupil_dx_m, double alt_m, int32_t pitch_px,
+                       double field_radius_arcsec, double coupling, int32_t patch, shw_dm_plan** out);
+
+/* Actuator count, surface side, and (nullable) host copy of the actuator
+ * positions [n_act][2] = (x, y) in pixels from the DM centre. */
+int shw_dm_plan_info(const shw_dm_plan* plan, int32_t* n_act, int32_t* size, double* act_xy);
+
+/* Host-only: the same facts without creating a plan (no HIP call).  act_xy
+ * (nullable) needs room for the count returned by a first call with NULL. */
+int shw_dm_geometry(int32_t pupil_n, double pupil_dx_m, double alt_m, int32_t pitch_px, double field_radius_arcsec,
+                    int32_t* n_act, int32_t* size, double* act_xy);
+
+/*
+ * d_surface[size][size] (FP32, device, row pitch = size) = sum_k
+ * d_coefs[k] * IF_k.  d_coefs: [n_act] FP32 OPD metres, device.  Asynchronous.
+ */
+int shw_dm_surface(shw_dm_plan* plan, const float* d_coefs, float* d_surface, void* hip_stream);
+
+int shw_dm_plan_destroy(shw_dm_plan* plan);
+
+/*
+ * Residual OPD of n_out pupils: out_k[y][x] = screen[sr_k + y][sc_k + x]
+ * - sum_d surf_d[r_kd + y][c_kd + x] for y, x < pupil_n, where (sr_k, sc_k)
+ * and (r_kd, c_kd) are window origins (rows, columns) given per output k
+ * in the host arrays scr_origin[n_out][2] and dm_origin[n_out][n_dm][2].
+ * The screen is screen_rows x screen_cols with row pitch screen_pitch;
+ * surface d is surf_size[d] square with row pitch surf_size[d]; d_surf is a
+ * host array of n_dm (<= 4) device pointers.  Output k starts at d_out +
+ * k * out_stride with rows out_pitch apart.  Every window must lie inside
+ * its array (checked on the host).  Asynchronous.
+ */
+int shw_residual_opd(const float* d_screen, int32_t screen_rows, int32_t screen_cols, int64_t screen_pitch,
+                     int32_t n_dm, const float* const* d_surf, const int32_t* surf_size, int32_t pupil_n,
+                     int32_t n_out, const int32_t* scr_origin, const int32_t* dm_origin, float* d_out,
+                     int64_t out_pitch, int64_t out_stride, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

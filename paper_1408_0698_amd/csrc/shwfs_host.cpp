@@ -15,6 +15,7 @@
 
 #include "internal.h"
 #include "psf_internal.h"
+#include "dm_internal.h"
 
 using namespace shw;
 
@@ -434,6 +435,177 @@ extern "C" int psf_accumulate(shw_psf_plan* p, const float* d_opd_m, int64_t row
     const int nf = n_frames - f0 < p->chunk ? n_frames - f0 : p->chunk;
     hipError_t e = launch_psf_chunk(a, f0, nf, p->d_work, d_psf_acc, d_strehl, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "psf_accumulate launch");
+  }
+  return ok();
+}
+
+// ---------------------------------------------------------------- deformable mirrors, residual OPD
+
+struct shw_dm_plan {
+  int32_t size = 0, pitch = 0, m = 0, patch = 0, n_act = 0;
+  double sigma = 0;
+  int device = 0;
+  std::vector<double> act;   // [n_act][2] (x, y)
+  int* d_grid = nullptr;
+};
+
+// Metapupil radius, surface side and actuator grid (host, FP64).
+static int dm_geometry(int32_t pupil_n, double dx, double alt_m, int32_t pitch_px, double field_arcsec, double* R,
+                       int* size, int* m, std::vector<int>* grid, std::vector<double>* act) {
+  if (pupil_n < 2 || pupil_n > 16384 || pupil_n % 2) return fail(SHW_E_INVALID, "pupil_n %d must be even in [2, 16384]", pupil_n);
+  if (!(is_fin(dx) && dx > 0)) return fail(SHW_E_INVALID, "pupil_dx_m must be > 0");
+  if (!(is_fin(alt_m) && alt_m >= 0)) return fail(SHW_E_INVALID, "alt_m must be >= 0");
+  if (pitch_px < 1 || pitch_px > 4096) return fail(SHW_E_INVALID, "pitch_px %d outside [1, 4096]", pitch_px);
+  if (!(is_fin(field_arcsec) && field_arcsec >= 0)) return fail(SHW_E_INVALID, "field radius must be >= 0");
+  *R = pupil_n / 2.0 + alt_m * field_arcsec * kArcsec / dx;
+  *size = 2 * (int)std::ceil(*R - 1e-9);
+  if (*size > 65536) return fail(SHW_E_INVALID, "surface too large (%d)", *size);
+  *m = (int)std::floor(*R / pitch_px);
+  const int G = 2 * *m + 1;
+  grid->assign((size_t)G * G, -1);
+  act->clear();
+  int n = 0;
+  for (int gy = -*m; gy <= *m; ++gy)
+    for (int gx = -*m; gx <= *m; ++gx) {
+      const double x = (double)gx * pitch_px, y = (double)gy * pitch_px;
+      if (x * x + y * y <= *R * *R) {
+        (*grid)[(size_t)(gy + *m) * G + (gx + *m)] = n++;
+        act->push_back(x);
+        act->push_back(y);
+      }
+    }
+  return SHW_OK;
+}
+
+extern "C" int shw_dm_geometry(int32_t pupil_n, double pupil_dx_m, double alt_m, int32_t pitch_px,
+                               double field_radius_arcsec, int32_t* n_act, int32_t* size, double* act_xy) {
+  double R;
+  int sz, m;
+  std::vector<int> grid;
+  std::vector<double> act;
+  const int r = dm_geometry(pupil_n, pupil_dx_m, alt_m, pitch_px, field_radius_arcsec, &R, &sz, &m, &grid, &act);
+  if (r != SHW_OK) return r;
+  if (n_act) *n_act = (int32_t)(act.size() / 2);
+  if (size) *size = sz;
+  if (act_xy)
+    for (size_t k = 0; k < act.size(); ++k) act_xy[k] = act[k];
+  return ok();
+}
+
+extern "C" int shw_dm_plan_destroy(shw_dm_plan* p) {
+  if (!p) return ok();
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != p->device) (void)hipSetDevice(p->device);
+  if (p->d_grid) (void)hipFree(p->d_grid);
+  if (cur != p->device) (void)hipSetDevice(cur);
+  delete p;
+  return ok();
+}
+
+extern "C" int shw_dm_plan_create(int32_t abi_version, int32_t pupil_n, double pupil_dx_m, double alt_m,
+                                  int32_t pitch_px, double field_radius_arcsec, double coupling, int32_t patch,
+                                  shw_dm_plan** out) {
+  if (!out) return fail(SHW_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (abi_version != SHW_ABI_VERSION) return fail(SHW_E_ABI, "abi_version %d, library %d", abi_version, SHW_ABI_VERSION);
+  if (!(is_fin(coupling) && coupling > 0 && coupling < 1)) return fail(SHW_E_INVALID, "coupling must be in (0, 1)");
+  if (patch < 2 || patch > 1024 || patch % 2) return fail(SHW_E_INVALID, "patch %d must be even in [2, 1024]", patch);
+  double R;
+  int size, m;
+  std::vector<int> grid;
+  std::vector<double> act;
+  const int r = dm_geometry(pupil_n, pupil_dx_m, alt_m, pitch_px, field_radius_arcsec, &R, &size, &m, &grid, &act);
+  if (r != SHW_OK) return r;
+  auto* p = new shw_dm_plan();
+  p->size = size;
+  p->pitch = pitch_px;
+  p->patch = patch;
+  p->m = m;
+  p->sigma = pitch_px / std::sqrt(2.0 * std::log(1.0 / coupling));
+  p->act = act;
+  p->n_act = (int32_t)(act.size() / 2);
+  hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = hipMalloc(&p->d_grid, sizeof(int) * grid.size());
+  if (e == hipSuccess) e = hipMemcpy(p->d_grid, grid.data(), sizeof(int) * grid.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    shw_dm_plan_destroy(p);
+    return hip_fail(e, "DM plan tables");
+  }
+  *out = p;
+  return ok();
+}
+
+extern "C" int shw_dm_plan_info(const shw_dm_plan* p, int32_t* n_act, int32_t* size, double* act_xy) {
+  if (!p) return fail(SHW_E_INVALID, "plan is NULL");
+  if (n_act) *n_act = p->n_act;
+  if (size) *size = p->size;
+  if (act_xy)
+    for (size_t k = 0; k < p->act.size(); ++k) act_xy[k] = p->act[k];
+  return ok();
+}
+
+extern "C" int shw_dm_surface(shw_dm_plan* p, const float* d_coefs, float* d_surface, void* stream) {
+  if (!p || !d_coefs || !d_surface) return fail(SHW_E_INVALID, "NULL argument");
+  DmLaunch a{};
+  a.grid = p->d_grid;
+  a.m = p->m;
+  a.pitch = p->pitch;
+  a.size = p->size;
+  a.half_patch = p->patch / 2;
+  a.inv_2s2 = (float)(1.0 / (2.0 * p->sigma * p->sigma));
+  hipError_t e = launch_dm_surface(a, d_coefs, d_surface, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "shw_dm_surface launch");
+  return ok();
+}
+
+extern "C" int shw_residual_opd(const float* d_screen, int32_t screen_rows, int32_t screen_cols, int64_t screen_pitch,
+                                int32_t n_dm, const float* const* d_surf, const int32_t* surf_size, int32_t pupil_n,
+                                int32_t n_out, const int32_t* scr_origin, const int32_t* dm_origin, float* d_out,
+                                int64_t out_pitch, int64_t out_stride, void* stream) {
+  if (n_out < 0) return fail(SHW_E_INVALID, "n_out < 0");
+  if (n_out == 0) return ok();
+  if (!d_screen || !d_out || !scr_origin) return fail(SHW_E_INVALID, "NULL argument");
+  if (n_dm < 0 || n_dm > kMaxDm) return fail(SHW_E_INVALID, "n_dm %d outside [0, %d]", n_dm, kMaxDm);
+  if (n_dm > 0 && (!d_surf || !surf_size || !dm_origin)) return fail(SHW_E_INVALID, "NULL DM argument");
+  if (pupil_n < 1 || screen_rows < 1 || screen_cols < 1 || screen_pitch < screen_cols)
+    return fail(SHW_E_INVALID, "bad screen or pupil size");
+  if (out_pitch < pupil_n || out_stride < 0) return fail(SHW_E_INVALID, "bad output layout");
+  for (int d = 0; d < n_dm; ++d)
+    if (!d_surf[d] || surf_size[d] < pupil_n) return fail(SHW_E_INVALID, "surface %d missing or smaller than the pupil", d);
+  for (int k = 0; k < n_out; ++k) {
+    const int r = scr_origin[2 * k], c = scr_origin[2 * k + 1];
+    if (r < 0 || c < 0 || r + pupil_n > screen_rows || c + pupil_n > screen_cols)
+      return fail(SHW_E_INVALID, "screen window %d at (%d, %d) leaves the screen", k, r, c);
+    for (int d = 0; d < n_dm; ++d) {
+      const int rr = dm_origin[(k * n_dm + d) * 2], cc = dm_origin[(k * n_dm + d) * 2 + 1];
+      if (rr < 0 || cc < 0 || rr + pupil_n > surf_size[d] || cc + pupil_n > surf_size[d])
+        return fail(SHW_E_INVALID, "DM %d window %d at (%d, %d) leaves the surface", d, k, rr, cc);
+    }
+  }
+  ResidualLaunch a{};
+  a.screen = d_screen;
+  a.screen_pitch = screen_pitch;
+  a.n_dm = n_dm;
+  a.pupil_n = pupil_n;
+  a.out_pitch = out_pitch;
+  a.out_stride = out_stride;
+  for (int d = 0; d < n_dm; ++d) {
+    a.surf[d] = d_surf[d];
+    a.surf_size[d] = surf_size[d];
+  }
+  for (int k0 = 0; k0 < n_out; k0 += kResidualChunk) {
+    const int nk = n_out - k0 < kResidualChunk ? n_out - k0 : kResidualChunk;
+    for (int k = 0; k < nk; ++k) {
+      a.scr_origin[k][0] = scr_origin[2 * (k0 + k)];
+      a.scr_origin[k][1] = scr_origin[2 * (k0 + k) + 1];
+      for (int d = 0; d < n_dm; ++d) {
+        a.dm_origin[k][d][0] = dm_origin[((k0 + k) * n_dm + d) * 2];
+        a.dm_origin[k][d][1] = dm_origin[((k0 + k) * n_dm + d) * 2 + 1];
+      }
+    }
+    hipError_t e = launch_residual(a, nk, d_out + (int64_t)k0 * out_stride, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "shw_residual_opd launch");
   }
   return ok();
 }

@@ -63,6 +63,16 @@ _sig = {
                                       C.POINTER(_P)]),
     "psf_accumulate": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int32, _P, _P, _P]),
     "shw_psf_plan_destroy": (C.c_int, [_P]),
+    "shw_dm_plan_create": (C.c_int, [C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double,
+                                     C.c_double, C.c_int32, C.POINTER(_P)]),
+    "shw_dm_plan_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "shw_dm_geometry": (C.c_int, [C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double, C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "shw_dm_surface": (C.c_int, [_P, _P, _P, _P]),
+    "shw_dm_plan_destroy": (C.c_int, [_P]),
+    "shw_residual_opd": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.POINTER(C.c_void_p),
+                                   C.POINTER(C.c_int32), C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int32), _P, C.c_int64, C.c_int64, _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -213,3 +223,62 @@ class PsfPlan:
         _check(_lib.psf_accumulate(self._h, _ptr(opd), opd.stride(1), opd.stride(0), opd.shape[0], _ptr(acc),
                                    _ptr(strehl), _stream_ptr(stream)), "psf_accumulate")
         return acc
+
+
+def dm_geometry(pupil_n, pupil_dx_m, alt_m, pitch_px, field_radius_arcsec):
+    """(actuator positions [n][2] as a list of (x, y) px, surface side) from the library's host code."""
+    n = C.c_int32(0)
+    size = C.c_int32(0)
+    _check(_lib.shw_dm_geometry(pupil_n, pupil_dx_m, alt_m, pitch_px, field_radius_arcsec, C.byref(n),
+                                C.byref(size), None), "shw_dm_geometry")
+    xy = (C.c_double * (2 * max(1, n.value)))()
+    _check(_lib.shw_dm_geometry(pupil_n, pupil_dx_m, alt_m, pitch_px, field_radius_arcsec, C.byref(n),
+                                C.byref(size), xy), "shw_dm_geometry")
+    v = list(xy)[: 2 * n.value]
+    return [(v[2 * k], v[2 * k + 1]) for k in range(n.value)], size.value
+
+
+class DmPlan:
+    """One deformable mirror: actuator grid and influence functions (plan owned by the library)."""
+
+    def __init__(self, pupil_n, pupil_dx_m, alt_m, pitch_px, field_radius_arcsec, coupling=0.3, patch=64):
+        h = C.c_void_p()
+        _check(_lib.shw_dm_plan_create(ABI_VERSION, pupil_n, pupil_dx_m, alt_m, pitch_px, field_radius_arcsec,
+                                       coupling, patch, C.byref(h)), "shw_dm_plan_create")
+        self._h = h
+        n = C.c_int32(0)
+        size = C.c_int32(0)
+        _check(_lib.shw_dm_plan_info(self._h, C.byref(n), C.byref(size), None), "shw_dm_plan_info")
+        self.n_act = n.value
+        self.size = size.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.shw_dm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def surface(self, coefs, out, stream=None):
+        """coefs: float32 device [n_act]; out: float32 device [size][size] (contiguous)."""
+        _check(_lib.shw_dm_surface(self._h, _ptr(coefs), _ptr(out), _stream_ptr(stream)), "shw_dm_surface")
+        return out
+
+
+def residual_opd(screen, surfaces, pupil_n, scr_origin, dm_origin, out, stream=None):
+    """out[k] = screen window k - sum_d surface_d window (k, d).
+
+    screen: float32 device [R][Cols] (rows contiguous); surfaces: list of square contiguous float32 device
+    arrays; scr_origin: [n_out][2] ints; dm_origin: [n_out][n_dm][2] ints; out: float32 device [n_out][N][N].
+    """
+    n_out = len(scr_origin)
+    n_dm = len(surfaces)
+    ptrs = (C.c_void_p * max(1, n_dm))(*[s.data_ptr() for s in surfaces])
+    sizes = (C.c_int32 * max(1, n_dm))(*[s.shape[0] for s in surfaces])
+    so = (C.c_int32 * (2 * max(1, n_out)))(*[int(v) for o in scr_origin for v in o])
+    do = (C.c_int32 * (2 * max(1, n_out * n_dm)))(*[int(v) for o in dm_origin for dd in o for v in dd])
+    _check(_lib.shw_residual_opd(_ptr(screen), screen.shape[0], screen.shape[1], screen.stride(0), n_dm, ptrs, sizes,
+                                 pupil_n, n_out, so, do, _ptr(out), out.stride(1), out.stride(0),
+                                 _stream_ptr(stream)), "shw_residual_opd")
+    return out

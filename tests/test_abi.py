@@ -98,3 +98,33 @@ def test_host_geometry_matches_oracle(cfg):
     vi, oil = OG.subap_table(cfg)
     assert idx == list(vi)
     assert np.array_equal(np.array(il), oil)
+
+
+@pytest.mark.parametrize("alt,pitch,n_want,size_want", [(0.0, 10, 5025, 800), (4000.0, 20, 1413, 848),
+                                                         (12700.0, 20, 1781, 952)])
+def test_host_dm_geometry_matches_oracle(alt, pitch, n_want, size_want):
+    from oracle import dm as OD
+    s = _lib()
+    act, size = s.dm_geometry(800, 4.875e-2, alt, pitch, 60.0)
+    want = OD.actuators(800, 4.875e-2, alt, pitch, 60.0)
+    assert len(act) == n_want == len(want) and size == size_want
+    assert np.array_equal(np.array(act), want)
+    assert size == OD.surface_size(800, 4.875e-2, alt, 60.0)
+
+
+def test_dm_and_residual_argument_checks():
+    s = _lib()
+    out = C.c_void_p()
+    assert s._lib.shw_dm_plan_create(s.ABI_VERSION, 801, 0.05, 0.0, 10, 60.0, 0.3, 64, C.byref(out)) == s.E_INVALID
+    assert s._lib.shw_dm_plan_create(s.ABI_VERSION, 800, 0.05, 0.0, 10, 60.0, 1.3, 64, C.byref(out)) == s.E_INVALID
+    assert s._lib.shw_dm_plan_create(s.ABI_VERSION, 800, 0.05, 0.0, 10, 60.0, 0.3, 63, C.byref(out)) == s.E_INVALID
+    assert s._lib.shw_dm_plan_create(s.ABI_VERSION, 800, 0.05, 0.0, 0, 60.0, 0.3, 64, C.byref(out)) == s.E_INVALID
+    assert s._lib.shw_dm_surface(None, None, None, None) == s.E_INVALID
+    so = (C.c_int32 * 2)(10, 1300)   # window leaves a 2048-wide screen
+    fake = C.c_void_p(16)
+    assert s._lib.shw_residual_opd(fake, 2048, 2048, 2048, 0, None, None, 800, 1, so, None, fake, 800, 640000,
+                                   None) == s.E_INVALID
+    assert s._lib.shw_residual_opd(fake, 2048, 2048, 2048, 5, None, None, 800, 1, so, None, fake, 800, 640000,
+                                   None) == s.E_INVALID
+    assert s._lib.shw_residual_opd(fake, 2048, 2048, 2048, 0, None, None, 800, 0, so, None, fake, 800, 640000,
+                                   None) == s.OK
