@@ -78,6 +78,93 @@ def cpu_baseline(cfg, launch, opd, min_seconds=10.0):
                       f"computed before timing"}
 
 
+def _time(fn, n, stream):
+    """Milliseconds per call of fn() over n calls, HIP events on `stream`."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(n):
+        fn(k)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def extras(stream):
+    """Secondary workloads: 8 m NGS frame replayed as a captured graph; 3 NGS 2x2 sub-apertures
+    of 400 px (FFT 512); science PSF of 9 stars x 20 frames including DM surfaces and residuals."""
+    import numpy as np
+    import torch
+
+    from gen import configs as G
+    from gen import screens as S
+    from paper_1408_0698_amd import shwfs
+    out = {}
+    # 8 m NGS (80 sub-apertures): launch-bound, replayed as a graph
+    plan0 = shwfs.WfsPlan(G.CFG0)
+    opd0 = torch.from_numpy(S.ngs8m_opd(1)[:, None].copy()).cuda()
+    sl0 = torch.zeros((1, 1, 2, plan0.n_valid), device="cuda")
+    ctr = torch.zeros(1, dtype=torch.int64, device="cuda")
+    gstream = torch.cuda.Stream()      # graph capture needs a stream other than the NULL stream
+    with torch.cuda.stream(gstream):
+        with shwfs.Graph.capture(gstream) as cap:
+            plan0.measure_devframe(opd0, sl0, ctr, stream=gstream)
+            shwfs.counter_add(ctr, 1, stream=gstream)
+        g = cap.graph
+        for _ in range(20):
+            g.launch(gstream)
+        ms_graph = _time(lambda k: g.launch(gstream), 500, gstream)
+        ms_eager = _time(lambda k: plan0.measure(opd0, sl0, frame0=k, stream=gstream), 500, gstream)
+    torch.cuda.synchronize()
+    out["ngs8m_graph_frames_per_s"] = 1e3 / ms_graph
+    out["ngs8m_eager_frames_per_s"] = 1e3 / ms_eager
+    # 3 NGS, 2x2 sub-apertures of 400 px padded to 512, noise on
+    plan4 = shwfs.WfsPlan(G.CFG4_NGS, 3)
+    opd4 = torch.from_numpy(S.lgs39m_opd(4, 3)).cuda()
+    sl4 = torch.zeros((4, 3, 2, plan4.n_valid), device="cuda")
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            plan4.measure(opd4, sl4, seed=1, stream=stream)
+        ms4 = _time(lambda k: plan4.measure(opd4, sl4, seed=1, frame0=4 * k, stream=stream), 20, stream)
+    out["ngs512_3x2x2_frames_per_s"] = 4e3 / ms4
+    # science PSF: DM surfaces from commands, residuals for 9 stars x 20 frames, PSF accumulation
+    scr = torch.from_numpy(S.screen_opd_m(2048, 4.875e-2).astype(np.float32)).cuda()
+    dms, coefs, surfs = [], [], []
+    for d, (alt, pitch) in enumerate(G.DMS):
+        dm = shwfs.DmPlan(800, 4.875e-2, alt, pitch, G.DM_FIELD_RADIUS_ARCSEC, G.DM_COUPLING, G.DM_PATCH)
+        dms.append(dm)
+        coefs.append(torch.from_numpy(S.dm_coefficients(dm.n_act, 100 + d).astype(np.float32)).cuda())
+        surfs.append(torch.zeros((dm.size, dm.size), device="cuda"))
+    arcsec = np.pi / 180 / 3600
+    nfr = G.CFG3_FRAMES
+    scr_o, dm_o = [], []
+    for (tx, ty) in G.CFG3_STARS:
+        for t in range(nfr):
+            scr_o.append((0, t))
+            dm_o.append([(sf.shape[0] // 2 - 400 + int(np.floor(alt * ty * arcsec / 4.875e-2 + 0.5)),
+                          sf.shape[0] // 2 - 400 + int(np.floor(alt * tx * arcsec / 4.875e-2 + 0.5)))
+                         for sf, (alt, _) in zip(surfs, G.DMS)])
+    res = torch.zeros((len(scr_o), 800, 800), device="cuda")
+    psf = shwfs.PsfPlan(800, 4.875e-2, 0.14, 1600, G.CFG3.wavelength_m)
+    acc = torch.zeros((9, 1600, 1600), device="cuda")
+    sr = torch.zeros((9, nfr), device="cuda")
+
+    def psf_step(k):
+        for dm, c, sf in zip(dms, coefs, surfs):
+            dm.surface(c, sf, stream=stream)
+        shwfs.residual_opd(scr, surfs, 800, scr_o, dm_o, res, stream=stream)
+        for st in range(9):
+            psf.accumulate(res[st * nfr:(st + 1) * nfr], acc[st], sr[st], stream=stream)
+
+    with torch.cuda.stream(stream):
+        psf_step(0)
+        ms3 = _time(psf_step, 3, stream)
+    out["psf_9stars_x20_star_frames_per_s"] = 9 * nfr * 1e3 / ms3
+    out["psf_step_ms"] = ms3
+    out["psf_mean_strehl_last_frame"] = float(sr[:, -1].mean().item())
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +173,8 @@ def main():
     ap.add_argument("--frames-per-step", type=int, default=1)
     ap.add_argument("--resident-frames", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before timing, run 5 plain device copies of this many MB (profiler counter scale)")
     args = ap.parse_args()
@@ -120,6 +209,16 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    variant = 0
+    tuned = None
+    if not args.no_autotune:
+        import tempfile
+
+        from paper_1408_0698_amd import autotune
+        os.environ.setdefault("SHW_AUTOTUNE_CACHE", os.path.join(tempfile.gettempdir(), "shwfs_autotune.json"))
+        tuned = autotune.tuned_variant(plan, opd[:B], slopes, "gfx950", reps=20, stream=stream, retune=True)
+        variant = tuned["variant"]
 
     def step(k):
         f0 = (k * B) % (nres - B + 1)
@@ -165,7 +264,11 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(B),
                      "kernel": "wfs_fused_kernel<10,40,40,16,lgs>",
                      "avg_launch_ms": avg_launch_ms},
+        "launch_variant": variant,
+        "autotune_ms_per_variant": tuned["ms_per_launch"] if tuned else None,
     }
+    if not args.no_extras:
+        out["extras"] = extras(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, launch, opd_host)
     print(json.dumps(out), flush=True)

@@ -87,7 +87,7 @@ typedef struct shw_wfs_config {
   double pupil_dx_m;          /* metres per pupil pixel, > 0 */
   double obstruction;         /* linear central obstruction, [0, 1) */
   int32_t n_subap;            /* sub-apertures across; divides pupil_n */
-  int32_t fft_n;              /* spot transform size, >= npx, multiple of npx */
+  int32_t fft_n;              /* spot transform size, in [npx, 4096] */
   int32_t conv_n;             /* convolution grid, >= fft_n, conv_n - fft_n even */
   int32_t det_n;              /* detector pixels across a sub-aperture, <= conv_n */
   int32_t lgs;                /* 0: NGS (no sodium kernel); 1: LGS */
@@ -204,6 +204,48 @@ typedef struct shw_work {
 int sh_wfs_measure_batch(const shw_work* items, int32_t n, void* hip_stream);
 
 int shw_wfs_plan_destroy(shw_wfs_plan* plan);
+
+/*
+ * Launch variants and autotuning (batching form: every sub-aperture of every
+ * sensor of every frame in one launch).  A plan has 1..n compiled launch
+ * variants of its fused kernel (register/occupancy target, one-shot or
+ * persistent grid); they give bitwise identical results.  Variant 0 is the
+ * default.  shw_wfs_plan_autotune times every variant on the given inputs
+ * (reps launches each after two warm-up launches, HIP events on the stream;
+ * synchronous), selects the fastest and returns its index in *best and the
+ * per-variant milliseconds per launch in ms (nullable, n entries).
+ */
+int shw_wfs_plan_variant_count(const shw_wfs_plan* plan, int32_t* n);
+int shw_wfs_plan_set_variant(shw_wfs_plan* plan, int32_t variant);
+int shw_wfs_plan_autotune(shw_wfs_plan* plan, const float* d_opd_m, int64_t row_pitch, int64_t wfs_stride,
+                          int64_t frame_stride, int32_t n_frames, float* d_slopes, int32_t reps, void* hip_stream,
+                          int32_t* best, float* ms);
+
+/*
+ * sh_wfs_measure with the frame number of the first frame read on the
+ * device from *d_frame0 when the kernel runs (so a captured graph can be
+ * replayed frame after frame; see shw_counter_add).  *d_frame0 + n_frames
+ * must be <= 2^32 (not checked: the value is only known on the device).
+ */
+int sh_wfs_measure_devframe(shw_wfs_plan* plan, const float* d_opd_m, int64_t row_pitch, int64_t wfs_stride,
+                            int64_t frame_stride, int32_t n_frames, uint64_t seed, const uint64_t* d_frame0,
+                            float* d_slopes, float* d_images, uint8_t* d_flags, void* hip_stream);
+
+/* *d_counter += inc on the device (a one-lane kernel, capturable). */
+int shw_counter_add(uint64_t* d_counter, uint64_t inc, void* hip_stream);
+
+/*
+ * Loop-step graphs: every library call issued on hip_stream between
+ * shw_graph_begin and shw_graph_end is recorded (nothing runs) into a HIP
+ * graph, instantiated by shw_graph_end; shw_graph_launch replays it on a
+ * stream.  Kernel arguments, including buffer addresses, are fixed at
+ * capture.  hip_stream must not be the NULL stream.
+ */
+typedef struct shw_graph shw_graph;
+int shw_graph_begin(void* hip_stream);
+int shw_graph_end(void* hip_stream, shw_graph** out);
+int shw_graph_launch(shw_graph* graph, void* hip_stream);
+int shw_graph_destroy(shw_graph* graph);
 
 /*
  * Science PSF (Sec. 3 PSF block, Sec. 5 integrated PSF and Strehl ratio).

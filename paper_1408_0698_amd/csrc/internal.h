@@ -24,6 +24,7 @@ struct WfsLaunch {
   float ron, thr;
   int32_t noise;
   uint32_t key0, key1, frame0;
+  const uint64_t* frame0_dev;  // nullable: frame number of the first frame, read on the device
 };
 
 // Shape of a compiled fused kernel.
@@ -34,8 +35,14 @@ struct WfsShape {
 // Returns true if a kernel for this shape is compiled in.
 bool wfs_shape_supported(const WfsShape& s);
 
+// Number of compiled launch variants of a shape (0 if unsupported).
+int wfs_variant_count(const WfsShape& s);
+
 // Launch the fused kernel for a.total work items. Returns the HIP error.
-hipError_t launch_wfs_fused(const WfsShape& s, const WfsLaunch& a, hipStream_t st);
+hipError_t launch_wfs_fused(const WfsShape& s, int variant, const WfsLaunch& a, hipStream_t st);
+
+// *d_counter += inc (one lane).
+hipError_t launch_counter_add(uint64_t* d_counter, uint64_t inc, hipStream_t st);
 
 // Kernel spectra: params [n][3] = (sigma_par, sigma_perp, psi) in conv-grid
 // pixels / radians (device, FP64); out [n][conv_n/2+1][conv_n] FP32, scaled by 1/conv_n^2.

@@ -14,6 +14,42 @@
 
 namespace shw {
 
+// ln(k!) for k < 256, FP64 at compile time (ln x = 2 atanh((x-1)/(x+1)) after
+// scaling into [0.75, 1.5]), rounded to FP32.
+constexpr double ct_log(double x) {
+  int e = 0;
+  while (x > 1.5) {
+    x *= 0.5;
+    ++e;
+  }
+  while (x < 0.75) {
+    x *= 2.0;
+    --e;
+  }
+  const double t = (x - 1.0) / (x + 1.0), t2 = t * t;
+  double term = t, sum = 0.0;
+  for (int n = 1; n < 80; n += 2) {
+    sum += term / n;
+    term *= t2;
+  }
+  return 2.0 * sum + e * 0.693147180559945309417232121458;
+}
+struct LogFactorialTable {
+  float v[256];
+  constexpr LogFactorialTable() : v() {
+    double acc = 0.0;
+    for (int k = 1; k < 256; ++k) {
+      acc += ct_log((double)k);
+      v[k] = (float)acc;
+    }
+  }
+};
+__constant__ const LogFactorialTable kLogFactorial = LogFactorialTable();
+
+__device__ __forceinline__ float log_factorial(float k) {
+  return k < 256.0f ? kLogFactorial.v[(int)k] : lgammaf(k + 1.0f);
+}
+
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
@@ -21,9 +57,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    // one 32 x 32 -> 64-bit product per multiplier (v_mad_u64_u32), split into hi and lo words
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
   }
   return c;
 }
@@ -33,7 +70,7 @@ __device__ __forceinline__ float u01(uint32_t x) {
   return ((float)(x >> 9) + 0.5f) * 1.1920928955078125e-07f;
 }
 
-__device__ __noinline__ int poisson_inversion(float lam, float u) {
+__device__ __forceinline__ int poisson_inversion(float lam, float u) {
 #pragma clang fp contract(off)
   float p = expf(-lam);
   float F = p;
@@ -46,7 +83,7 @@ __device__ __noinline__ int poisson_inversion(float lam, float u) {
   return k;
 }
 
-__device__ __noinline__ int poisson_ptrs(float lam, float u0, float v0, uint32_t pix, uint32_t gsub,
+__device__ __forceinline__ int poisson_ptrs(float lam, float u0, float v0, uint32_t pix, uint32_t gsub,
                                          uint32_t frame, uint32_t k0, uint32_t k1) {
 #pragma clang fp contract(off)
   const float slam = sqrtf(lam);
@@ -69,10 +106,17 @@ __device__ __noinline__ int poisson_ptrs(float lam, float u0, float v0, uint32_t
     if (us >= 0.07f && V <= vr) return kf > 0.0f ? (int)kf : 0;
     if (kf < 0.0f || (us < 0.013f && V > us)) continue;
     const float lhs = logf(V) + logf(invalpha) - logf(a / (us * us) + b);
-    const float rhs = -lam + kf * loglam - lgammaf(kf + 1.0f);
+    const float rhs = -lam + kf * loglam - log_factorial(kf);
     if (lhs <= rhs) return (int)kf;
   }
   return (int)floorf(lam + 0.5f);
+}
+
+// Standard normal from words 2 and 3 of the trial-0 block (Box-Muller).  No integer
+// decision depends on it, so the hardware cosine (argument in revolutions) and log2
+// are used: their ~1e-6 relative error is far below the read-noise tolerance.
+__device__ __forceinline__ float read_noise_z(uint4 w) {
+  return sqrtf(-2.0f * __logf(u01(w.z))) * __builtin_amdgcn_cosf(u01(w.w));
 }
 
 // Electrons of one pixel with mean lam: Poisson counts + ron * N(0, 1).
@@ -86,10 +130,7 @@ __device__ __forceinline__ float noisy_pixel(float lam, float ron, uint32_t pix,
     else
       k = poisson_ptrs(lam, u01(w.x), u01(w.y), pix, gsub, frame, k0, k1);
   }
-  float s, c;
-  sincospif(2.0f * u01(w.w), &s, &c);
-  const float z = sqrtf(-2.0f * logf(u01(w.z))) * c;
-  return (float)k + ron * z;
+  return (float)k + ron * read_noise_z(w);
 }
 
 }  // namespace shw

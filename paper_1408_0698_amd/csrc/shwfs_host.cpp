@@ -16,6 +16,7 @@
 #include "internal.h"
 #include "psf_internal.h"
 #include "dm_internal.h"
+#include "big_internal.h"
 
 using namespace shw;
 
@@ -60,6 +61,12 @@ struct shw_wfs_plan {
   float* d_khat = nullptr;
   size_t bytes = 0;
   std::vector<int32_t> valid;
+  int32_t variant = 0;
+  // large sub-apertures (FFT 512): row/column workspace for chunk_items work items
+  bool big = false;
+  int64_t chunk_items = 0;
+  float2* d_T = nullptr;
+  float* d_Jr = nullptr;
 };
 
 
@@ -82,8 +89,8 @@ static int check_config(const shw_wfs_config* c, int32_t n_wfs, const shw_lgs_ge
   if (c->n_subap < 1 || c->pupil_n % c->n_subap != 0)
     return fail(SHW_E_INVALID, "n_subap %d must divide pupil_n %d", c->n_subap, c->pupil_n);
   const int npx = c->pupil_n / c->n_subap;
-  if (c->fft_n < npx || c->fft_n % npx != 0)
-    return fail(SHW_E_INVALID, "fft_n %d must be a multiple of the sub-aperture size %d", c->fft_n, npx);
+  if (c->fft_n < npx || c->fft_n > 4096)
+    return fail(SHW_E_INVALID, "fft_n %d must be in [sub-aperture size %d, 4096]", c->fft_n, npx);
   if (c->conv_n < c->fft_n || (c->conv_n - c->fft_n) % 2 != 0)
     return fail(SHW_E_INVALID, "conv_n %d must be >= fft_n %d with an even difference", c->conv_n, c->fft_n);
   if (c->det_n < 1 || c->det_n > c->conv_n) return fail(SHW_E_INVALID, "det_n %d outside [1, conv_n]", c->det_n);
@@ -112,7 +119,7 @@ static int check_config(const shw_wfs_config* c, int32_t n_wfs, const shw_lgs_ge
   }
   if (prec != SHW_PREC_FP32) return fail(SHW_E_UNSUPPORTED, "precision %u has no kernel for this shape", prec);
   const WfsShape shape{npx, c->fft_n, c->conv_n, c->det_n, c->lgs};
-  if (!wfs_shape_supported(shape))
+  if (!wfs_shape_supported(shape) && !big_shape_supported(npx, c->fft_n, c->conv_n, c->det_n, c->lgs))
     return fail(SHW_E_UNSUPPORTED, "no kernel for npx %d, fft_n %d, conv_n %d, det_n %d, lgs %d", npx, c->fft_n,
                 c->conv_n, c->det_n, c->lgs);
   return SHW_OK;
@@ -198,6 +205,8 @@ extern "C" int shw_wfs_plan_destroy(shw_wfs_plan* p) {
   if (cur != p->device) (void)hipSetDevice(p->device);
   if (p->d_valid) (void)hipFree(p->d_valid);
   if (p->d_khat) (void)hipFree(p->d_khat);
+  if (p->d_T) (void)hipFree(p->d_T);
+  if (p->d_Jr) (void)hipFree(p->d_Jr);
   if (cur != p->device) (void)hipSetDevice(cur);
   delete p;
   return ok();
@@ -234,6 +243,22 @@ extern "C" int shw_wfs_plan_create(const shw_wfs_config* cfg, int32_t n_wfs, con
     return hip_fail(e, "plan tables");
   }
   p->bytes = sizeof(int32_t) * p->n_valid;
+  p->big = !wfs_shape_supported(p->shape);
+  if (p->big) {
+    // about 128 MB of row intermediates per chunk, at least one sensor frame
+    const int64_t per_item = (int64_t)p->npx * cfg->fft_n * (int64_t)sizeof(float2);
+    int64_t chunk = ((int64_t)128 << 20) / per_item;
+    if (chunk < 1) chunk = 1;
+    if (chunk > (int64_t)n_wfs * p->n_valid * 16) chunk = (int64_t)n_wfs * p->n_valid * 16;
+    p->chunk_items = chunk;
+    e = hipMalloc(&p->d_T, (size_t)(chunk * per_item));
+    if (e == hipSuccess) e = hipMalloc(&p->d_Jr, sizeof(float) * (size_t)chunk * cfg->det_n * cfg->fft_n);
+    if (e != hipSuccess) {
+      shw_wfs_plan_destroy(p);
+      return hip_fail(e, "large sub-aperture workspace");
+    }
+    p->bytes += (size_t)(chunk * per_item) + sizeof(float) * (size_t)chunk * cfg->det_n * cfg->fft_n;
+  }
   if (cfg->lgs) {
     const int64_t n = (int64_t)n_wfs * p->n_valid;
     const int H = cfg->conv_n / 2 + 1;
@@ -296,16 +321,17 @@ static WfsLaunch base_launch(const shw_wfs_plan* p) {
   return a;
 }
 
-extern "C" int sh_wfs_measure(shw_wfs_plan* p, const float* d_opd_m, int64_t row_pitch, int64_t wfs_stride,
-                              int64_t frame_stride, int32_t n_frames, uint64_t seed, uint64_t frame0,
-                              float* d_slopes, float* d_images, uint8_t* d_flags, void* stream) {
+static int measure_impl(shw_wfs_plan* p, const float* d_opd_m, int64_t row_pitch, int64_t wfs_stride,
+                        int64_t frame_stride, int32_t n_frames, uint64_t seed, uint64_t frame0,
+                        const uint64_t* d_frame0, float* d_slopes, float* d_images, uint8_t* d_flags, void* stream) {
   if (!p) return fail(SHW_E_INVALID, "plan is NULL");
   if (n_frames < 0) return fail(SHW_E_INVALID, "n_frames %d < 0", n_frames);
   if (n_frames == 0) return ok();
   if (!d_opd_m || !d_slopes) return fail(SHW_E_INVALID, "NULL OPD or slope buffer");
   if (row_pitch < p->cfg.pupil_n) return fail(SHW_E_INVALID, "row_pitch %lld < pupil_n", (long long)row_pitch);
   if (wfs_stride < 0 || frame_stride < 0) return fail(SHW_E_INVALID, "negative stride");
-  if (frame0 + (uint64_t)n_frames > (1ull << 32)) return fail(SHW_E_INVALID, "frame counter exceeds 2^32");
+  if (!d_frame0 && frame0 + (uint64_t)n_frames > (1ull << 32)) return fail(SHW_E_INVALID, "frame counter exceeds 2^32");
+  if (d_frame0 && p->big) return fail(SHW_E_UNSUPPORTED, "device frame counter not available for FFT 512 plans");
   WfsLaunch a = base_launch(p);
   a.opd = d_opd_m;
   a.row_pitch = row_pitch;
@@ -318,7 +344,41 @@ extern "C" int sh_wfs_measure(shw_wfs_plan* p, const float* d_opd_m, int64_t row
   a.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
   a.key1 = (uint32_t)(seed >> 32);
   a.frame0 = (uint32_t)frame0;
-  hipError_t e = launch_wfs_fused(p->shape, a, (hipStream_t)stream);
+  a.frame0_dev = d_frame0;
+  if (p->big) {
+    BigLaunch b{};
+    b.opd = a.opd;
+    b.row_pitch = a.row_pitch;
+    b.wfs_stride = a.wfs_stride;
+    b.frame_stride = a.frame_stride;
+    b.valid_idx = a.valid_idx;
+    b.slopes = a.slopes;
+    b.images = a.images;
+    b.flags = a.flags;
+    b.n_valid = a.n_valid;
+    b.n_wfs = a.n_wfs;
+    b.n_subap = a.n_subap;
+    b.npx = p->npx;
+    b.det_n = p->cfg.det_n;
+    b.inv_lambda = a.inv_lambda;
+    b.r2_outer = a.r2_outer;
+    b.r2_inner = a.r2_inner;
+    b.half_n = a.half_n;
+    b.ph_scale = a.ph_scale;
+    b.ron = a.ron;
+    b.thr = a.thr;
+    b.noise = a.noise;
+    b.key0 = a.key0;
+    b.key1 = a.key1;
+    b.frame0 = a.frame0;
+    for (int64_t i0 = 0; i0 < a.total; i0 += p->chunk_items) {
+      const int64_t n = a.total - i0 < p->chunk_items ? a.total - i0 : p->chunk_items;
+      hipError_t e = launch_big(b, i0, n, p->d_T, p->d_Jr, (hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, "sh_wfs_measure launch");
+    }
+    return ok();
+  }
+  hipError_t e = launch_wfs_fused(p->shape, p->variant, a, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "sh_wfs_measure launch");
   return ok();
 }
@@ -607,5 +667,140 @@ extern "C" int shw_residual_opd(const float* d_screen, int32_t screen_rows, int3
     hipError_t e = launch_residual(a, nk, d_out + (int64_t)k0 * out_stride, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "shw_residual_opd launch");
   }
+  return ok();
+}
+
+extern "C" int sh_wfs_measure(shw_wfs_plan* p, const float* d_opd_m, int64_t row_pitch, int64_t wfs_stride,
+                              int64_t frame_stride, int32_t n_frames, uint64_t seed, uint64_t frame0,
+                              float* d_slopes, float* d_images, uint8_t* d_flags, void* stream) {
+  return measure_impl(p, d_opd_m, row_pitch, wfs_stride, frame_stride, n_frames, seed, frame0, nullptr, d_slopes,
+                      d_images, d_flags, stream);
+}
+
+extern "C" int sh_wfs_measure_devframe(shw_wfs_plan* p, const float* d_opd_m, int64_t row_pitch, int64_t wfs_stride,
+                                       int64_t frame_stride, int32_t n_frames, uint64_t seed, const uint64_t* d_frame0,
+                                       float* d_slopes, float* d_images, uint8_t* d_flags, void* stream) {
+  if (!d_frame0) return fail(SHW_E_INVALID, "d_frame0 is NULL");
+  return measure_impl(p, d_opd_m, row_pitch, wfs_stride, frame_stride, n_frames, seed, 0, d_frame0, d_slopes,
+                      d_images, d_flags, stream);
+}
+
+// ---------------------------------------------------------------- variants, autotuning
+
+extern "C" int shw_wfs_plan_variant_count(const shw_wfs_plan* p, int32_t* n) {
+  if (!p || !n) return fail(SHW_E_INVALID, "NULL argument");
+  *n = p->big ? 1 : wfs_variant_count(p->shape);
+  return ok();
+}
+
+extern "C" int shw_wfs_plan_set_variant(shw_wfs_plan* p, int32_t v) {
+  if (!p) return fail(SHW_E_INVALID, "plan is NULL");
+  const int n = p->big ? 1 : wfs_variant_count(p->shape);
+  if (v < 0 || v >= n) return fail(SHW_E_INVALID, "variant %d outside [0, %d)", v, n);
+  p->variant = v;
+  return ok();
+}
+
+extern "C" int shw_wfs_plan_autotune(shw_wfs_plan* p, const float* d_opd_m, int64_t row_pitch, int64_t wfs_stride,
+                                     int64_t frame_stride, int32_t n_frames, float* d_slopes, int32_t reps,
+                                     void* stream, int32_t* best, float* ms) {
+  if (!p || !best) return fail(SHW_E_INVALID, "NULL argument");
+  if (n_frames < 1 || reps < 1 || reps > 100000) return fail(SHW_E_INVALID, "n_frames >= 1 and reps in [1, 1e5]");
+  const int n = p->big ? 1 : wfs_variant_count(p->shape);
+  const int32_t keep = p->variant;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(e, "autotune events");
+  }
+  float best_ms = 0.0f;
+  int32_t best_v = 0;
+  int rc = SHW_OK;
+  for (int v = 0; v < n && rc == SHW_OK; ++v) {
+    p->variant = v;
+    for (int k = 0; k < 2 + reps && rc == SHW_OK; ++k) {
+      if (k == 2) e = hipEventRecord(e0, (hipStream_t)stream);
+      if (e != hipSuccess) break;
+      rc = sh_wfs_measure(p, d_opd_m, row_pitch, wfs_stride, frame_stride, n_frames, 0, 0, d_slopes, nullptr,
+                          nullptr, stream);
+    }
+    if (rc != SHW_OK) break;
+    if (e == hipSuccess) e = hipEventRecord(e1, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e != hipSuccess) break;
+    t /= (float)reps;
+    if (ms) ms[v] = t;
+    if (v == 0 || t < best_ms) {
+      best_ms = t;
+      best_v = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != SHW_OK) {
+    p->variant = keep;
+    return rc;
+  }
+  if (e != hipSuccess) {
+    p->variant = keep;
+    return hip_fail(e, "autotune timing");
+  }
+  p->variant = best_v;
+  *best = best_v;
+  return ok();
+}
+
+// ---------------------------------------------------------------- graphs, device counters
+
+struct shw_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" int shw_counter_add(uint64_t* d_counter, uint64_t inc, void* stream) {
+  if (!d_counter) return fail(SHW_E_INVALID, "d_counter is NULL");
+  hipError_t e = launch_counter_add(d_counter, inc, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "shw_counter_add launch");
+  return ok();
+}
+
+extern "C" int shw_graph_begin(void* stream) {
+  if (!stream) return fail(SHW_E_INVALID, "graph capture needs a non-NULL stream");
+  hipError_t e = hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  return ok();
+}
+
+extern "C" int shw_graph_end(void* stream, shw_graph** out) {
+  if (!stream || !out) return fail(SHW_E_INVALID, "NULL argument");
+  *out = nullptr;
+  auto* g = new shw_graph();
+  hipError_t e = hipStreamEndCapture((hipStream_t)stream, &g->graph);
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return hip_fail(e, "graph capture");
+  }
+  *out = g;
+  return ok();
+}
+
+extern "C" int shw_graph_launch(shw_graph* g, void* stream) {
+  if (!g) return fail(SHW_E_INVALID, "graph is NULL");
+  hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return ok();
+}
+
+extern "C" int shw_graph_destroy(shw_graph* g) {
+  if (!g) return ok();
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
   return ok();
 }

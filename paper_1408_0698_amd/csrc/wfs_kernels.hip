@@ -43,29 +43,51 @@ constexpr float rebin_weight(int CN, int DN, int p, int k) {
   return hi > lo ? (float)(hi - lo) : 0.0f;
 }
 
-template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB>
-__global__ __launch_bounds__(SPB * CONV_N) void wfs_fused_kernel(const WfsLaunch a) {
+// Value of the same register in the partner lane t ^ 1 (DPP quad permutation 1, 0, 3, 2).
+__device__ __forceinline__ float pair_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float2 pair_swap(float2 v) { return make_float2(pair_swap(v.x), pair_swap(v.y)); }
+
+// LDS floats per item for the given shape.
+template <int NPX, int FFT_N, int CONV_N, int DET_N>
+struct FusedLayout {
+  static constexpr int HN = CONV_N / 2;
+  static constexpr int ST = CONV_N + 1;
+  static constexpr int ROWS0 = NPX > HN + 1 ? NPX : HN + 1;
+  static constexpr int ROWS = ROWS0 > DET_N ? ROWS0 : DET_N;
+  static constexpr int NPIX = DET_N * DET_N;
+  static constexpr int RED = (NPIX + 2 + 1) & ~1;
+  static constexpr int PLANE0 = ROWS * ST > RED + 6 * CONV_N ? ROWS * ST : RED + 6 * CONV_N;
+  static constexpr int PLANE = (PLANE0 + 1) & ~1;
+};
+
+// One group of SPB work items (one block's worth).  Every lane of the block calls it.
+template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, bool SPLIT>
+__device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t group, uint32_t frame_base,
+                                                float* __restrict__ s_re, float* __restrict__ s_im) {
   constexpr int L = CONV_N;                  // lanes per item
   constexpr int R = FFT_N / NPX;             // column residues of the row pass
-  constexpr int H = CONV_N / 2 + 1;          // stored half spectrum rows
+  constexpr int H = CONV_N / 2 + 1;          // stored half spectrum rows (kernel spectra)
+  constexpr int HN = CONV_N / 2;             // half length; packed spectrum rows in LDS
   constexpr int ST = CONV_N + 1;             // odd LDS row stride (floats)
-  constexpr int ROWS0 = NPX > H ? NPX : H;
+  constexpr int ROWS0 = NPX > HN ? NPX : HN;
   constexpr int ROWS = ROWS0 > DET_N ? ROWS0 : DET_N;
-  constexpr int PLANE = ((ROWS * ST) + 1) & ~1;  // even: the imaginary plane is reused for doubles
+  using LY = FusedLayout<NPX, FFT_N, CONV_N, DET_N>;
+  constexpr int NPIX = LY::NPIX;
+  // stage D reuses the imaginary plane: a queue of NPIX pixel indices, its count, then 3 L doubles
+  constexpr int QCOUNT = NPIX;
+  constexpr int RED = LY::RED;
+  constexpr int PLANE = LY::PLANE;  // even: doubles stay 8-byte aligned
   constexpr int OFF = (CONV_N - FFT_N) / 2;  // spot offset in the convolution grid
   constexpr float INV_N2 = 1.0f / (float)(FFT_N * FFT_N);
-  constexpr int NPIX = DET_N * DET_N;
   constexpr int PIX_ITERS = (NPIX + L - 1) / L;
   static_assert(FFT_N % NPX == 0 && CONV_N >= FFT_N && (CONV_N - FFT_N) % 2 == 0, "shape");
-  static_assert(3 * L * 2 <= PLANE, "reduction space");
-
-  __shared__ __align__(16) float s_re[SPB * PLANE];
-  __shared__ __align__(16) float s_im[SPB * PLANE];
 
   const int tid = threadIdx.x;
   const int s = tid / L;
   const int l = tid - s * L;
-  const int64_t item = (int64_t)blockIdx.x * SPB + s;
+  const int64_t item = group * SPB + s;
   const bool active = item < a.total;
   const int64_t per_frame = (int64_t)a.n_wfs * a.n_valid;
   const int64_t it = active ? item : 0;
@@ -134,50 +156,152 @@ __global__ __launch_bounds__(SPB * CONV_N) void wfs_fused_kernel(const WfsLaunch
   }
 
   // ---------------------------------------------------------------- B: convolution with k
+  // J = I (*) k through the half spectrum of the real image.  Columns: real transforms as
+  // half-length complex transforms.  Rows 0 and N/2 of the column spectrum are real and are
+  // packed into one complex row, leaving N/2 rows; each row is filtered by a lane pair that
+  // splits its N-point transforms radix-2 (even/odd samples), exchanging halves through DPP.
   if constexpr (LGS) {
+    static_assert(CONV_N % 4 == 0, "LGS convolution needs conv_n divisible by 4");
     __syncthreads();  // every lane has read the row-pass plane
     {
-      float2 z[CONV_N];
+      // B1: R[k] = sum_v I[v] w^(kv), k = 0..N/2, from Z = FFT_{N/2}(I[2m] + i I[2m+1])
+      float2 z[HN];
 #pragma unroll
-      for (int v = 0; v < CONV_N; ++v) z[v] = make_float2(col[v], 0.0f);
-      RegFFT<CONV_N, -1>::run(z);
+      for (int m = 0; m < HN; ++m) z[m] = make_float2(col[2 * m], col[2 * m + 1]);
+      RegFFT<HN, -1>::run(z);
+      float r0 = 0.0f, rh = 0.0f;
 #pragma unroll
-      for (int k = 0; k < H; ++k) {
-        re[k * ST + l] = z[k].x;
-        im[k * ST + l] = z[k].y;
+      for (int k = 0; k <= HN; ++k) {
+        const float2 zk = z[k % HN];
+        const float2 zc = cconj(z[(HN - k) % HN]);
+        const float2 ev = cscale(cadd(zk, zc), 0.5f);
+        // odd part: -i/2 (zk - zc), times w^k
+        const float2 d = csub(zk, zc);
+        const float2 od = twiddle_mul<CONV_N, -1>(make_float2(0.5f * d.y, -0.5f * d.x), k);
+        const float2 r = cadd(ev, od);
+        if (k == 0) {
+          r0 = r.x;
+        } else if (k == HN) {
+          rh = r.x;
+        } else {
+          re[k * ST + l] = r.x;
+          im[k * ST + l] = r.y;
+        }
+      }
+      if constexpr (SPLIT) {
+        re[l] = r0;  // rows 0 and N/2 are real: packed as one complex row
+        im[l] = rh;
+      } else {
+        re[l] = r0;
+        im[l] = 0.0f;
+        re[HN * ST + l] = rh;
+        im[HN * ST + l] = 0.0f;
       }
     }
     __syncthreads();
-    if (active && l < H) {
-      float2 z[CONV_N];
+    if constexpr (!SPLIT) {
+      // B2 (whole rows): lane k < N/2 + 1 transforms row k, multiplies by K^, transforms back
+      if (active && l <= HN) {
+        float2 z[CONV_N];
 #pragma unroll
-      for (int u = 0; u < CONV_N; ++u) z[u] = make_float2(re[l * ST + u], im[l * ST + u]);
-      RegFFT<CONV_N, -1>::run(z);
-      const float* kh = a.khat + ((int64_t)(w * a.n_valid + i) * H + l) * CONV_N;
+        for (int u = 0; u < CONV_N; ++u) z[u] = make_float2(re[l * ST + u], im[l * ST + u]);
+        RegFFT<CONV_N, -1>::run(z);
+        const float* kh = a.khat + ((int64_t)(w * a.n_valid + i) * H + l) * CONV_N;
 #pragma unroll
-      for (int u = 0; u < CONV_N; ++u) z[u] = cscale(z[u], kh[u]);
-      RegFFT<CONV_N, 1>::run(z);
+        for (int u = 0; u < CONV_N; ++u) z[u] = cscale(z[u], kh[u]);
+        RegFFT<CONV_N, 1>::run(z);
 #pragma unroll
-      for (int u = 0; u < CONV_N; ++u) {
-        re[l * ST + u] = z[u].x;
-        im[l * ST + u] = z[u].y;
+        for (int u = 0; u < CONV_N; ++u) {
+          re[l * ST + u] = z[u].x;
+          im[l * ST + u] = z[u].y;
+        }
+      }
+    } else if (active) {
+      // B2: lane pair (r, h): forward row transform, multiply by K^, inverse row transform
+      const int r = l >> 1, h = l & 1;
+      float2 x[HN];
+#pragma unroll
+      for (int u = 0; u < HN; ++u) x[u] = make_float2(re[r * ST + 2 * u + h], im[r * ST + 2 * u + h]);
+      RegFFT<HN, -1>::run(x);
+      if (h) {
+#pragma unroll
+        for (int c = 0; c < HN; ++c) x[c] = twiddle_mul<CONV_N, -1>(x[c], c);
+      }
+#pragma unroll
+      for (int c = 0; c < HN; ++c) {
+        const float2 o = pair_swap(x[c]);
+        // h = 0: X[c] = E + W O (partner holds W O); h = 1: X[c + N/2] = E (partner) - W O
+        x[c] = h ? csub(o, x[c]) : cadd(x[c], o);
+      }
+      const float* kh = a.khat + ((int64_t)(w * a.n_valid + i) * H) * CONV_N + h * HN;
+      if (r == 0) {
+        // packed row: Y = X (K0 + KH)/2 + conj(X[-c]) (K0 - KH)/2
+        float2 mir[HN];
+#pragma unroll
+        for (int c = 0; c < HN; ++c) mir[c] = pair_swap(x[c]);
+        float2 y[HN];
+#pragma unroll
+        for (int c = 0; c < HN; ++c) {
+          const float2 xm = cconj(c == 0 ? x[0] : mir[HN - c]);
+          const float k0 = kh[c], kn = kh[HN * CONV_N + c];
+          const float ka = 0.5f * (k0 + kn), kb = 0.5f * (k0 - kn);
+          y[c] = cadd(cscale(x[c], ka), cscale(xm, kb));
+        }
+#pragma unroll
+        for (int c = 0; c < HN; ++c) x[c] = y[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < HN; ++c) x[c] = cscale(x[c], kh[r * CONV_N + c]);
+      }
+      // inverse: h = 0 -> even outputs from Y[c] + Y[c+N/2]; h = 1 -> odd outputs from (Y[c] - Y[c+N/2]) W^-c
+#pragma unroll
+      for (int c = 0; c < HN; ++c) {
+        const float2 o = pair_swap(x[c]);
+        x[c] = h ? twiddle_mul<CONV_N, 1>(csub(o, x[c]), c) : cadd(x[c], o);
+      }
+      RegFFT<HN, 1>::run(x);
+#pragma unroll
+      for (int u = 0; u < HN; ++u) {
+        re[r * ST + 2 * u + h] = x[u].x;
+        im[r * ST + 2 * u + h] = x[u].y;
       }
     }
     __syncthreads();
     {
-      float2 z[CONV_N];
+      // B3: real J from the half spectrum: y = IFFT_{N/2}(C), C[k] = (Z[k] + conj Z[N/2-k])
+      //     + i W^-k (Z[k] - conj Z[N/2-k]); J[2m] = Re y[m], J[2m+1] = Im y[m]
+      float2 zz[HN + 1];
+      if constexpr (SPLIT) {
+        zz[0] = make_float2(re[l], 0.0f);
+        zz[HN] = make_float2(im[l], 0.0f);
+      } else {
+        zz[0] = make_float2(re[l], 0.0f);
+        zz[HN] = make_float2(re[HN * ST + l], 0.0f);
+      }
 #pragma unroll
-      for (int k = 0; k < H; ++k) z[k] = make_float2(re[k * ST + l], im[k * ST + l]);
+      for (int k = 1; k < HN; ++k) zz[k] = make_float2(re[k * ST + l], im[k * ST + l]);
+      float2 y[HN];
 #pragma unroll
-      for (int k = 1; k < CONV_N / 2; ++k) z[CONV_N - k] = cconj(z[k]);
-      RegFFT<CONV_N, 1>::run(z);
+      for (int k = 0; k < HN; ++k) {
+        const float2 zk = zz[k];
+        const float2 zc = cconj(zz[HN - k]);
+        const float2 e = cadd(zk, zc);
+        const float2 d = twiddle_mul<CONV_N, 1>(csub(zk, zc), k);
+        y[k] = make_float2(e.x - d.y, e.y + d.x);
+      }
+      RegFFT<HN, 1>::run(y);
 #pragma unroll
-      for (int v = 0; v < CONV_N; ++v) col[v] = z[v].x;
+      for (int m = 0; m < HN; ++m) {
+        col[2 * m] = y[m].x;
+        col[2 * m + 1] = y[m].y;
+      }
     }
   }
 
   // ---------------------------------------------------------------- C: rebin
   __syncthreads();  // the planes are free
+  int* queue = reinterpret_cast<int*>(im);
+  if (l == 0) queue[QCOUNT] = 0;
 #pragma unroll
   for (int p = 0; p < DET_N; ++p) {
     float acc = 0.0f;
@@ -191,55 +315,108 @@ __global__ __launch_bounds__(SPB * CONV_N) void wfs_fused_kernel(const WfsLaunch
   __syncthreads();
 
   // ---------------------------------------------------------------- D: photometry, noise, centroid
+  // Pass 1 handles every pixel except noisy ones with mean >= 10, which are queued in LDS;
+  // pass 2 runs the rejection sampler on the queue with the item's lanes side by side.
   constexpr float B = (float)CONV_N / (float)DET_N;
   constexpr float CD = 0.5f * (float)(DET_N - 1);
   double s0 = 0.0, sx = 0.0, sy = 0.0;
   const uint32_t gsub = (uint32_t)(w * a.n_valid + i);
-  const uint32_t frame = a.frame0 + (uint32_t)f;
+  const uint32_t frame = frame_base + (uint32_t)f;
+  auto detector_pixel = [&](int pix) {
+    const int p = pix / DET_N;
+    const int q = pix - p * DET_N;
+    const float lo = B * (float)q, hi = B * (float)(q + 1);
+    const int kb = (int)floorf(lo);
+    const int ke = min((int)ceilf(hi), CONV_N);
+    float det = 0.0f;
+    for (int k = kb; k < ke; ++k) {
+      const float wgt = fminf((float)(k + 1), hi) - fmaxf((float)k, lo);
+      if (wgt > 0.0f) det += wgt * re[p * ST + k];
+    }
+    return det;
+  };
+  auto accumulate = [&](int pix, float img) {
+    const int p = pix / DET_N;
+    const int q = pix - p * DET_N;
+    if (a.images) a.images[item * NPIX + pix] = img;
+    const double t = (double)fmaxf(img - a.thr, 0.0f);
+    s0 += t;
+    sx += (double)((float)q - CD) * t;
+    sy += (double)((float)p - CD) * t;
+  };
   if (active) {
 #pragma unroll 1
     for (int j = 0; j < PIX_ITERS; ++j) {
       const int pix = l + L * j;
       if (pix >= NPIX) break;
-      const int p = pix / DET_N;
-      const int q = pix - p * DET_N;
-      const float lo = B * (float)q, hi = B * (float)(q + 1);
-      const int kb = (int)floorf(lo);
-      const int ke = min((int)ceilf(hi), CONV_N);
-      float det = 0.0f;
-      for (int k = kb; k < ke; ++k) {
-        const float wgt = fminf((float)(k + 1), hi) - fmaxf((float)k, lo);
-        if (wgt > 0.0f) det += wgt * re[p * ST + k];
-      }
+      const float det = detector_pixel(pix);
       float img = det;
       if (a.ph_scale > 0.0f) {
         const float lam = a.ph_scale * det;
-        img = a.noise ? noisy_pixel(lam, a.ron, (uint32_t)pix, gsub, frame, a.key0, a.key1) : lam;
+        img = lam;
+        if (a.noise) {
+          if (lam >= 10.0f) {
+            queue[atomicAdd(&queue[QCOUNT], 1)] = pix;
+            continue;
+          }
+          const uint4 wd = philox4x32_10(make_uint4(0u, (uint32_t)pix, gsub, frame), a.key0, a.key1);
+          const int k = lam > 0.0f ? poisson_inversion(lam, u01(wd.x)) : 0;
+          img = (float)k + a.ron * read_noise_z(wd);
+        }
       }
-      if (a.images) a.images[item * NPIX + pix] = img;
-      const double t = (double)fmaxf(img - a.thr, 0.0f);
-      s0 += t;
-      sx += (double)((float)q - CD) * t;
-      sy += (double)((float)p - CD) * t;
+      accumulate(pix, img);
     }
   }
-  double* red = reinterpret_cast<double*>(im);
+  __syncthreads();
+  if (active) {
+    const int nq = queue[QCOUNT];
+#pragma unroll 1
+    for (int e = l; e < nq; e += L) {
+      const int pix = queue[e];
+      const float lam = a.ph_scale * detector_pixel(pix);
+      const uint4 wd = philox4x32_10(make_uint4(0u, (uint32_t)pix, gsub, frame), a.key0, a.key1);
+      const int k = poisson_ptrs(lam, u01(wd.x), u01(wd.y), (uint32_t)pix, gsub, frame, a.key0, a.key1);
+      accumulate(pix, (float)k + a.ron * read_noise_z(wd));
+    }
+  }
+  double* red = reinterpret_cast<double*>(im + RED);
   red[l] = s0;
   red[L + l] = sx;
   red[2 * L + l] = sy;
   __syncthreads();
   if (active && l == 0) {
     double t0 = 0.0, tx = 0.0, ty = 0.0;
+#pragma unroll 4
     for (int j = 0; j < L; ++j) {
       t0 += red[j];
       tx += red[L + j];
       ty += red[2 * L + j];
     }
-    const int64_t fw = item / a.n_valid;
+    const int64_t fw = (int64_t)f * a.n_wfs + w;
     const bool empty = !(t0 > 0.0);
     a.slopes[(fw * 2) * a.n_valid + i] = empty ? 0.0f : (float)(tx / t0);
     a.slopes[(fw * 2 + 1) * a.n_valid + i] = empty ? 0.0f : (float)(ty / t0);
     if (a.flags) a.flags[item] = empty ? 1 : 0;
+  }
+}
+
+// One-shot grid (one group per block) or persistent grid (blocks stride over the groups).
+// The frame number of the first frame comes from a.frame0_dev when set (graph replay).
+template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, int WPE, bool PERSIST, bool SPLIT>
+__global__ __launch_bounds__(SPB * CONV_N) __attribute__((amdgpu_waves_per_eu(WPE))) void wfs_fused_kernel(
+    const WfsLaunch a) {
+  using LY = FusedLayout<NPX, FFT_N, CONV_N, DET_N>;
+  __shared__ __align__(16) float s_re[SPB * LY::PLANE];
+  __shared__ __align__(16) float s_im[SPB * LY::PLANE];
+  const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev : a.frame0;
+  if constexpr (PERSIST) {
+    const int64_t ngroups = (a.total + SPB - 1) / SPB;
+    for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+      wfs_fused_group<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, SPLIT>(a, g, frame_base, s_re, s_im);
+      __syncthreads();
+    }
+  } else {
+    wfs_fused_group<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, SPLIT>(a, blockIdx.x, frame_base, s_re, s_im);
   }
 }
 
@@ -250,14 +427,50 @@ constexpr int items_per_block(int lanes) {
   return spb;
 }
 
-template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS>
-static hipError_t launch_one(const WfsLaunch& a, hipStream_t st) {
-  constexpr int SPB = items_per_block(CONV_N);
-  const int64_t blocks = (a.total + SPB - 1) / SPB;
-  if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL((wfs_fused_kernel<NPX, FFT_N, CONV_N, DET_N, LGS, SPB>), dim3((unsigned)blocks),
-                     dim3(SPB * CONV_N), 0, st, a);
+template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, int WPE, bool PERSIST, bool SPLIT>
+static hipError_t launch_variant(const WfsLaunch& a, hipStream_t st) {
+  auto kern = wfs_fused_kernel<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, WPE, PERSIST, SPLIT>;
+  const int64_t groups = (a.total + SPB - 1) / SPB;
+  if (groups <= 0) return hipSuccess;
+  int64_t blocks = groups;
+  if constexpr (PERSIST) {
+    static int resident = 0;  // blocks resident on the device for this kernel (per process, device 0 shape)
+    if (resident == 0) {
+      int dev = 0, cus = 0, per_cu = 0;
+      hipError_t e = hipGetDevice(&dev);
+      if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, SPB * CONV_N, 0);
+      if (e != hipSuccess) return e;
+      resident = (per_cu > 0 ? per_cu : 1) * cus;
+    }
+    if (blocks > resident) blocks = resident;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(SPB * CONV_N), 0, st, a);
   return hipGetLastError();
+}
+
+// Launch variants of the 40-point shapes: (row transforms whole or split over lane pairs,
+// waves-per-EU target, persistent grid).  Variant 0 is the default.
+constexpr int kTunedVariants = 6;
+
+template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS>
+static hipError_t launch_one(int variant, const WfsLaunch& a, hipStream_t st) {
+  constexpr int SPB = items_per_block(CONV_N);
+  constexpr bool TUNED = (CONV_N == 40 && DET_N == 16);
+  if constexpr (TUNED) {
+    switch (variant) {
+      case 0: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, false>(a, st);
+      case 1: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 4, false, false>(a, st);
+      case 2: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, true>(a, st);
+      case 3: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 4, false, true>(a, st);
+      case 4: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, true, false>(a, st);
+      case 5: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 4, true, false>(a, st);
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    if (variant != 0) return hipErrorInvalidValue;
+    return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, false>(a, st);
+  }
 }
 
 #define SHW_WFS_SHAPES(X)     \
@@ -278,13 +491,27 @@ bool wfs_shape_supported(const WfsShape& s) {
   return false;
 }
 
-hipError_t launch_wfs_fused(const WfsShape& s, const WfsLaunch& a, hipStream_t st) {
+int wfs_variant_count(const WfsShape& s) {
+  if (!wfs_shape_supported(s)) return 0;
+  return (s.conv_n == 40 && s.det_n == 16) ? kTunedVariants : 1;
+}
+
+hipError_t launch_wfs_fused(const WfsShape& s, int variant, const WfsLaunch& a, hipStream_t st) {
 #define X(np, fn, cn, dn, lg) \
   if (s.npx == np && s.fft_n == fn && s.conv_n == cn && s.det_n == dn && (s.lgs != 0) == lg) \
-    return launch_one<np, fn, cn, dn, lg>(a, st);
+    return launch_one<np, fn, cn, dn, lg>(variant, a, st);
   SHW_WFS_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
+}
+
+__global__ void counter_add_kernel(uint64_t* c, uint64_t inc) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) c[0] += inc;
+}
+
+hipError_t launch_counter_add(uint64_t* d_counter, uint64_t inc, hipStream_t st) {
+  hipLaunchKernelGGL(counter_add_kernel, dim3(1), dim3(64), 0, st, d_counter, inc);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- kernel spectra (plan setup)

@@ -59,6 +59,17 @@ _sig = {
                                  _P, _P, _P, _P]),
     "sh_wfs_measure_batch": (C.c_int, [C.POINTER(WorkC), C.c_int32, _P]),
     "shw_wfs_plan_destroy": (C.c_int, [_P]),
+    "shw_wfs_plan_variant_count": (C.c_int, [_P, C.POINTER(C.c_int32)]),
+    "shw_wfs_plan_set_variant": (C.c_int, [_P, C.c_int32]),
+    "shw_wfs_plan_autotune": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int64, C.c_int32, _P, C.c_int32, _P,
+                                        C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+    "sh_wfs_measure_devframe": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_uint64, _P,
+                                          _P, _P, _P, _P]),
+    "shw_counter_add": (C.c_int, [_P, C.c_uint64, _P]),
+    "shw_graph_begin": (C.c_int, [_P]),
+    "shw_graph_end": (C.c_int, [_P, C.POINTER(_P)]),
+    "shw_graph_launch": (C.c_int, [_P, _P]),
+    "shw_graph_destroy": (C.c_int, [_P]),
     "shw_psf_plan_create": (C.c_int, [C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double,
                                       C.POINTER(_P)]),
     "psf_accumulate": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int32, _P, _P, _P]),
@@ -177,6 +188,34 @@ class WfsPlan:
                "shw_wfs_plan_kernel_spectra")
         return out
 
+    @property
+    def n_variants(self):
+        n = C.c_int32(0)
+        _check(_lib.shw_wfs_plan_variant_count(self._h, C.byref(n)), "shw_wfs_plan_variant_count")
+        return n.value
+
+    def set_variant(self, v):
+        _check(_lib.shw_wfs_plan_set_variant(self._h, v), "shw_wfs_plan_set_variant")
+
+    def autotune(self, opd, slopes, reps=20, stream=None):
+        """Time every launch variant on these inputs; select the fastest.  Returns (best, [ms per launch])."""
+        n = self.n_variants
+        ms = (C.c_float * n)()
+        best = C.c_int32(-1)
+        _check(_lib.shw_wfs_plan_autotune(self._h, _ptr(opd), opd.stride(2), opd.stride(1), opd.stride(0),
+                                          opd.shape[0], _ptr(slopes), reps, _stream_ptr(stream), C.byref(best), ms),
+               "shw_wfs_plan_autotune")
+        return best.value, list(ms)
+
+    def measure_devframe(self, opd, slopes, d_frame0, images=None, flags=None, seed=0, stream=None):
+        """As measure, with the first frame number read on the device from the uint64 tensor d_frame0."""
+        if opd.dim() != 4 or opd.stride(3) != 1:
+            raise ValueError("opd must be [frames][wfs][rows][cols] with contiguous rows")
+        _check(_lib.sh_wfs_measure_devframe(self._h, _ptr(opd), opd.stride(2), opd.stride(1), opd.stride(0),
+                                            opd.shape[0], seed, _ptr(d_frame0), _ptr(slopes), _ptr(images),
+                                            _ptr(flags), _stream_ptr(stream)), "sh_wfs_measure_devframe")
+        return slopes
+
     def measure(self, opd, slopes, images=None, flags=None, seed=0, frame0=0, stream=None):
         """opd: float32 device tensor [F][W][N][N] (last dim contiguous); slopes [F][W][2][n_valid]."""
         if opd.dim() != 4 or opd.stride(3) != 1:
@@ -282,3 +321,50 @@ def residual_opd(screen, surfaces, pupil_n, scr_origin, dm_origin, out, stream=N
                                  pupil_n, n_out, so, do, _ptr(out), out.stride(1), out.stride(0),
                                  _stream_ptr(stream)), "shw_residual_opd")
     return out
+
+
+def counter_add(d_counter, inc=1, stream=None):
+    """d_counter (uint64 device tensor, one element) += inc, as a kernel on the stream."""
+    _check(_lib.shw_counter_add(_ptr(d_counter), inc, _stream_ptr(stream)), "shw_counter_add")
+
+
+class Graph:
+    """A captured loop step: library calls issued on `stream` inside `with Graph.capture(stream)`."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @staticmethod
+    def capture(stream):
+        return _Capture(stream)
+
+    def launch(self, stream=None):
+        _check(_lib.shw_graph_launch(self._h, _stream_ptr(stream)), "shw_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.shw_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class _Capture:
+    def __init__(self, stream):
+        self.stream = stream
+        self.graph = None
+
+    def __enter__(self):
+        _check(_lib.shw_graph_begin(_stream_ptr(self.stream)), "shw_graph_begin")
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        h = C.c_void_p()
+        rc = _lib.shw_graph_end(_stream_ptr(self.stream), C.byref(h))
+        if exc_type is None:
+            _check(rc, "shw_graph_end")
+            self.graph = Graph(h)
+        elif rc == OK:
+            _lib.shw_graph_destroy(h)
+        return False

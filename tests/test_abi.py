@@ -51,7 +51,7 @@ def test_supported_workloads_pass_validation(cfg, n_wfs):
 
 @pytest.mark.parametrize("change,code", [
     (dict(pupil_n=81), -1),                 # n_subap does not divide pupil_n
-    (dict(fft_n=12), -1),                   # not a multiple of the sub-aperture size
+    (dict(fft_n=12), -4),                   # not a multiple of the sub-aperture size: no kernel
     (dict(fft_n=4), -1),                    # smaller than the sub-aperture
     (dict(conv_n=17), -1),                  # odd padding
     (dict(det_n=0), -1),

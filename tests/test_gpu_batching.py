@@ -1,0 +1,98 @@
+"""Batching form: launch variants agree bitwise, the autotuner picks one, and a captured
+loop-step graph replayed frame after frame equals eager calls."""
+import numpy as np
+import pytest
+
+from gen import configs as G
+from gen import screens as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _plan(cfg, n_wfs):
+    from paper_1408_0698_amd import shwfs
+    return shwfs.WfsPlan(cfg, n_wfs, G.launch_positions(cfg, n_wfs) if cfg.lgs else None)
+
+
+def test_variants_are_bitwise_identical(torch_dev):
+    cfg = G.CFG1.replace(pupil_n=170, n_subap=17)   # 220 valid: ragged last group
+    plan = _plan(cfg, 3)
+    assert plan.n_variants == 6
+    opd = torch_dev.from_numpy(S.lgs39m_opd(3, 3, pupil_n=170)).cuda()
+    ref = None
+    for v in range(plan.n_variants):
+        plan.set_variant(v)
+        sl = torch_dev.zeros((3, 3, 2, plan.n_valid), device="cuda")
+        im = torch_dev.zeros((3, 3, plan.n_valid, 16, 16), device="cuda")
+        plan.measure(opd, sl, im, seed=7, frame0=40)
+        torch_dev.cuda.synchronize()
+        if ref is None:
+            ref = (sl.clone(), im.clone())
+        else:
+            assert torch_dev.equal(sl, ref[0]) and torch_dev.equal(im, ref[1]), f"variant {v}"
+
+
+def test_persistent_variant_covers_many_groups(torch_dev):
+    """More groups than resident blocks (full 6-LGS frames x 4): persistent equals one-shot."""
+    plan = _plan(G.CFG1, 6)
+    opd = torch_dev.from_numpy(S.lgs39m_opd(4, 6)).cuda()
+    out = []
+    for v in (0, 4, 5):
+        plan.set_variant(v)
+        sl = torch_dev.zeros((4, 6, 2, plan.n_valid), device="cuda")
+        plan.measure(opd, sl, seed=3, frame0=0)
+        torch_dev.cuda.synchronize()
+        out.append(sl)
+    assert torch_dev.equal(out[0], out[1]) and torch_dev.equal(out[0], out[2])
+
+
+def test_autotune_selects_a_variant(torch_dev, tmp_path, monkeypatch):
+    from paper_1408_0698_amd import autotune
+    monkeypatch.setenv("SHW_AUTOTUNE_CACHE", str(tmp_path / "at.json"))
+    plan = _plan(G.CFG1.replace(pupil_n=400, n_subap=40), 6)
+    opd = torch_dev.from_numpy(S.lgs39m_opd(1, 6, pupil_n=400)).cuda()
+    sl = torch_dev.zeros((1, 6, 2, plan.n_valid), device="cuda")
+    rec = autotune.tuned_variant(plan, opd, sl, "gfx950", reps=3)
+    assert 0 <= rec["variant"] < plan.n_variants and len(rec["ms_per_launch"]) == plan.n_variants
+    assert min(rec["ms_per_launch"]) == rec["ms_per_launch"][rec["variant"]]
+    rec2 = autotune.tuned_variant(plan, opd, sl, "gfx950")
+    assert rec2["variant"] == rec["variant"]
+
+
+def test_graph_replay_advances_frames(torch_dev):
+    """Capture [measure with device frame counter, counter += 1]; replay 4 times with eager work
+    and synchronisations in between; replay k equals the eager call for frame base + k."""
+    from paper_1408_0698_amd import shwfs
+    torch = torch_dev
+    cfg = G.CFG0.replace(photons_per_subap=100.0, ron_e=2.0, threshold_e=1.0, flags=1)
+    plan = _plan(cfg, 1)
+    opd = torch.from_numpy(S.ngs8m_opd(1)[:, None].copy()).cuda()
+    counter = torch.tensor([1000], dtype=torch.int64, device="cuda")
+    sl = torch.zeros((1, 1, 2, plan.n_valid), device="cuda")
+    im = torch.zeros((1, 1, plan.n_valid, 8, 8), device="cuda")
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        with shwfs.Graph.capture(stream) as cap:
+            plan.measure_devframe(opd, sl, counter, images=im, seed=11, stream=stream)
+            shwfs.counter_add(counter, 1, stream=stream)
+    g = cap.graph
+    for k in range(4):
+        with torch.cuda.stream(stream):
+            g.launch(stream)
+        stream.synchronize()
+        got = (sl.clone(), im.clone())
+        ref_sl = torch.zeros_like(sl)
+        ref_im = torch.zeros_like(im)
+        plan.measure(opd, ref_sl, ref_im, seed=11, frame0=1000 + k)
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], ref_sl) and torch.equal(got[1], ref_im), f"replay {k}"
+    assert int(counter.item()) == 1004
