@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "internal.h"
+
 namespace shw {
 
 struct BigLaunch {
@@ -19,6 +21,7 @@ struct BigLaunch {
   float ph_scale, ron, thr;
   int32_t noise;
   uint32_t key0, key1, frame0;
+  const FrameWork* list;  // nullable: per-frame buffers and keys
 };
 
 bool big_shape_supported(int npx, int fft_n, int conv_n, int det_n, int lgs);

@@ -113,8 +113,10 @@ __global__ __launch_bounds__(kBlock) void big_rows_kernel(const BigLaunch a, int
   const int sidx = a.valid_idx[i];
   const int sa = sidx / a.n_subap, sb = sidx - (sidx / a.n_subap) * a.n_subap;
   const int prow = sa * a.npx + y;
-  const float* src = a.opd + (int64_t)f * a.frame_stride + (int64_t)w * a.wfs_stride + (int64_t)prow * a.row_pitch +
-                     (int64_t)sb * a.npx;
+  const float* src = a.list ? a.list[f].opd + (int64_t)w * a.list[f].wfs_stride + (int64_t)prow * a.list[f].row_pitch
+                            : a.opd + (int64_t)f * a.frame_stride + (int64_t)w * a.wfs_stride +
+                                  (int64_t)prow * a.row_pitch;
+  src += (int64_t)sb * a.npx;
   const float ay = (float)prow + 0.5f - a.half_n;
   float2 v[8];
 #pragma unroll
@@ -199,7 +201,17 @@ __global__ __launch_bounds__(256) void big_detect_kernel(const BigLaunch a, int6
   const int b = kN / a.det_n;
   const float cd = 0.5f * (float)(a.det_n - 1);
   const uint32_t gsub = (uint32_t)(w * a.n_valid + i);
-  const uint32_t frame = a.frame0 + (uint32_t)f;
+  uint32_t frame = a.frame0 + (uint32_t)f, key0 = a.key0, key1 = a.key1;
+  float* slopes_fw = a.slopes + ((int64_t)f * a.n_wfs + w) * 2 * a.n_valid;
+  float* images_it = a.images ? a.images + item * (int64_t)(a.det_n * a.det_n) : nullptr;
+  if (a.list) {
+    const FrameWork& fw = a.list[f];
+    frame = (uint32_t)fw.frame;
+    key0 = (uint32_t)(fw.seed & 0xFFFFFFFFu);
+    key1 = (uint32_t)(fw.seed >> 32);
+    slopes_fw = fw.slopes + (int64_t)w * 2 * a.n_valid;
+    images_it = fw.images ? fw.images + ((int64_t)w * a.n_valid + i) * (a.det_n * a.det_n) : nullptr;
+  }
   double s0 = 0.0, sx = 0.0, sy = 0.0;
   for (int pix = threadIdx.x; pix < npix; pix += 256) {
     const int p = pix / a.det_n, q = pix - p * a.det_n;
@@ -209,9 +221,9 @@ __global__ __launch_bounds__(256) void big_detect_kernel(const BigLaunch a, int6
     float img = det;
     if (a.ph_scale > 0.0f) {
       const float lam = a.ph_scale * det;
-      img = a.noise ? noisy_pixel(lam, a.ron, (uint32_t)pix, gsub, frame, a.key0, a.key1) : lam;
+      img = a.noise ? noisy_pixel(lam, a.ron, (uint32_t)pix, gsub, frame, key0, key1) : lam;
     }
-    if (a.images) a.images[item * npix + pix] = img;
+    if (images_it) images_it[pix] = img;
     const double t = (double)fmaxf(img - a.thr, 0.0f);
     s0 += t;
     sx += (double)((float)q - cd) * t;
@@ -227,12 +239,11 @@ __global__ __launch_bounds__(256) void big_detect_kernel(const BigLaunch a, int6
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const int64_t fw = item / a.n_valid;
     const double t0 = red[0][0];
     const bool empty = !(t0 > 0.0);
-    a.slopes[(fw * 2) * a.n_valid + i] = empty ? 0.0f : (float)(red[1][0] / t0);
-    a.slopes[(fw * 2 + 1) * a.n_valid + i] = empty ? 0.0f : (float)(red[2][0] / t0);
-    if (a.flags) a.flags[item] = empty ? 1 : 0;
+    slopes_fw[i] = empty ? 0.0f : (float)(red[1][0] / t0);
+    slopes_fw[a.n_valid + i] = empty ? 0.0f : (float)(red[2][0] / t0);
+    if (a.flags && !a.list) a.flags[item] = empty ? 1 : 0;
   }
 }
 

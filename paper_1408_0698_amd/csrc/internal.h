@@ -6,6 +6,15 @@
 
 namespace shw {
 
+// One frame of a work list: its own buffers and noise key (device array of these).
+struct FrameWork {
+  const float* opd;
+  int64_t row_pitch, wfs_stride;
+  float* slopes;   // [n_wfs][2][n_valid]
+  float* images;   // nullable [n_wfs][n_valid][det][det]
+  uint64_t seed, frame;
+};
+
 // Arguments of one fused Shack-Hartmann launch (all work items share a plan geometry).
 struct WfsLaunch {
   const float* opd;          // OPD metres
@@ -25,6 +34,7 @@ struct WfsLaunch {
   int32_t noise;
   uint32_t key0, key1, frame0;
   const uint64_t* frame0_dev;  // nullable: frame number of the first frame, read on the device
+  const FrameWork* list;       // nullable: frame f takes buffers, strides and key from list[f]
 };
 
 // Shape of a compiled fused kernel.

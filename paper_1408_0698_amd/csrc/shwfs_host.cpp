@@ -62,6 +62,8 @@ struct shw_wfs_plan {
   size_t bytes = 0;
   std::vector<int32_t> valid;
   int32_t variant = 0;
+  FrameWork* d_list = nullptr;   // work list of sh_wfs_measure_batch
+  int32_t list_cap = 0;
   // large sub-apertures (FFT 512): row/column workspace for chunk_items work items
   bool big = false;
   int64_t chunk_items = 0;
@@ -206,6 +208,7 @@ extern "C" int shw_wfs_plan_destroy(shw_wfs_plan* p) {
   if (p->d_valid) (void)hipFree(p->d_valid);
   if (p->d_khat) (void)hipFree(p->d_khat);
   if (p->d_T) (void)hipFree(p->d_T);
+  if (p->d_list) (void)hipFree(p->d_list);
   if (p->d_Jr) (void)hipFree(p->d_Jr);
   if (cur != p->device) (void)hipSetDevice(cur);
   delete p;
@@ -321,6 +324,42 @@ static WfsLaunch base_launch(const shw_wfs_plan* p) {
   return a;
 }
 
+// Large-sub-aperture passes for the items of a (chunks of the plan's workspace).
+static int launch_big_list(shw_wfs_plan* p, const WfsLaunch& a, void* stream) {
+  BigLaunch b{};
+  b.opd = a.opd;
+  b.row_pitch = a.row_pitch;
+  b.wfs_stride = a.wfs_stride;
+  b.frame_stride = a.frame_stride;
+  b.valid_idx = a.valid_idx;
+  b.slopes = a.slopes;
+  b.images = a.images;
+  b.flags = a.flags;
+  b.n_valid = a.n_valid;
+  b.n_wfs = a.n_wfs;
+  b.n_subap = a.n_subap;
+  b.npx = p->npx;
+  b.det_n = p->cfg.det_n;
+  b.inv_lambda = a.inv_lambda;
+  b.r2_outer = a.r2_outer;
+  b.r2_inner = a.r2_inner;
+  b.half_n = a.half_n;
+  b.ph_scale = a.ph_scale;
+  b.ron = a.ron;
+  b.thr = a.thr;
+  b.noise = a.noise;
+  b.key0 = a.key0;
+  b.key1 = a.key1;
+  b.frame0 = a.frame0;
+  b.list = a.list;
+  for (int64_t i0 = 0; i0 < a.total; i0 += p->chunk_items) {
+    const int64_t n = a.total - i0 < p->chunk_items ? a.total - i0 : p->chunk_items;
+    hipError_t e = launch_big(b, i0, n, p->d_T, p->d_Jr, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "large sub-aperture launch");
+  }
+  return ok();
+}
+
 static int measure_impl(shw_wfs_plan* p, const float* d_opd_m, int64_t row_pitch, int64_t wfs_stride,
                         int64_t frame_stride, int32_t n_frames, uint64_t seed, uint64_t frame0,
                         const uint64_t* d_frame0, float* d_slopes, float* d_images, uint8_t* d_flags, void* stream) {
@@ -345,39 +384,7 @@ static int measure_impl(shw_wfs_plan* p, const float* d_opd_m, int64_t row_pitch
   a.key1 = (uint32_t)(seed >> 32);
   a.frame0 = (uint32_t)frame0;
   a.frame0_dev = d_frame0;
-  if (p->big) {
-    BigLaunch b{};
-    b.opd = a.opd;
-    b.row_pitch = a.row_pitch;
-    b.wfs_stride = a.wfs_stride;
-    b.frame_stride = a.frame_stride;
-    b.valid_idx = a.valid_idx;
-    b.slopes = a.slopes;
-    b.images = a.images;
-    b.flags = a.flags;
-    b.n_valid = a.n_valid;
-    b.n_wfs = a.n_wfs;
-    b.n_subap = a.n_subap;
-    b.npx = p->npx;
-    b.det_n = p->cfg.det_n;
-    b.inv_lambda = a.inv_lambda;
-    b.r2_outer = a.r2_outer;
-    b.r2_inner = a.r2_inner;
-    b.half_n = a.half_n;
-    b.ph_scale = a.ph_scale;
-    b.ron = a.ron;
-    b.thr = a.thr;
-    b.noise = a.noise;
-    b.key0 = a.key0;
-    b.key1 = a.key1;
-    b.frame0 = a.frame0;
-    for (int64_t i0 = 0; i0 < a.total; i0 += p->chunk_items) {
-      const int64_t n = a.total - i0 < p->chunk_items ? a.total - i0 : p->chunk_items;
-      hipError_t e = launch_big(b, i0, n, p->d_T, p->d_Jr, (hipStream_t)stream);
-      if (e != hipSuccess) return hip_fail(e, "sh_wfs_measure launch");
-    }
-    return ok();
-  }
+  if (p->big) return launch_big_list(p, a, stream);
   hipError_t e = launch_wfs_fused(p->shape, p->variant, a, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "sh_wfs_measure launch");
   return ok();
@@ -393,11 +400,43 @@ extern "C" int sh_wfs_measure_batch(const shw_work* items, int32_t n, void* stre
     if (w.row_pitch < w.plan->cfg.pupil_n || w.wfs_stride < 0) return fail(SHW_E_INVALID, "item %d stride", k);
     if (w.frame >= (1ull << 32)) return fail(SHW_E_INVALID, "item %d frame exceeds 2^32", k);
   }
+  // one launch per distinct plan, over a device work list of that plan's frames
+  std::vector<shw_wfs_plan*> plans;
   for (int32_t k = 0; k < n; ++k) {
-    const shw_work& w = items[k];
-    const int r = sh_wfs_measure(w.plan, w.d_opd_m, w.row_pitch, w.wfs_stride, 0, 1, w.seed, w.frame, w.d_slopes,
-                                 w.d_images, nullptr, stream);
-    if (r != SHW_OK) return r;
+    bool seen = false;
+    for (auto* q : plans) seen = seen || q == items[k].plan;
+    if (!seen) plans.push_back(items[k].plan);
+  }
+  for (auto* p : plans) {
+    std::vector<FrameWork> list;
+    for (int32_t k = 0; k < n; ++k) {
+      if (items[k].plan != p) continue;
+      const shw_work& w = items[k];
+      list.push_back(FrameWork{w.d_opd_m, w.row_pitch, w.wfs_stride, w.d_slopes, w.d_images, w.seed, w.frame});
+    }
+    const int32_t nf = (int32_t)list.size();
+    if (nf > p->list_cap) {
+      if (p->d_list) (void)hipFree(p->d_list);
+      p->d_list = nullptr;
+      p->list_cap = 0;
+      const int32_t cap = nf < 256 ? 256 : nf;
+      hipError_t e = hipMalloc(&p->d_list, sizeof(FrameWork) * cap);
+      if (e != hipSuccess) return hip_fail(e, "work list");
+      p->list_cap = cap;
+    }
+    hipError_t e = hipMemcpyAsync(p->d_list, list.data(), sizeof(FrameWork) * nf, hipMemcpyHostToDevice,
+                                  (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "work list upload");
+    WfsLaunch a = base_launch(p);
+    a.list = p->d_list;
+    a.total = (int64_t)nf * p->n_wfs * p->n_valid;
+    if (p->big) {
+      const int rc = launch_big_list(p, a, stream);
+      if (rc != SHW_OK) return rc;
+    } else {
+      e = launch_wfs_fused(p->shape, p->variant, a, (hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, "sh_wfs_measure_batch launch");
+    }
   }
   return ok();
 }

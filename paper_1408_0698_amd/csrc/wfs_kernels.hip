@@ -100,14 +100,37 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   const int sb = sidx - sa * a.n_subap;
   float* re = s_re + s * PLANE;
   float* im = s_im + s * PLANE;
+  // per-frame buffers and noise key: from the work list, or the launch-wide layout
+  const float* opd_f;
+  int64_t row_pitch, wfs_stride;
+  float* slopes_fw;   // this frame and sensor: [2][n_valid]
+  float* images_it;   // this item: [det][det] or null
+  uint32_t key0 = a.key0, key1 = a.key1;
+  uint32_t frame = frame_base + (uint32_t)f;
+  if (a.list) {
+    const FrameWork& fw = a.list[f];
+    opd_f = fw.opd;
+    row_pitch = fw.row_pitch;
+    wfs_stride = fw.wfs_stride;
+    slopes_fw = fw.slopes + (int64_t)w * 2 * a.n_valid;
+    images_it = fw.images ? fw.images + ((int64_t)w * a.n_valid + i) * (DET_N * DET_N) : nullptr;
+    key0 = (uint32_t)(fw.seed & 0xFFFFFFFFu);
+    key1 = (uint32_t)(fw.seed >> 32);
+    frame = (uint32_t)fw.frame;
+  } else {
+    opd_f = a.opd + (int64_t)f * a.frame_stride;
+    row_pitch = a.row_pitch;
+    wfs_stride = a.wfs_stride;
+    slopes_fw = a.slopes + ((int64_t)f * a.n_wfs + w) * 2 * a.n_valid;
+    images_it = a.images ? a.images + it * (DET_N * DET_N) : nullptr;
+  }
 
   // ---------------------------------------------------------------- A: row pass
   if (active && l < FFT_N) {
     const int y = l / R;
     const int k2 = l - y * R;
     const int prow = sa * NPX + y;
-    const float* src = a.opd + (int64_t)f * a.frame_stride + (int64_t)w * a.wfs_stride +
-                       (int64_t)prow * a.row_pitch + (int64_t)sb * NPX;
+    const float* src = opd_f + (int64_t)w * wfs_stride + (int64_t)prow * row_pitch + (int64_t)sb * NPX;
     const float ay = (float)prow + 0.5f - a.half_n;
     const float ay2 = ay * ay;
     float2 z[NPX];
@@ -321,7 +344,6 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   constexpr float CD = 0.5f * (float)(DET_N - 1);
   double s0 = 0.0, sx = 0.0, sy = 0.0;
   const uint32_t gsub = (uint32_t)(w * a.n_valid + i);
-  const uint32_t frame = frame_base + (uint32_t)f;
   auto detector_pixel = [&](int pix) {
     const int p = pix / DET_N;
     const int q = pix - p * DET_N;
@@ -338,7 +360,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   auto accumulate = [&](int pix, float img) {
     const int p = pix / DET_N;
     const int q = pix - p * DET_N;
-    if (a.images) a.images[item * NPIX + pix] = img;
+    if (images_it) images_it[pix] = img;
     const double t = (double)fmaxf(img - a.thr, 0.0f);
     s0 += t;
     sx += (double)((float)q - CD) * t;
@@ -359,7 +381,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
             queue[atomicAdd(&queue[QCOUNT], 1)] = pix;
             continue;
           }
-          const uint4 wd = philox4x32_10(make_uint4(0u, (uint32_t)pix, gsub, frame), a.key0, a.key1);
+          const uint4 wd = philox4x32_10(make_uint4(0u, (uint32_t)pix, gsub, frame), key0, key1);
           const int k = lam > 0.0f ? poisson_inversion(lam, u01(wd.x)) : 0;
           img = (float)k + a.ron * read_noise_z(wd);
         }
@@ -374,8 +396,8 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
     for (int e = l; e < nq; e += L) {
       const int pix = queue[e];
       const float lam = a.ph_scale * detector_pixel(pix);
-      const uint4 wd = philox4x32_10(make_uint4(0u, (uint32_t)pix, gsub, frame), a.key0, a.key1);
-      const int k = poisson_ptrs(lam, u01(wd.x), u01(wd.y), (uint32_t)pix, gsub, frame, a.key0, a.key1);
+      const uint4 wd = philox4x32_10(make_uint4(0u, (uint32_t)pix, gsub, frame), key0, key1);
+      const int k = poisson_ptrs(lam, u01(wd.x), u01(wd.y), (uint32_t)pix, gsub, frame, key0, key1);
       accumulate(pix, (float)k + a.ron * read_noise_z(wd));
     }
   }
@@ -392,11 +414,10 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       tx += red[L + j];
       ty += red[2 * L + j];
     }
-    const int64_t fw = (int64_t)f * a.n_wfs + w;
     const bool empty = !(t0 > 0.0);
-    a.slopes[(fw * 2) * a.n_valid + i] = empty ? 0.0f : (float)(tx / t0);
-    a.slopes[(fw * 2 + 1) * a.n_valid + i] = empty ? 0.0f : (float)(ty / t0);
-    if (a.flags) a.flags[item] = empty ? 1 : 0;
+    slopes_fw[i] = empty ? 0.0f : (float)(tx / t0);
+    slopes_fw[a.n_valid + i] = empty ? 0.0f : (float)(ty / t0);
+    if (a.flags && !a.list) a.flags[item] = empty ? 1 : 0;
   }
 }
 
