@@ -10,6 +10,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -17,6 +19,7 @@
 #include "psf_internal.h"
 #include "dm_internal.h"
 #include "big_internal.h"
+#include "mfma_internal.h"
 
 using namespace shw;
 
@@ -62,6 +65,8 @@ struct shw_wfs_plan {
   size_t bytes = 0;
   std::vector<int32_t> valid;
   int32_t variant = 0;
+  int32_t prec = 0;              // SHW_PREC_*: 0 = FP32 register FFTs, else MFMA DFT GEMMs
+  uint2* d_mfma_tab = nullptr;   // constant matrices of the MFMA variant
   FrameWork* d_list = nullptr;   // work list of sh_wfs_measure_batch
   int32_t list_cap = 0;
   // large sub-apertures (FFT 512): row/column workspace for chunk_items work items
@@ -119,7 +124,11 @@ static int check_config(const shw_wfs_config* c, int32_t n_wfs, const shw_lgs_ge
       if (!is_fin(geom[w].launch_x_m) || !is_fin(geom[w].launch_y_m))
         return fail(SHW_E_INVALID, "launch position %d not finite", w);
   }
-  if (prec != SHW_PREC_FP32) return fail(SHW_E_UNSUPPORTED, "precision %u has no kernel for this shape", prec);
+  if (prec != SHW_PREC_FP32) {
+    if (!mfma_shape_supported(npx, c->fft_n, c->conv_n, c->det_n, (int)prec))
+      return fail(SHW_E_UNSUPPORTED, "precision %u has no kernel for this shape", prec);
+    return SHW_OK;
+  }
   const WfsShape shape{npx, c->fft_n, c->conv_n, c->det_n, c->lgs};
   if (!wfs_shape_supported(shape) && !big_shape_supported(npx, c->fft_n, c->conv_n, c->det_n, c->lgs))
     return fail(SHW_E_UNSUPPORTED, "no kernel for npx %d, fft_n %d, conv_n %d, det_n %d, lgs %d", npx, c->fft_n,
@@ -198,6 +207,81 @@ static void elongation(const shw_wfs_config* c, const shw_lgs_geom& g, int32_t s
   out[2] = std::atan2(dy, dx);
 }
 
+// ---------------------------------------------------------------- MFMA constant tables
+
+static uint16_t bf16_rne(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+static float bf16_to_float(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// hi/lo halves of v for the precision: bf16 hi + bf16 residual, or fp16 hi + fp16 of 2^11 x residual.
+static void split_const(double v, int prec, uint16_t* hi, uint16_t* lo) {
+  if (prec == SHW_PREC_FP16X3) {
+    // no subnormal high part: below the fp16 normal range the scaled low part carries the value
+    const _Float16 h = std::fabs(v) < 6.103515625e-05 ? (_Float16)0.0 : (_Float16)v;
+    const _Float16 l = (_Float16)((v - (double)h) * 2048.0);
+    std::memcpy(hi, &h, 2);
+    std::memcpy(lo, &l, 2);
+  } else {
+    const uint16_t h = bf16_rne((float)v);
+    *hi = h;
+    *lo = bf16_rne((float)(v - (double)bf16_to_float(h)));
+  }
+}
+
+static std::vector<uint16_t> mfma_tables(const shw_wfs_config* c, int prec) {
+  const double pi = 3.14159265358979323846;
+  const int N = 40, n = 10;
+  const double cc = (N - 1) / 2.0;
+  auto Wm = [&](int comp, int x, int u) -> double {  // W^T[x][u]
+    if (x >= n || u >= N) return 0.0;
+    const double th = 2.0 * pi * (u - cc) * x / N;
+    return comp == 0 ? std::cos(th) : (comp == 1 ? -std::sin(th) : std::sin(th));
+  };
+  auto Gm = [&](int comp, int k, int v) -> double {
+    if (k >= N || v >= N) return 0.0;
+    const double th = 2.0 * pi * (double)((k * v) % N) / N;
+    return comp == 0 ? std::cos(th) : (comp == 1 ? std::sin(th) : -std::sin(th));
+  };
+  const double b = (double)c->conv_n / c->det_n;
+  auto Wb = [&](int k, int p) -> double {  // Wb^T[k][p]
+    if (k >= N || p >= c->det_n) return 0.0;
+    const double lo = std::max((double)k, b * p), hi = std::min((double)(k + 1), b * (p + 1));
+    return hi > lo ? hi - lo : 0.0;
+  };
+  std::vector<uint16_t> t((size_t)kMfmaTableTiles * 64 * 8, 0);
+  auto put = [&](int tile, int lane, int r, double v) {
+    uint16_t h, l;
+    split_const(v, prec, &h, &l);
+    t[((size_t)tile * 64 + lane) * 8 + r] = h;
+    t[((size_t)tile * 64 + lane) * 8 + 4 + r] = l;
+  };
+  for (int lane = 0; lane < 64; ++lane)
+    for (int r = 0; r < 4; ++r) {
+      const int kr = 4 * (lane / 16) + r, nc = lane % 16;
+      for (int tc = 0; tc < 3; ++tc) {
+        put(kTabWr + tc, lane, r, Wm(0, kr, 16 * tc + nc));
+        put(kTabWi + tc, lane, r, Wm(1, kr, 16 * tc + nc));
+        put(kTabWiNeg + tc, lane, r, Wm(2, kr, 16 * tc + nc));
+      }
+      for (int tb = 0; tb < 3; ++tb)
+        for (int tc = 0; tc < 3; ++tc) {
+          put(kTabC + tb * 3 + tc, lane, r, Gm(0, 16 * tb + kr, 16 * tc + nc));
+          put(kTabS + tb * 3 + tc, lane, r, Gm(1, 16 * tb + kr, 16 * tc + nc));
+          put(kTabSNeg + tb * 3 + tc, lane, r, Gm(2, 16 * tb + kr, 16 * tc + nc));
+        }
+      for (int tb = 0; tb < 3; ++tb) put(kTabWb + tb, lane, r, Wb(16 * tb + kr, nc));
+    }
+  return t;
+}
+
 // ---------------------------------------------------------------- plan
 
 extern "C" int shw_wfs_plan_destroy(shw_wfs_plan* p) {
@@ -209,6 +293,7 @@ extern "C" int shw_wfs_plan_destroy(shw_wfs_plan* p) {
   if (p->d_khat) (void)hipFree(p->d_khat);
   if (p->d_T) (void)hipFree(p->d_T);
   if (p->d_list) (void)hipFree(p->d_list);
+  if (p->d_mfma_tab) (void)hipFree(p->d_mfma_tab);
   if (p->d_Jr) (void)hipFree(p->d_Jr);
   if (cur != p->device) (void)hipSetDevice(cur);
   delete p;
@@ -246,7 +331,18 @@ extern "C" int shw_wfs_plan_create(const shw_wfs_config* cfg, int32_t n_wfs, con
     return hip_fail(e, "plan tables");
   }
   p->bytes = sizeof(int32_t) * p->n_valid;
-  p->big = !wfs_shape_supported(p->shape);
+  p->prec = (int32_t)((cfg->flags >> SHW_PRECISION_SHIFT) & 0xFu);
+  if (p->prec != SHW_PREC_FP32) {
+    const std::vector<uint16_t> t = mfma_tables(cfg, p->prec);
+    e = hipMalloc(&p->d_mfma_tab, t.size() * sizeof(uint16_t));
+    if (e == hipSuccess) e = hipMemcpy(p->d_mfma_tab, t.data(), t.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      shw_wfs_plan_destroy(p);
+      return hip_fail(e, "MFMA tables");
+    }
+    p->bytes += t.size() * sizeof(uint16_t);
+  }
+  p->big = p->prec == SHW_PREC_FP32 && !wfs_shape_supported(p->shape);
   if (p->big) {
     // about 128 MB of row intermediates per chunk, at least one sensor frame
     const int64_t per_item = (int64_t)p->npx * cfg->fft_n * (int64_t)sizeof(float2);
@@ -385,6 +481,12 @@ static int measure_impl(shw_wfs_plan* p, const float* d_opd_m, int64_t row_pitch
   a.frame0 = (uint32_t)frame0;
   a.frame0_dev = d_frame0;
   if (p->big) return launch_big_list(p, a, stream);
+  if (p->prec != SHW_PREC_FP32) {
+    if (d_frame0) return fail(SHW_E_UNSUPPORTED, "device frame counter not available for MFMA plans");
+    hipError_t e = launch_wfs_mfma(p->prec, p->cfg.lgs != 0, a, p->d_mfma_tab, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "sh_wfs_measure launch");
+    return ok();
+  }
   hipError_t e = launch_wfs_fused(p->shape, p->variant, a, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "sh_wfs_measure launch");
   return ok();
@@ -417,6 +519,7 @@ extern "C" int sh_wfs_measure_batch(const shw_work* items, int32_t n, void* stre
     const int32_t nf = (int32_t)list.size();
     if (nf > p->list_cap) {
       if (p->d_list) (void)hipFree(p->d_list);
+  if (p->d_mfma_tab) (void)hipFree(p->d_mfma_tab);
       p->d_list = nullptr;
       p->list_cap = 0;
       const int32_t cap = nf < 256 ? 256 : nf;
@@ -427,6 +530,7 @@ extern "C" int sh_wfs_measure_batch(const shw_work* items, int32_t n, void* stre
     hipError_t e = hipMemcpyAsync(p->d_list, list.data(), sizeof(FrameWork) * nf, hipMemcpyHostToDevice,
                                   (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "work list upload");
+    if (p->prec != SHW_PREC_FP32) return fail(SHW_E_UNSUPPORTED, "work lists need an FP32 plan");
     WfsLaunch a = base_launch(p);
     a.list = p->d_list;
     a.total = (int64_t)nf * p->n_wfs * p->n_valid;

@@ -43,6 +43,14 @@ constexpr float rebin_weight(int CN, int DN, int p, int k) {
   return hi > lo ? (float)(hi - lo) : 0.0f;
 }
 
+// Detector pixels per lane in the final stage: the smallest divisor QB of det_n such that
+// det_n^2 / QB pixels fit on the item's lanes and conv_n QB / det_n is an integer.
+constexpr int det_block(int conv_n, int det_n, int lanes) {
+  for (int qb = 1; qb <= det_n; ++qb)
+    if (det_n % qb == 0 && det_n * (det_n / qb) <= lanes && (conv_n * qb) % det_n == 0) return qb;
+  return det_n;
+}
+
 // Value of the same register in the partner lane t ^ 1 (DPP quad permutation 1, 0, 3, 2).
 __device__ __forceinline__ float pair_swap(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0xB1, 0xF, 0xF, false));
@@ -57,7 +65,8 @@ struct FusedLayout {
   static constexpr int ROWS0 = NPX > HN + 1 ? NPX : HN + 1;
   static constexpr int ROWS = ROWS0 > DET_N ? ROWS0 : DET_N;
   static constexpr int NPIX = DET_N * DET_N;
-  static constexpr int RED = (NPIX + 2 + 1) & ~1;
+  static constexpr int DETA = NPIX + 1;                 // detector values, after the queue and its count
+  static constexpr int RED = (DETA + NPIX + 1) & ~1;
   static constexpr int PLANE0 = ROWS * ST > RED + 6 * CONV_N ? ROWS * ST : RED + 6 * CONV_N;
   static constexpr int PLANE = (PLANE0 + 1) & ~1;
 };
@@ -77,11 +86,11 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   constexpr int NPIX = LY::NPIX;
   // stage D reuses the imaginary plane: a queue of NPIX pixel indices, its count, then 3 L doubles
   constexpr int QCOUNT = NPIX;
+  constexpr int DETA = LY::DETA;
   constexpr int RED = LY::RED;
   constexpr int PLANE = LY::PLANE;  // even: doubles stay 8-byte aligned
   constexpr int OFF = (CONV_N - FFT_N) / 2;  // spot offset in the convolution grid
   constexpr float INV_N2 = 1.0f / (float)(FFT_N * FFT_N);
-  constexpr int PIX_ITERS = (NPIX + L - 1) / L;
   static_assert(FFT_N % NPX == 0 && CONV_N >= FFT_N && (CONV_N - FFT_N) % 2 == 0, "shape");
 
   const int tid = threadIdx.x;
@@ -143,9 +152,9 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       const double ramp = (double)((FFT_N - 1) * (x + y)) / (2.0 * FFT_N) - (double)(x * k2) / (double)FFT_N;
       double wv = (double)src[x] * a.inv_lambda + ramp;
       wv -= floor(wv);
-      float sn, cs;
-      sincospif(2.0f * (float)wv, &sn, &cs);
-      z[x] = lit ? make_float2(cs, sn) : make_float2(0.0f, 0.0f);
+      // hardware sine/cosine take the argument in revolutions: exp(2 pi i wv) after the FP64 reduction
+      const float fw = (float)wv;
+      z[x] = lit ? make_float2(__builtin_amdgcn_cosf(fw), __builtin_amdgcn_sinf(fw)) : make_float2(0.0f, 0.0f);
     }
     RegFFT<NPX, -1>::run(z);
 #pragma unroll
@@ -338,25 +347,18 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   __syncthreads();
 
   // ---------------------------------------------------------------- D: photometry, noise, centroid
+  // Lane l takes detector row p = l / G and the QB consecutive pixels q0 .. q0 + QB - 1,
+  // q0 = QB (l % G); b QB is an integer, so the row rebin of the block reads the KB = b QB
+  // inputs from k0 = b q0 with weights known at compile time.
   // Pass 1 handles every pixel except noisy ones with mean >= 10, which are queued in LDS;
   // pass 2 runs the rejection sampler on the queue with the item's lanes side by side.
-  constexpr float B = (float)CONV_N / (float)DET_N;
+  constexpr int QB = det_block(CONV_N, DET_N, L);
+  constexpr int G = DET_N / QB;
+  constexpr int KB = CONV_N * QB / DET_N;
   constexpr float CD = 0.5f * (float)(DET_N - 1);
+  static_assert(DET_N * G <= L && (CONV_N * QB) % DET_N == 0, "detector blocking");
   double s0 = 0.0, sx = 0.0, sy = 0.0;
   const uint32_t gsub = (uint32_t)(w * a.n_valid + i);
-  auto detector_pixel = [&](int pix) {
-    const int p = pix / DET_N;
-    const int q = pix - p * DET_N;
-    const float lo = B * (float)q, hi = B * (float)(q + 1);
-    const int kb = (int)floorf(lo);
-    const int ke = min((int)ceilf(hi), CONV_N);
-    float det = 0.0f;
-    for (int k = kb; k < ke; ++k) {
-      const float wgt = fminf((float)(k + 1), hi) - fmaxf((float)k, lo);
-      if (wgt > 0.0f) det += wgt * re[p * ST + k];
-    }
-    return det;
-  };
   auto accumulate = [&](int pix, float img) {
     const int p = pix / DET_N;
     const int q = pix - p * DET_N;
@@ -366,12 +368,28 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
     sx += (double)((float)q - CD) * t;
     sy += (double)((float)p - CD) * t;
   };
-  if (active) {
+  float* det_area = im + DETA;
+  if (active && l < DET_N * G) {
+    const int p = l / G;
+    const int q0 = QB * (l - p * G);
+    const float* row = re + p * ST + (q0 / QB) * KB;
+    float in[KB];
+#pragma unroll
+    for (int t = 0; t < KB; ++t) in[t] = row[t];
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+      float det = 0.0f;
+#pragma unroll
+      for (int t = 0; t < KB; ++t) {
+        const float wgt = rebin_weight(CONV_N, DET_N, j, t);
+        if (wgt != 0.0f) det += wgt * in[t];
+      }
+      det_area[p * DET_N + q0 + j] = det;
+    }
 #pragma unroll 1
-    for (int j = 0; j < PIX_ITERS; ++j) {
-      const int pix = l + L * j;
-      if (pix >= NPIX) break;
-      const float det = detector_pixel(pix);
+    for (int j = 0; j < QB; ++j) {
+      const int pix = p * DET_N + q0 + j;
+      const float det = det_area[pix];
       float img = det;
       if (a.ph_scale > 0.0f) {
         const float lam = a.ph_scale * det;
@@ -395,7 +413,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
 #pragma unroll 1
     for (int e = l; e < nq; e += L) {
       const int pix = queue[e];
-      const float lam = a.ph_scale * detector_pixel(pix);
+      const float lam = a.ph_scale * det_area[pix];
       const uint4 wd = philox4x32_10(make_uint4(0u, (uint32_t)pix, gsub, frame), key0, key1);
       const int k = poisson_ptrs(lam, u01(wd.x), u01(wd.y), (uint32_t)pix, gsub, frame, key0, key1);
       accumulate(pix, (float)k + a.ron * read_noise_z(wd));
@@ -500,7 +518,6 @@ static hipError_t launch_one(int variant, const WfsLaunch& a, hipStream_t st) {
   X(8, 16, 16, 16, false)     \
   X(10, 40, 40, 16, true)     \
   X(10, 40, 40, 16, false)    \
-  X(10, 40, 40, 40, false)    \
   X(10, 20, 40, 16, true)     \
   X(10, 20, 20, 10, false)
 

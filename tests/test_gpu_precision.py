@@ -1,0 +1,99 @@
+"""Precision form: the 39 m LGS sensor with its transforms as MFMA DFT-matrix GEMMs.
+
+Reports, for every variant, max and RMS errors of detector images and slopes
+against the FP64 oracle (noise off); the split-precision variants must meet
+the parity bar (1e-4 image, 1e-3 px), plain bf16 is reported only.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gen import configs as G
+from gen import screens as S
+from oracle import wfs as OW
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = {"bf16": G.PREC_BF16, "bf16x3": G.PREC_BF16X3, "fp16x3": G.PREC_FP16X3}
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def reference():
+    cfg = G.CFG1.replace(pupil_n=170, n_subap=17, flags=0)
+    launch = G.launch_positions(cfg, 6)
+    opd = S.lgs39m_opd(2, 6, pupil_n=170)
+    return cfg, launch, opd, OW.Sensor(cfg, 6, launch).measure(opd)
+
+
+def _run(torch, cfg, launch, opd, n_wfs=6):
+    from paper_1408_0698_amd import shwfs
+    plan = shwfs.WfsPlan(cfg, n_wfs, launch)
+    d = torch.from_numpy(opd).cuda()
+    sl = torch.full((opd.shape[0], n_wfs, 2, plan.n_valid), float("nan"), device="cuda")
+    im = torch.full((opd.shape[0], n_wfs, plan.n_valid, cfg.det_n, cfg.det_n), float("nan"), device="cuda")
+    plan.measure(d, sl, im)
+    torch.cuda.synchronize()
+    return sl.cpu().numpy().astype(np.float64), im.cpu().numpy().astype(np.float64)
+
+
+def _errors(sl, im, want):
+    scale = np.abs(want["images"]).max(axis=(-1, -2), keepdims=True)
+    rel = np.abs(im - want["images"]) / scale
+    ds = np.abs(sl - want["slopes"])
+    return {"image_max": float(rel.max()), "image_rms": float(np.sqrt((rel ** 2).mean())),
+            "slope_max_px": float(ds.max()), "slope_rms_px": float(np.sqrt((ds ** 2).mean()))}
+
+
+def test_precision_variants_against_oracle(torch_dev, reference):
+    cfg, launch, opd, want = reference
+    report = {}
+    sl, im = _run(torch_dev, cfg, launch, opd)
+    report["fp32_fft"] = _errors(sl, im, want)
+    for name, prec in VARIANTS.items():
+        c = cfg.replace(flags=prec << 4)
+        sl, im = _run(torch_dev, c, launch, opd)
+        assert np.isfinite(sl).all() and np.isfinite(im).all(), name
+        report[name] = _errors(sl, im, want)
+    print("precision report:", json.dumps(report))
+    out = os.environ.get("SHW_PRECISION_REPORT")
+    if out:
+        with open(out, "w") as fh:
+            json.dump(report, fh, indent=1)
+    for name in ("bf16x3", "fp16x3"):
+        assert report[name]["image_max"] <= 1e-4 and report[name]["slope_max_px"] <= 1e-3, (name, report[name])
+    # plain bf16 (8-bit mantissa) is reported, not held to the bar
+    assert report["bf16"]["image_max"] < 0.05
+
+
+def test_precision_variant_ngs_and_noise(torch_dev):
+    """NGS shape without the convolution, and noise on: the split variant keeps parity."""
+    from tests.test_gpu_wfs import check_noisy
+    cfg = G.CFG1.replace(pupil_n=130, n_subap=13, flags=1 | (G.PREC_FP16X3 << 4))
+    launch = G.launch_positions(cfg, 6)
+    opd = S.lgs39m_opd(1, 6, pupil_n=130)
+    from paper_1408_0698_amd import shwfs
+    plan = shwfs.WfsPlan(cfg, 6, launch)
+    d = torch_dev.from_numpy(opd).cuda()
+    sl = torch_dev.zeros((1, 6, 2, plan.n_valid), device="cuda")
+    im = torch_dev.zeros((1, 6, plan.n_valid, 16, 16), device="cuda")
+    plan.measure(d, sl, im, seed=77, frame0=5)
+    torch_dev.cuda.synchronize()
+    sens = OW.Sensor(cfg, 6, launch)
+    want = sens.measure(opd, seed=77, frame0=5)
+    got = {"slopes": sl.cpu().numpy().astype(np.float64), "images": im.cpu().numpy().astype(np.float64)}
+    check_noisy(cfg, 6, launch, got, want, 77, 5, lambda w: w * sens.n_valid + np.arange(sens.n_valid))
+    ngs = G.CFG1.replace(pupil_n=130, n_subap=13, lgs=0, flags=G.PREC_BF16X3 << 4, photons_per_subap=0.0)
+    sl2, im2 = _run(torch_dev, ngs, None, opd, n_wfs=6)
+    want2 = OW.Sensor(ngs, 6).measure(opd)
+    e = _errors(sl2, im2, want2)
+    assert e["image_max"] <= 1e-4 and e["slope_max_px"] <= 1e-3, e
