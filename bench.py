@@ -118,6 +118,33 @@ def extras(stream):
     torch.cuda.synchronize()
     out["ngs8m_graph_frames_per_s"] = 1e3 / ms_graph
     out["ngs8m_eager_frames_per_s"] = 1e3 / ms_eager
+    # 8 m NGS, 4096 frames per launch (batch of loop steps)
+    opd0b = torch.from_numpy(S.ngs8m_opd(4096)[:, None].copy()).cuda()
+    sl0b = torch.zeros((4096, 1, 2, plan0.n_valid), device="cuda")
+    with torch.cuda.stream(stream):
+        plan0.measure(opd0b, sl0b, stream=stream)
+        ms_b = _time(lambda k: plan0.measure(opd0b, sl0b, frame0=4096 * k, stream=stream), 10, stream)
+    out["ngs8m_b4096_frames_per_s"] = 4096e3 / ms_b
+    out["ngs8m_b4096_tflops_nominal"] = 4096 * plan0.n_valid * 5 * 256 * math.log2(256) / (ms_b * 1e-3) / 1e12
+    del opd0b, sl0b
+    # precision form: the 6-LGS frame with MFMA DFT GEMMs (noise on)
+    launch = G.launch_positions(G.CFG1, 6)
+    opd1 = torch.from_numpy(S.lgs39m_opd(2, 6)).cuda()
+    mm = {}
+    for name, prec, mult in (("bf16", G.PREC_BF16, 1), ("bf16x3", G.PREC_BF16X3, 3), ("fp16x3", G.PREC_FP16X3, 3)):
+        pl = shwfs.WfsPlan(G.CFG1.replace(flags=G.CFG1.flags | (prec << 4)), 6, launch)
+        sl = torch.zeros((1, 6, 2, pl.n_valid), device="cuda")
+        with torch.cuda.stream(stream):
+            for k in range(3):
+                pl.measure(opd1[k % 2:k % 2 + 1], sl, seed=1, frame0=k, stream=stream)
+            ms = _time(lambda k: pl.measure(opd1[k % 2:k % 2 + 1], sl, seed=1, frame0=k, stream=stream), 20, stream)
+        # 384 16x16x16 products per sub-aperture, each one (bf16) or three (split) MFMA instructions
+        flops = 6 * pl.n_valid * 384 * mult * 2 * 16 * 16 * 16
+        mm[name] = {"frames_per_s": 1e3 / ms, "ms_per_frame": ms, "mfma_tflops": flops / (ms * 1e-3) / 1e12,
+                    "mfma_frac_of_2500": flops / (ms * 1e-3) / 2.5e15}
+        pl.close()
+    out["precision_mfma"] = mm
+    del opd1
     # 3 NGS, 2x2 sub-apertures of 400 px padded to 512, noise on
     plan4 = shwfs.WfsPlan(G.CFG4_NGS, 3)
     opd4 = torch.from_numpy(S.lgs39m_opd(4, 3)).cuda()
@@ -153,32 +180,67 @@ def extras(stream):
         for dm, c, sf in zip(dms, coefs, surfs):
             dm.surface(c, sf, stream=stream)
         shwfs.residual_opd(scr, surfs, 800, scr_o, dm_o, res, stream=stream)
-        for st in range(9):
-            psf.accumulate(res[st * nfr:(st + 1) * nfr], acc[st], sr[st], stream=stream)
+        psf.accumulate_stars(res.view(9, nfr, 800, 800), acc, sr, stream=stream)
 
     with torch.cuda.stream(stream):
         psf_step(0)
         ms3 = _time(psf_step, 3, stream)
     out["psf_9stars_x20_star_frames_per_s"] = 9 * nfr * 1e3 / ms3
     out["psf_step_ms"] = ms3
+    # algorithmic HBM bytes per star-frame: OPD 2.56 MB + intermediate written and read 2 x 10.24 MB,
+    # plus the accumulator read and written once per star per step (2 x 10.24 MB / 20 frames)
+    per_sf = 800 * 800 * 4 + 2 * 800 * 1600 * 8 + 2 * 1600 * 1600 * 4 / nfr
+    out["psf_algorithmic_GBps"] = per_sf * 9 * nfr / (ms3 * 1e-3) / 1e9
     out["psf_mean_strehl_last_frame"] = float(sr[:, -1].mean().item())
     del res, acc
     torch.cuda.synchronize()
+    out.update(calibration(stream))
     out["served"] = served()
+    out["served_load_sweep"] = [served(rate_hz=r, duration_s=1.0, warm=False) for r in (4000.0, 8000.0, 16000.0)]
     return out
 
 
-def served(rate_hz=2000.0, duration_s=3.0):
+def calibration(stream):
+    """Push-pull interaction matrix of one LGS sensor (launcher 0, noise off) over every actuator of the
+    ground DM (pitch 10 px): 2 frames per mode, influence frames, measurement and combination on the GPU."""
+    import time
+
+    import numpy as np
+    import torch
+
+    from gen import configs as G
+    from paper_1408_0698_amd import calib, shwfs
+    cfg = G.CFG1.replace(flags=0)
+    plan = shwfs.WfsPlan(cfg, 1, G.launch_positions(G.CFG1, 6)[:1])
+    alt, pitch = G.DMS[0]
+    dm = shwfs.DmPlan(800, 4.875e-2, alt, pitch, G.DM_FIELD_RADIUS_ARCSEC, G.DM_COUPLING, G.DM_PATCH)
+    r0 = (dm.size - 800) // 2
+    acts = np.arange(dm.n_act, dtype=np.int32)
+    with torch.cuda.stream(stream):
+        calib.interaction_matrix(plan, dm, acts[:512], 50e-9, r0, r0, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        im = calib.interaction_matrix(plan, dm, acts, 50e-9, r0, r0, stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    ok = bool(torch.isfinite(im).all().item())
+    del im
+    return {"calibration_modes": int(dm.n_act), "calibration_s": dt, "calibration_frames_per_s": 2 * dm.n_act / dt,
+            "calibration_finite": ok}
+
+
+def served(rate_hz=2000.0, duration_s=3.0, warm=True):
     """Served mix: Poisson arrivals at rate_hz, 70% 8 m frames and 30% 39 m frames (6 LGS + 3 NGS)
     over 12 instances (8 small, 4 large), continuous batching under a 4 GB instance-and-staging
     budget (plans are counted on top); p50/p99 arrival -> slopes-ready latency."""
     from paper_1408_0698_amd.serve import GpuExecutor, Server, latency_report, make_mix
-    warm_inst, warm = make_mix(rate_hz=rate_hz, duration_s=0.3, seed=1)
     ex = GpuExecutor()
     budget = ex.shared_bytes() + (4 << 30)
-    w = Server(ex, warm_inst, budget)
-    w.warm()
-    w.run(warm, timeout=120)
+    if warm:
+        warm_inst, warm_reqs = make_mix(rate_hz=rate_hz, duration_s=0.3, seed=1)
+        w = Server(ex, warm_inst, budget)
+        w.warm()
+        w.run(warm_reqs, timeout=120)
     instances, reqs = make_mix(rate_hz=rate_hz, duration_s=duration_s, seed=2000)
     srv = Server(ex, instances, budget)
     srv.warm()

@@ -87,6 +87,26 @@ CFG1_NWFS = 6
 # intensity embedded in a 40x40 convolution grid.
 CFG1_R2 = CFG1.replace(fft_n=20, conv_n=40)
 
+# Sodium sub-layer form of the 39 m LGS sensor: three sub-layers (the count of the paper's
+# timing).  The profile is a Gaussian of FWHM t cut into n equal slabs over [-t, t], each
+# sub-layer at its slab centre with the slab's share of the profile as weight.  t is the
+# thickness whose geometric elongation across the diameter, t D / H^2, equals the
+# elongation of the single-kernel form (3 arcsec), so the two forms see the same spread.
+def sodium_profile(n_sub: int, thickness_m: float):
+    """(dh_m, weight) of n_sub slabs of a Gaussian profile of FWHM thickness_m over [-t, t]."""
+    sigma = thickness_m / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    edges = [-thickness_m + 2.0 * thickness_m * k / n_sub for k in range(n_sub + 1)]
+    cdf = [0.5 * (1.0 + math.erf(e / (sigma * math.sqrt(2.0)))) for e in edges]
+    dh = [0.5 * (edges[k] + edges[k + 1]) for k in range(n_sub)]
+    wt = [cdf[k + 1] - cdf[k] for k in range(n_sub)]
+    tot = sum(wt)
+    return dh, [v / tot for v in wt]
+
+
+SODIUM_NSUB = 3
+SODIUM_THICKNESS_M = (CFG1.elong_max_arcsec * math.pi / (180.0 * 3600.0)) * CFG1.na_height_m ** 2 / CFG1.diameter_m
+SODIUM = sodium_profile(SODIUM_NSUB, SODIUM_THICKNESS_M)
+
 # cfg4 NGS: 2x2 sub-apertures of 400x400 px padded to 512, detector 16x16.
 CFG4_NGS = WfsConfig(pupil_n=800, pupil_dx_m=4.875e-2, obstruction=0.14, n_subap=2, min_illum=0.5,
                      fft_n=512, conv_n=512, wavelength_m=0.75e-6, lgs=0, det_n=16,

@@ -145,6 +145,27 @@ int shw_wfs_geometry(const shw_wfs_config* cfg, int32_t* n_valid, int32_t* valid
 int shw_wfs_plan_create(const shw_wfs_config* cfg, int32_t n_wfs, const shw_lgs_geom* geom,
                         shw_wfs_plan** out);
 
+/*
+ * Sodium sub-layer form of the LGS sensor (Sec. 4: the sodium layer is cut
+ * into sub-layers; each gets its own tip-tilt and defocus, its spot is
+ * weighted by the sodium profile, the laser extent is a Gaussian
+ * convolution, the sub-layer images are piled up before noise and
+ * centroid).  Sub-layer j lies at height na_height_m + dh_m[j] with profile
+ * weight weight[j] (>= 0; normalised here to unit sum).  Seen from pupil
+ * point r, the beam point of sensor w at height h is a point source at
+ * (launch_w, h); against the focus at na_height_m = H it adds
+ *     -|r - launch_w|^2 / 2 * (1/h - 1/H)   metres of OPD
+ * (tip-tilt plus defocus over each sub-aperture, a constant otherwise).
+ * The convolution kernel is then the round laser spot (FWHM
+ * spot_fwhm_arcsec): the elongation comes from the sub-layers.
+ * Requires lgs = 1, FP32 precision, 1 <= n_sub <= 16, a shape with a
+ * sub-layer kernel (sub-apertures of 10 pixels, fft_n = conv_n = 40,
+ * det_n = 16; or 8 / 16 / 16 / 8), else SHW_E_INVALID / SHW_E_UNSUPPORTED.
+ * dh_m and weight are host arrays of n_sub entries, copied.
+ */
+int shw_wfs_plan_create_sodium(const shw_wfs_config* cfg, int32_t n_wfs, const shw_lgs_geom* geom, int32_t n_sub,
+                               const double* dh_m, const double* weight, shw_wfs_plan** out);
+
 /* Plan facts: valid sub-apertures per sensor, device bytes held.  Either pointer may be NULL. */
 int shw_wfs_plan_info(const shw_wfs_plan* plan, int32_t* n_valid, size_t* device_bytes);
 
@@ -179,6 +200,19 @@ int shw_wfs_plan_kernel_spectra(const shw_wfs_plan* plan, int32_t wfs, float* d_
 int sh_wfs_measure(shw_wfs_plan* plan, const float* d_opd_m, int64_t row_pitch, int64_t wfs_stride,
                    int64_t frame_stride, int32_t n_frames, uint64_t seed, uint64_t frame0,
                    float* d_slopes, float* d_images, uint8_t* d_flags, void* hip_stream);
+
+/*
+ * sh_wfs_measure_sodium - sh_wfs_measure for a plan made by
+ * shw_wfs_plan_create_sodium, with one wavefront per sub-layer (Sec. 4: the
+ * sensor takes the open-loop wavefront minus the DMs for each sodium
+ * sub-layer): element (f, w, sub-layer j, r, c) at d_opd_m[f*frame_stride +
+ * w*wfs_stride + j*sub_stride + r*row_pitch + c]; sub_stride = 0 gives every
+ * sub-layer the same wavefront (what sh_wfs_measure does on such a plan).
+ * SHW_E_INVALID for a plan without sub-layers or a negative stride.
+ */
+int sh_wfs_measure_sodium(shw_wfs_plan* plan, const float* d_opd_m, int64_t row_pitch, int64_t sub_stride,
+                          int64_t wfs_stride, int64_t frame_stride, int32_t n_frames, uint64_t seed,
+                          uint64_t frame0, float* d_slopes, float* d_images, uint8_t* d_flags, void* hip_stream);
 
 /*
  * One item of a mixed batch: one frame of all sensors of a plan.
@@ -265,6 +299,18 @@ int shw_psf_plan_create(int32_t abi_version, int32_t pupil_n, double pupil_dx_m,
 int psf_accumulate(shw_psf_plan* plan, const float* d_opd_m, int64_t row_pitch, int64_t frame_stride,
                    int32_t n_frames, float* d_psf_acc, float* d_strehl, void* hip_stream);
 
+/*
+ * psf_accumulate over n_stars stars at once (the test-star grid of a science
+ * field): star s frame f starts at d_opd_m + s*star_stride + f*frame_stride,
+ * its accumulator at d_psf_acc + s*acc_stride (acc_stride >= fft_m^2), its
+ * Strehl ratio at d_strehl[s*n_frames + f] (nullable).  The plan's workspace
+ * grows (once, up to 4 GiB) to hold every frame of every star of the call;
+ * growing synchronises the device.  Asynchronous otherwise.
+ */
+int psf_accumulate_stars(shw_psf_plan* plan, const float* d_opd_m, int64_t row_pitch, int64_t frame_stride,
+                         int64_t star_stride, int32_t n_frames, int32_t n_stars, float* d_psf_acc,
+                         int64_t acc_stride, float* d_strehl, void* hip_stream);
+
 int shw_psf_plan_destroy(shw_psf_plan* plan);
 
 
@@ -305,6 +351,31 @@ int shw_dm_geometry(int32_t pupil_n, double pupil_dx_m, double alt_m, int32_t pi
 int shw_dm_surface(shw_dm_plan* plan, const float* d_coefs, float* d_surface, void* hip_stream);
 
 int shw_dm_plan_destroy(shw_dm_plan* plan);
+
+/*
+ * Push-pull calibration (Sec. 3 interaction-matrix block: the slopes the WFS
+ * registers for each pushed mode; Sec. 5: a modal push-pull calibration of
+ * one LGS sensor over 5000 modes).  The modes here are the influence
+ * functions of the DM's actuators.
+ *
+ * shw_dm_influence_opd: d_out[k][y][x] (row pitch out_pitch, frame stride
+ * out_stride) = d_amp[k] * IF of actuator d_act[k] at surface pixel
+ * (row0 + y, col0 + x), for k < n, y, x < pupil_n; 0 outside the actuator's
+ * patch.  d_act (int32) and d_amp (FP32) are device arrays of n entries
+ * (n <= 65535); an index outside [0, n_act) yields a frame of NaN.  The
+ * window must lie inside the size x size surface (SHW_E_INVALID otherwise).
+ *
+ * shw_push_pull: d_im[s * ld_im + m] = (d_slopes[2m][s] - d_slopes[2m+1][s]) * scale
+ * for m < n_modes, s < n_slopes: frames 2m / 2m+1 are the push / pull of mode
+ * m, scale = 1 / (2 amplitude); d_im is the interaction matrix, one row per slope
+ * (ld_im >= n_modes, SHW_E_INVALID otherwise).  Both calls are asynchronous on
+ * hip_stream; the caller owns every buffer.
+ */
+int shw_dm_influence_opd(const shw_dm_plan* plan, const int32_t* d_act, const float* d_amp, int32_t n, int32_t row0,
+                         int32_t col0, int32_t pupil_n, float* d_out, int64_t out_pitch, int64_t out_stride,
+                         void* hip_stream);
+int shw_push_pull(const float* d_slopes, int32_t n_modes, int32_t n_slopes, float scale, float* d_im, int64_t ld_im,
+                  void* hip_stream);
 
 /*
  * Residual OPD of n_out pupils: out_k[y][x] = screen[sr_k + y][sc_k + x]

@@ -22,7 +22,7 @@ are listed in ``READINGS`` and in the design notes.  Parts with no anchor
 outside this package (the physical realism of the LGS spot) are "parity
 unpinned": only self-consistency with the readings is checked.
 """
-from . import geometry, philox, wfs, psf, dm  # noqa: F401
+from . import geometry, philox, wfs, psf, dm, calib  # noqa: F401
 
 READINGS = {
     "O1": "binary pupil, pixel-centre test, linear obstruction ratio",

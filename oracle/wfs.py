@@ -134,14 +134,41 @@ def centroid(img, threshold):
     return np.where(empty, 0.0, sx_num / safe), np.where(empty, 0.0, sy_num / safe), empty
 
 
+def sublayer_opd(cfg, launch_xy, dh_m):
+    """Extra OPD (metres) over the pupil for the sodium sub-layer at height H + dh (reading O13).
+
+    Sec. 4: each sodium sub-layer brings its own tip-tilt and defocus.  The
+    beam point at height h above the launcher at L is a point source; its
+    spherical wavefront at pupil point r, taken against the one from the
+    focus height H, is -|r - L|^2 / 2 * (1/h - 1/H) (paraxial).
+    """
+    n = cfg.pupil_n
+    c = (np.arange(n, dtype=np.float64) + 0.5 - n / 2.0) * cfg.pupil_dx_m
+    x = c[None, :] - launch_xy[0]
+    y = c[:, None] - launch_xy[1]
+    H = cfg.na_height_m
+    return -0.5 * (x * x + y * y) * (1.0 / (H + dh_m) - 1.0 / H)
+
+
+def round_kernel_spectrum(cfg):
+    """K^ of the round laser spot (FWHM spot_fwhm_arcsec) on the conv grid: the sub-layer form's kernel."""
+    px_as = G.fft_pixel_rad(cfg) / G.ARCSEC
+    sigma = cfg.spot_fwhm_arcsec / (2.0 * np.sqrt(2.0 * np.log(2.0))) / px_as
+    return G.kernel_spectrum(G.sodium_kernel(cfg.conv_n, sigma, sigma, 0.0)).real
+
+
 def measure_one(cfg, opd_m, valid_idx, illum, khat=None, seed=0, gsub0=0, frame=0,
-                chunk=2048, subset=None):
+                chunk=2048, subset=None, layers=None):
     """One sensor, one frame.  Returns dict(slopes=[2][S], images=[S][d][d], empty=[S]).
 
     khat: callable mapping sub-aperture indices to their K^ (LGS only).
 
     subset: optional indices into valid_idx to evaluate only some sub-apertures
     (their global ids and noise counters stay those of the full sensor).
+
+    layers: optional list of (weight, opd) for the sodium sub-layer form: the
+    spot is sum_j weight_j |transform of sub-layer j|^2 (Sec. 4: per-sub-layer
+    spots times the profile, piled up) and opd_m is not used.
     """
     sel = np.arange(len(valid_idx)) if subset is None else np.asarray(subset)
     noise = bool(cfg.flags & 1) and cfg.photons_per_subap > 0
@@ -153,7 +180,10 @@ def measure_one(cfg, opd_m, valid_idx, illum, khat=None, seed=0, gsub0=0, frame=
     empty = np.empty(len(sel), dtype=bool)
     for s0 in range(0, len(sel), chunk):
         ii = sel[s0:s0 + chunk]
-        I = spot_intensity(cfg, subap_fields(cfg, opd_m, valid_idx[ii]))
+        if layers is None:
+            I = spot_intensity(cfg, subap_fields(cfg, opd_m, valid_idx[ii]))
+        else:
+            I = sum(wt * spot_intensity(cfg, subap_fields(cfg, o, valid_idx[ii])) for wt, o in layers)
         I = embed(cfg, I)
         J = convolve(I, khat(ii)) if cfg.lgs else I
         det = rebin(J, cfg.det_n)
@@ -174,18 +204,28 @@ def measure_one(cfg, opd_m, valid_idx, illum, khat=None, seed=0, gsub0=0, frame=
 class Sensor:
     """n_wfs sensors of one geometry: tables built once (plan setup, Sec. 4 inputs)."""
 
-    def __init__(self, cfg, n_wfs=1, launch=None):
+    def __init__(self, cfg, n_wfs=1, launch=None, sodium=None):
+        """sodium: optional (dh_m, weight): the sodium sub-layer form (weights normalised to unit sum)."""
         self.cfg = cfg
         self.n_wfs = n_wfs
         self.valid_idx, self.illum = G.subap_table(cfg)
         self.n_valid = len(self.valid_idx)
         self.launch = launch
         self._khat = {}
+        self.sodium = None
+        if sodium is not None:
+            dh = np.asarray(sodium[0], dtype=np.float64)
+            wt = np.asarray(sodium[1], dtype=np.float64)
+            self.sodium = (dh, wt / wt.sum())
+            self._round = round_kernel_spectrum(cfg)
+            self._sub_opd = [[sublayer_opd(cfg, launch[w], d) for d in dh] for w in range(n_wfs)]
 
     def khat(self, w, sel):
         """K^ of sub-apertures sel of sensor w ([len(sel)][conv_n][conv_n]), cached."""
         if not self.cfg.lgs:
             return None
+        if self.sodium is not None:
+            return np.broadcast_to(self._round, (len(sel),) + self._round.shape)
         need = [int(i) for i in sel if (w, int(i)) not in self._khat]
         if need:
             ks = kernel_spectra(self.cfg, self.launch[w], self.valid_idx[need])
@@ -194,7 +234,7 @@ class Sensor:
         return np.stack([self._khat[(w, int(i))] for i in sel])
 
     def measure(self, opd, seed=0, frame0=0, subset=None):
-        """opd: [n_frames][n_wfs][N_p][N_p].
+        """opd: [n_frames][n_wfs][N_p][N_p], or [n_frames][n_wfs][n_sub][N_p][N_p] for the sub-layer form.
 
         Returns slopes [F][W][2][S'], images [F][W][S'][d][d] (electrons after noise),
         lam (expected electrons before noise, same shape) and empty [F][W][S'].
@@ -208,9 +248,15 @@ class Sensor:
         empty = np.empty((nf, self.n_wfs, S), dtype=bool)
         for f in range(nf):
             for w in range(self.n_wfs):
+                layers = None
+                if self.sodium is not None:
+                    dh, wt = self.sodium
+                    per_layer = opd.ndim == 5
+                    layers = [(wt[j], np.asarray(opd[f, w, j] if per_layer else opd[f, w], dtype=np.float64)
+                               + self._sub_opd[w][j]) for j in range(len(dh))]
                 r = measure_one(self.cfg, opd[f, w], self.valid_idx, self.illum,
                                 (lambda ii, w=w: self.khat(w, ii)),
-                                seed=seed, gsub0=w * self.n_valid, frame=frame0 + f, subset=subset)
+                                seed=seed, gsub0=w * self.n_valid, frame=frame0 + f, subset=subset, layers=layers)
                 slopes[f, w] = r["slopes"]
                 images[f, w] = r["images"]
                 lam[f, w] = r["lam"]

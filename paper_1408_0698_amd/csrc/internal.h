@@ -35,11 +35,19 @@ struct WfsLaunch {
   uint32_t key0, key1, frame0;
   const uint64_t* frame0_dev;  // nullable: frame number of the first frame, read on the device
   const FrameWork* list;       // nullable: frame f takes buffers, strides and key from list[f]
+  // sodium sub-layers (kernels built with sub-layers only): sub-layer j adds c_j |r - L_w|^2 / 2
+  // waves to the phase (r the pixel centre, L_w the launcher, both in pupil pixels from the axis)
+  // and weighs its spot by weight_j
+  int32_t n_sub, pad1;
+  int64_t sub_stride;          // OPD elements between the sub-layer wavefronts of a sensor (0: shared)
+  const double* sub_coef;      // [n_sub][2] = (c_j waves / pixel^2, weight_j)
+  const double* launch_px;     // [n_wfs][2] launcher (x, y) in pupil pixels from the axis
 };
 
 // Shape of a compiled fused kernel.
 struct WfsShape {
   int npx, fft_n, conv_n, det_n, lgs;
+  int sub;  // 1: sodium sub-layer kernels (LGS shapes only)
 };
 
 // Returns true if a kernel for this shape is compiled in.

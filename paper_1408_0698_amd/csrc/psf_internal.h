@@ -7,8 +7,10 @@
 namespace shw {
 
 struct PsfLaunch {
-  const float* opd;        // OPD metres, frame f at opd + f * frame_stride
-  int64_t row_pitch, frame_stride;
+  const float* opd;        // OPD metres, star s frame f at opd + s * star_stride + f * frame_stride
+  int64_t row_pitch, frame_stride, star_stride;
+  int64_t acc_stride;      // accumulator of star s at acc + s * acc_stride
+  int32_t n_frames;        // frames per star in the call (Strehl index s * n_frames + f)
   int32_t pupil_n, pad0;
   double inv_lambda;
   float r2_outer, r2_inner, half_n;
@@ -17,8 +19,9 @@ struct PsfLaunch {
 
 bool psf_size_supported(int fft_m, int pupil_n);
 
-// Row and column passes over frames [f0, f0 + nf); T holds nf * pupil_n * fft_m complex.
-hipError_t launch_psf_chunk(const PsfLaunch& a, int64_t f0, int nf, float2* T, float* acc, float* strehl,
-                            hipStream_t st);
+// Row and column passes over frames [f0, f0 + nf) of stars [0, n_stars); T holds
+// n_stars * nf * pupil_n * fft_m complex.
+hipError_t launch_psf_chunk(const PsfLaunch& a, int n_stars, int64_t f0, int nf, float2* T, float* acc,
+                            float* strehl, hipStream_t st);
 
 }  // namespace shw

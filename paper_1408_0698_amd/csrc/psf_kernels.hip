@@ -82,19 +82,20 @@ __device__ __forceinline__ void transpose_tile(float* pl, const float2* Y, float
 
 }  // namespace
 
-__global__ __launch_bounds__(kLines * kQ) void psf_rows_kernel(const PsfLaunch a, int64_t f0, int64_t nrows,
+__global__ __launch_bounds__(kLines * kQ) void psf_rows_kernel(const PsfLaunch a, int64_t f0, int nf, int64_t nrows,
                                                                float2* __restrict__ T) {
   __shared__ float s_pl[kLines * kQ * kST];
   const int tid = threadIdx.x;
   const int line = tid / kQ, lane = tid - line * kQ;
-  const int64_t row = (int64_t)blockIdx.x * kLines + line;  // (frame - f0) * pupil_n + y
+  const int64_t row = (int64_t)blockIdx.x * kLines + line;  // (star * nf + frame - f0) * pupil_n + y
   const bool active = row < nrows;
-  const int64_t fl = active ? row / a.pupil_n : 0;
-  const int y = active ? (int)(row - fl * a.pupil_n) : 0;
+  const int64_t sf = active ? row / a.pupil_n : 0;
+  const int y = active ? (int)(row - sf * a.pupil_n) : 0;
+  const int64_t star = sf / nf, fl = sf - star * nf;
   float* pl = s_pl + line * kQ * kST;
   float2 v[kNZ];
   {
-    const float* src = a.opd + (f0 + fl) * a.frame_stride + (int64_t)y * a.row_pitch;
+    const float* src = a.opd + star * a.star_stride + (f0 + fl) * a.frame_stride + (int64_t)y * a.row_pitch;
     const float by = (float)y + 0.5f - a.half_n;
     const float by2 = by * by;
 #pragma unroll
@@ -133,13 +134,14 @@ __global__ __launch_bounds__(kLines * kQ) void psf_cols_kernel(const PsfLaunch a
   __shared__ float s_pl[kLines * kQ * kST];
   const int tid = threadIdx.x;
   const int line = tid / kQ, lane = tid - line * kQ;
-  const int u = blockIdx.x * kLines + line;  // column; the grid covers exactly kM columns
+  const int star = blockIdx.x / (kM / kLines);
+  const int u = (blockIdx.x - star * (kM / kLines)) * kLines + line;  // column of this star
   float* pl = s_pl + line * kQ * kST;
   float sum[kQ];
 #pragma unroll
   for (int k2 = 0; k2 < kQ; ++k2) sum[k2] = 0.0f;
   for (int fl = 0; fl < nf; ++fl) {
-    const float2* src = T + (int64_t)fl * a.pupil_n * kM + u;
+    const float2* src = T + ((int64_t)star * nf + fl) * a.pupil_n * kM + u;
     float2 v[kNZ];
 #pragma unroll
     for (int n1 = 0; n1 < kNZ; ++n1) {
@@ -156,27 +158,27 @@ __global__ __launch_bounds__(kLines * kQ) void psf_cols_kernel(const PsfLaunch a
       const float p = (z[k2].x * z[k2].x + z[k2].y * z[k2].y) * a.inv_norm;
       sum[k2] += p;
       // on-axis sample: v = u = M/2, i.e. lane 0, k2 = 20 of column M/2
-      if (strehl && u == kM / 2 && lane == 0 && k2 == kM / 2 / kQ) strehl[f0 + fl] = p;
+      if (strehl && u == kM / 2 && lane == 0 && k2 == kM / 2 / kQ) strehl[(int64_t)star * a.n_frames + f0 + fl] = p;
     }
   }
 #pragma unroll
   for (int k2 = 0; k2 < kQ; ++k2) {
     const int v = lane + kQ * k2;
-    acc[(int64_t)v * kM + u] += sum[k2];
+    acc[star * a.acc_stride + (int64_t)v * kM + u] += sum[k2];
   }
 }
 
 bool psf_size_supported(int fft_m, int pupil_n) { return fft_m == kM && pupil_n >= 1 && pupil_n <= kM / 2; }
 
-hipError_t launch_psf_chunk(const PsfLaunch& a, int64_t f0, int nf, float2* T, float* acc, float* strehl,
-                            hipStream_t st) {
-  const int64_t nrows = (int64_t)nf * a.pupil_n;
+hipError_t launch_psf_chunk(const PsfLaunch& a, int n_stars, int64_t f0, int nf, float2* T, float* acc,
+                            float* strehl, hipStream_t st) {
+  const int64_t nrows = (int64_t)n_stars * nf * a.pupil_n;
   const int64_t rb = (nrows + kLines - 1) / kLines;
-  hipLaunchKernelGGL(psf_rows_kernel, dim3((unsigned)rb), dim3(kLines * kQ), 0, st, a, f0, nrows, T);
+  hipLaunchKernelGGL(psf_rows_kernel, dim3((unsigned)rb), dim3(kLines * kQ), 0, st, a, f0, nf, nrows, T);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(psf_cols_kernel, dim3(kM / kLines), dim3(kLines * kQ), 0, st, a, f0, nf, (const float2*)T, acc,
-                     strehl);
+  hipLaunchKernelGGL(psf_cols_kernel, dim3((unsigned)(n_stars * (kM / kLines))), dim3(kLines * kQ), 0, st, a, f0, nf,
+                     (const float2*)T, acc, strehl);
   return hipGetLastError();
 }
 

@@ -74,6 +74,9 @@ struct shw_wfs_plan {
   int64_t chunk_items = 0;
   float2* d_T = nullptr;
   float* d_Jr = nullptr;
+  // sodium sub-layers: [n_sub][2] (phase coefficient, weight) then [n_wfs][2] launcher pixels
+  int32_t n_sub = 0;
+  double* d_sub = nullptr;
 };
 
 
@@ -295,22 +298,65 @@ extern "C" int shw_wfs_plan_destroy(shw_wfs_plan* p) {
   if (p->d_list) (void)hipFree(p->d_list);
   if (p->d_mfma_tab) (void)hipFree(p->d_mfma_tab);
   if (p->d_Jr) (void)hipFree(p->d_Jr);
+  if (p->d_sub) (void)hipFree(p->d_sub);
   if (cur != p->device) (void)hipSetDevice(cur);
   delete p;
   return ok();
 }
 
-extern "C" int shw_wfs_plan_create(const shw_wfs_config* cfg, int32_t n_wfs, const shw_lgs_geom* geom,
-                                   shw_wfs_plan** out) {
+// Sodium sub-layer tables: phase coefficient and normalised weight per sub-layer, launcher
+// positions in pupil pixels.  A point of the beam at height h seen from pupil point r has the
+// wavefront of a point source at (L, h); against the focus at the layer height H this adds
+// -|r - L|^2 / 2 (1/h - 1/H) metres of OPD (Sec. 4: tip-tilt and defocus per sub-layer).
+static int sodium_tables(const shw_wfs_config* c, int32_t n_wfs, const shw_lgs_geom* geom, int32_t n_sub,
+                         const double* dh_m, const double* weight, std::vector<double>& t) {
+  if (!c->lgs) return fail(SHW_E_INVALID, "sodium sub-layers need an LGS configuration");
+  if (n_sub < 1 || n_sub > 16) return fail(SHW_E_INVALID, "n_sub %d outside [1, 16]", n_sub);
+  if (!dh_m || !weight) return fail(SHW_E_INVALID, "NULL sub-layer table");
+  const double H = c->na_height_m;
+  if (!(is_fin(H) && H > 0)) return fail(SHW_E_INVALID, "na_height_m must be > 0");
+  double wsum = 0.0;
+  for (int j = 0; j < n_sub; ++j) {
+    if (!(is_fin(dh_m[j]) && H + dh_m[j] > 0)) return fail(SHW_E_INVALID, "sub-layer %d height not > 0", j);
+    if (!(is_fin(weight[j]) && weight[j] >= 0)) return fail(SHW_E_INVALID, "sub-layer %d weight not >= 0", j);
+    wsum += weight[j];
+  }
+  if (!(wsum > 0)) return fail(SHW_E_INVALID, "sub-layer weights sum to 0");
+  const unsigned prec = (c->flags >> SHW_PRECISION_SHIFT) & 0xFu;
+  const WfsShape shape{c->pupil_n / c->n_subap, c->fft_n, c->conv_n, c->det_n, c->lgs, 1};
+  if (prec != SHW_PREC_FP32 || !wfs_shape_supported(shape))
+    return fail(SHW_E_UNSUPPORTED, "no sodium sub-layer kernel for this shape and precision");
+  const double dx = c->pupil_dx_m;
+  t.assign((size_t)2 * (n_sub + n_wfs), 0.0);
+  for (int j = 0; j < n_sub; ++j) {
+    const double kappa = 1.0 / (H + dh_m[j]) - 1.0 / H;
+    t[2 * j] = -dx * dx * kappa / c->wavelength_m;
+    t[2 * j + 1] = weight[j] / wsum;
+  }
+  for (int w = 0; w < n_wfs; ++w) {
+    t[2 * (n_sub + w)] = geom[w].launch_x_m / dx;
+    t[2 * (n_sub + w) + 1] = geom[w].launch_y_m / dx;
+  }
+  return SHW_OK;
+}
+
+static int plan_create(const shw_wfs_config* cfg, int32_t n_wfs, const shw_lgs_geom* geom, int32_t n_sub,
+                       const double* dh_m, const double* weight, shw_wfs_plan** out) {
   if (!out) return fail(SHW_E_INVALID, "out is NULL");
   *out = nullptr;
   int r = check_config(cfg, n_wfs, geom);
   if (r != SHW_OK) return r;
+  std::vector<double> sub_tab;
+  if (n_sub > 0) {
+    r = sodium_tables(cfg, n_wfs, geom, n_sub, dh_m, weight, sub_tab);
+    if (r != SHW_OK) return r;
+  }
   auto* p = new shw_wfs_plan();
   p->cfg = *cfg;
   p->n_wfs = n_wfs;
   p->npx = cfg->pupil_n / cfg->n_subap;
-  p->shape = WfsShape{p->npx, cfg->fft_n, cfg->conv_n, cfg->det_n, cfg->lgs};
+  p->n_sub = n_sub;
+  p->shape = WfsShape{p->npx, cfg->fft_n, cfg->conv_n, cfg->det_n, cfg->lgs, n_sub > 0 ? 1 : 0};
   std::vector<double> illum;
   valid_table(cfg, p->valid, illum);
   p->n_valid = (int32_t)p->valid.size();
@@ -331,6 +377,16 @@ extern "C" int shw_wfs_plan_create(const shw_wfs_config* cfg, int32_t n_wfs, con
     return hip_fail(e, "plan tables");
   }
   p->bytes = sizeof(int32_t) * p->n_valid;
+  if (n_sub > 0) {
+    e = hipMalloc(&p->d_sub, sizeof(double) * sub_tab.size());
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_sub, sub_tab.data(), sizeof(double) * sub_tab.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      shw_wfs_plan_destroy(p);
+      return hip_fail(e, "sub-layer tables");
+    }
+    p->bytes += sizeof(double) * sub_tab.size();
+  }
   p->prec = (int32_t)((cfg->flags >> SHW_PRECISION_SHIFT) & 0xFu);
   if (p->prec != SHW_PREC_FP32) {
     const std::vector<uint16_t> t = mfma_tables(cfg, p->prec);
@@ -363,7 +419,14 @@ extern "C" int shw_wfs_plan_create(const shw_wfs_config* cfg, int32_t n_wfs, con
     const int H = cfg->conv_n / 2 + 1;
     std::vector<double> params((size_t)n * 3);
     for (int w = 0; w < n_wfs; ++w)
-      for (int i = 0; i < p->n_valid; ++i) elongation(cfg, geom[w], p->valid[i], &params[((size_t)w * p->n_valid + i) * 3]);
+      for (int i = 0; i < p->n_valid; ++i) {
+        double* q = &params[((size_t)w * p->n_valid + i) * 3];
+        elongation(cfg, geom[w], p->valid[i], q);
+        if (n_sub > 0) {  // the sub-layers make the elongation: the kernel is the round laser spot
+          q[0] = q[1];
+          q[2] = 0.0;
+        }
+      }
     double* d_params = nullptr;
     e = hipMalloc(&d_params, sizeof(double) * params.size());
     if (e == hipSuccess) e = hipMemcpy(d_params, params.data(), sizeof(double) * params.size(), hipMemcpyHostToDevice);
@@ -379,6 +442,21 @@ extern "C" int shw_wfs_plan_create(const shw_wfs_config* cfg, int32_t n_wfs, con
   }
   *out = p;
   return ok();
+}
+
+extern "C" int shw_wfs_plan_create(const shw_wfs_config* cfg, int32_t n_wfs, const shw_lgs_geom* geom,
+                                   shw_wfs_plan** out) {
+  return plan_create(cfg, n_wfs, geom, 0, nullptr, nullptr, out);
+}
+
+extern "C" int shw_wfs_plan_create_sodium(const shw_wfs_config* cfg, int32_t n_wfs, const shw_lgs_geom* geom,
+                                          int32_t n_sub, const double* dh_m, const double* weight,
+                                          shw_wfs_plan** out) {
+  if (n_sub < 1) {
+    if (out) *out = nullptr;
+    return fail(SHW_E_INVALID, "n_sub %d < 1", n_sub);
+  }
+  return plan_create(cfg, n_wfs, geom, n_sub, dh_m, weight, out);
 }
 
 extern "C" int shw_wfs_plan_info(const shw_wfs_plan* p, int32_t* n_valid, size_t* device_bytes) {
@@ -417,6 +495,9 @@ static WfsLaunch base_launch(const shw_wfs_plan* p) {
   a.ron = (float)c.ron_e;
   a.thr = c.photons_per_subap > 0 ? (float)c.threshold_e : 0.0f;
   a.noise = (c.flags & SHW_FLAG_NOISE) && c.photons_per_subap > 0 ? 1 : 0;
+  a.n_sub = p->n_sub;
+  a.sub_coef = p->d_sub;
+  a.launch_px = p->d_sub ? p->d_sub + 2 * p->n_sub : nullptr;
   return a;
 }
 
@@ -458,7 +539,8 @@ static int launch_big_list(shw_wfs_plan* p, const WfsLaunch& a, void* stream) {
 
 static int measure_impl(shw_wfs_plan* p, const float* d_opd_m, int64_t row_pitch, int64_t wfs_stride,
                         int64_t frame_stride, int32_t n_frames, uint64_t seed, uint64_t frame0,
-                        const uint64_t* d_frame0, float* d_slopes, float* d_images, uint8_t* d_flags, void* stream) {
+                        const uint64_t* d_frame0, float* d_slopes, float* d_images, uint8_t* d_flags, void* stream,
+                        int64_t sub_stride = 0) {
   if (!p) return fail(SHW_E_INVALID, "plan is NULL");
   if (n_frames < 0) return fail(SHW_E_INVALID, "n_frames %d < 0", n_frames);
   if (n_frames == 0) return ok();
@@ -480,6 +562,7 @@ static int measure_impl(shw_wfs_plan* p, const float* d_opd_m, int64_t row_pitch
   a.key1 = (uint32_t)(seed >> 32);
   a.frame0 = (uint32_t)frame0;
   a.frame0_dev = d_frame0;
+  a.sub_stride = sub_stride;
   if (p->big) return launch_big_list(p, a, stream);
   if (p->prec != SHW_PREC_FP32) {
     if (d_frame0) return fail(SHW_E_UNSUPPORTED, "device frame counter not available for MFMA plans");
@@ -509,6 +592,8 @@ extern "C" int sh_wfs_measure_batch(const shw_work* items, int32_t n, void* stre
     for (auto* q : plans) seen = seen || q == items[k].plan;
     if (!seen) plans.push_back(items[k].plan);
   }
+  for (auto* p : plans)
+    if (p->prec != SHW_PREC_FP32) return fail(SHW_E_UNSUPPORTED, "work lists need an FP32 plan");
   for (auto* p : plans) {
     std::vector<FrameWork> list;
     for (int32_t k = 0; k < n; ++k) {
@@ -519,7 +604,6 @@ extern "C" int sh_wfs_measure_batch(const shw_work* items, int32_t n, void* stre
     const int32_t nf = (int32_t)list.size();
     if (nf > p->list_cap) {
       if (p->d_list) (void)hipFree(p->d_list);
-  if (p->d_mfma_tab) (void)hipFree(p->d_mfma_tab);
       p->d_list = nullptr;
       p->list_cap = 0;
       const int32_t cap = nf < 256 ? 256 : nf;
@@ -530,7 +614,6 @@ extern "C" int sh_wfs_measure_batch(const shw_work* items, int32_t n, void* stre
     hipError_t e = hipMemcpyAsync(p->d_list, list.data(), sizeof(FrameWork) * nf, hipMemcpyHostToDevice,
                                   (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "work list upload");
-    if (p->prec != SHW_PREC_FP32) return fail(SHW_E_UNSUPPORTED, "work lists need an FP32 plan");
     WfsLaunch a = base_launch(p);
     a.list = p->d_list;
     a.total = (int64_t)nf * p->n_wfs * p->n_valid;
@@ -615,18 +698,44 @@ extern "C" int shw_psf_plan_create(int32_t abi_version, int32_t pupil_n, double 
   return ok();
 }
 
-extern "C" int psf_accumulate(shw_psf_plan* p, const float* d_opd_m, int64_t row_pitch, int64_t frame_stride,
-                              int32_t n_frames, float* d_psf_acc, float* d_strehl, void* stream) {
+static int psf_impl(shw_psf_plan* p, const float* d_opd_m, int64_t row_pitch, int64_t frame_stride,
+                    int64_t star_stride, int32_t n_frames, int32_t n_stars, float* d_psf_acc, int64_t acc_stride,
+                    float* d_strehl, void* stream) {
   if (!p) return fail(SHW_E_INVALID, "plan is NULL");
-  if (n_frames < 0) return fail(SHW_E_INVALID, "n_frames %d < 0", n_frames);
-  if (n_frames == 0) return ok();
+  if (n_frames < 0 || n_stars < 0) return fail(SHW_E_INVALID, "negative frame or star count");
+  if (n_frames == 0 || n_stars == 0) return ok();
   if (!d_opd_m || !d_psf_acc) return fail(SHW_E_INVALID, "NULL OPD or accumulator");
   if (row_pitch < p->pupil_n) return fail(SHW_E_INVALID, "row_pitch %lld < pupil_n", (long long)row_pitch);
-  if (frame_stride < 0) return fail(SHW_E_INVALID, "negative frame_stride");
+  if (frame_stride < 0 || star_stride < 0) return fail(SHW_E_INVALID, "negative stride");
+  if (n_stars > 1 && acc_stride < (int64_t)p->fft_m * p->fft_m) return fail(SHW_E_INVALID, "accumulators overlap");
+  // grow the intermediate to hold every frame of every star (up to 4 GiB); otherwise run
+  // frame chunks of all stars
+  const int64_t per_frame = (int64_t)p->pupil_n * p->fft_m * (int64_t)sizeof(float2);
+  const int64_t want = (int64_t)n_stars * n_frames;
+  if (want > p->chunk && want * per_frame <= ((int64_t)4 << 30)) {
+    float2* t = nullptr;
+    hipError_t e = hipMalloc(&t, (size_t)(want * per_frame));
+    if (e != hipSuccess) return hip_fail(e, "PSF workspace");
+    // the old workspace may still be read by queued work on another stream: wait before freeing
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      (void)hipFree(t);
+      return hip_fail(e, "PSF workspace");
+    }
+    (void)hipFree(p->d_work);
+    p->d_work = t;
+    p->chunk = (int32_t)want;
+    p->bytes = (size_t)(want * per_frame);
+  }
+  int32_t k = (int32_t)(p->chunk / n_stars);
+  if (k < 1) return fail(SHW_E_NOMEM, "PSF workspace holds %d frames, %d stars", p->chunk, n_stars);
   PsfLaunch a{};
   a.opd = d_opd_m;
   a.row_pitch = row_pitch;
   a.frame_stride = frame_stride;
+  a.star_stride = star_stride;
+  a.acc_stride = acc_stride;
+  a.n_frames = n_frames;
   a.pupil_n = p->pupil_n;
   a.inv_lambda = 1.0 / p->wavelength;
   const double h = p->pupil_n / 2.0;
@@ -634,12 +743,24 @@ extern "C" int psf_accumulate(shw_psf_plan* p, const float* d_opd_m, int64_t row
   a.r2_inner = (float)((p->obstruction * h) * (p->obstruction * h));
   a.half_n = (float)h;
   a.inv_norm = (float)(1.0 / ((double)p->lit * (double)p->lit));
-  for (int32_t f0 = 0; f0 < n_frames; f0 += p->chunk) {
-    const int nf = n_frames - f0 < p->chunk ? n_frames - f0 : p->chunk;
-    hipError_t e = launch_psf_chunk(a, f0, nf, p->d_work, d_psf_acc, d_strehl, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "psf_accumulate launch");
+  for (int32_t f0 = 0; f0 < n_frames; f0 += k) {
+    const int nf = n_frames - f0 < k ? n_frames - f0 : k;
+    hipError_t e = launch_psf_chunk(a, n_stars, f0, nf, p->d_work, d_psf_acc, d_strehl, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "psf launch");
   }
   return ok();
+}
+
+extern "C" int psf_accumulate(shw_psf_plan* p, const float* d_opd_m, int64_t row_pitch, int64_t frame_stride,
+                              int32_t n_frames, float* d_psf_acc, float* d_strehl, void* stream) {
+  return psf_impl(p, d_opd_m, row_pitch, frame_stride, 0, n_frames, 1, d_psf_acc, 0, d_strehl, stream);
+}
+
+extern "C" int psf_accumulate_stars(shw_psf_plan* p, const float* d_opd_m, int64_t row_pitch, int64_t frame_stride,
+                                    int64_t star_stride, int32_t n_frames, int32_t n_stars, float* d_psf_acc,
+                                    int64_t acc_stride, float* d_strehl, void* stream) {
+  return psf_impl(p, d_opd_m, row_pitch, frame_stride, star_stride, n_frames, n_stars, d_psf_acc, acc_stride, d_strehl,
+                  stream);
 }
 
 // ---------------------------------------------------------------- deformable mirrors, residual OPD
@@ -650,6 +771,7 @@ struct shw_dm_plan {
   int device = 0;
   std::vector<double> act;   // [n_act][2] (x, y)
   int* d_grid = nullptr;
+  float* d_act_xy = nullptr;  // [n_act][2] FP32 device copy (influence-function frames)
 };
 
 // Metapupil radius, surface side and actuator grid (host, FP64).
@@ -701,6 +823,7 @@ extern "C" int shw_dm_plan_destroy(shw_dm_plan* p) {
   (void)hipGetDevice(&cur);
   if (cur != p->device) (void)hipSetDevice(p->device);
   if (p->d_grid) (void)hipFree(p->d_grid);
+  if (p->d_act_xy) (void)hipFree(p->d_act_xy);
   if (cur != p->device) (void)hipSetDevice(cur);
   delete p;
   return ok();
@@ -728,9 +851,13 @@ extern "C" int shw_dm_plan_create(int32_t abi_version, int32_t pupil_n, double p
   p->sigma = pitch_px / std::sqrt(2.0 * std::log(1.0 / coupling));
   p->act = act;
   p->n_act = (int32_t)(act.size() / 2);
+  std::vector<float> axy(act.begin(), act.end());
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess) e = hipMalloc(&p->d_grid, sizeof(int) * grid.size());
   if (e == hipSuccess) e = hipMemcpy(p->d_grid, grid.data(), sizeof(int) * grid.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&p->d_act_xy, sizeof(float) * (axy.empty() ? 1 : axy.size()));
+  if (e == hipSuccess && !axy.empty())
+    e = hipMemcpy(p->d_act_xy, axy.data(), sizeof(float) * axy.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     shw_dm_plan_destroy(p);
     return hip_fail(e, "DM plan tables");
@@ -818,6 +945,17 @@ extern "C" int sh_wfs_measure(shw_wfs_plan* p, const float* d_opd_m, int64_t row
                               float* d_slopes, float* d_images, uint8_t* d_flags, void* stream) {
   return measure_impl(p, d_opd_m, row_pitch, wfs_stride, frame_stride, n_frames, seed, frame0, nullptr, d_slopes,
                       d_images, d_flags, stream);
+}
+
+extern "C" int sh_wfs_measure_sodium(shw_wfs_plan* p, const float* d_opd_m, int64_t row_pitch, int64_t sub_stride,
+                                     int64_t wfs_stride, int64_t frame_stride, int32_t n_frames, uint64_t seed,
+                                     uint64_t frame0, float* d_slopes, float* d_images, uint8_t* d_flags,
+                                     void* stream) {
+  if (!p) return fail(SHW_E_INVALID, "plan is NULL");
+  if (p->n_sub < 1) return fail(SHW_E_INVALID, "plan has no sodium sub-layers");
+  if (sub_stride < 0) return fail(SHW_E_INVALID, "negative sub-layer stride");
+  return measure_impl(p, d_opd_m, row_pitch, wfs_stride, frame_stride, n_frames, seed, frame0, nullptr, d_slopes,
+                      d_images, d_flags, stream, sub_stride);
 }
 
 extern "C" int sh_wfs_measure_devframe(shw_wfs_plan* p, const float* d_opd_m, int64_t row_pitch, int64_t wfs_stride,
@@ -945,5 +1083,48 @@ extern "C" int shw_graph_destroy(shw_graph* g) {
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
+  return ok();
+}
+
+// ---------------------------------------------------------------- push-pull calibration
+
+extern "C" int shw_dm_influence_opd(const shw_dm_plan* p, const int32_t* d_act, const float* d_amp, int32_t n,
+                                    int32_t row0, int32_t col0, int32_t pupil_n, float* d_out, int64_t out_pitch,
+                                    int64_t out_stride, void* stream) {
+  if (!p) return fail(SHW_E_INVALID, "plan is NULL");
+  if (n < 0 || n > 65535) return fail(SHW_E_INVALID, "n = %d outside [0, 65535]", n);
+  if (n == 0) return ok();
+  if (!d_act || !d_amp || !d_out) return fail(SHW_E_INVALID, "NULL argument");
+  if (pupil_n < 1 || row0 < 0 || col0 < 0 || row0 + pupil_n > p->size || col0 + pupil_n > p->size)
+    return fail(SHW_E_INVALID, "pupil window (%d, %d) + %d leaves the %d-pixel surface", row0, col0, pupil_n, p->size);
+  if (out_pitch < pupil_n || out_stride < 0) return fail(SHW_E_INVALID, "bad output layout");
+  InfluenceLaunch a{};
+  a.act_xy = p->d_act_xy;
+  a.act = d_act;
+  a.amp = d_amp;
+  a.n = n;
+  a.n_act = p->n_act;
+  a.size = p->size;
+  a.half_patch = p->patch / 2;
+  a.row0 = row0;
+  a.col0 = col0;
+  a.pupil_n = pupil_n;
+  a.inv_2s2 = (float)(1.0 / (2.0 * p->sigma * p->sigma));
+  a.out_pitch = out_pitch;
+  a.out_stride = out_stride;
+  hipError_t e = launch_influence_opd(a, d_out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "shw_dm_influence_opd launch");
+  return ok();
+}
+
+extern "C" int shw_push_pull(const float* d_slopes, int32_t n_modes, int32_t n_slopes, float scale, float* d_im,
+                             int64_t ld_im, void* stream) {
+  if (n_modes < 0 || n_slopes < 0) return fail(SHW_E_INVALID, "negative size");
+  if (n_modes == 0 || n_slopes == 0) return ok();
+  if (!d_slopes || !d_im) return fail(SHW_E_INVALID, "NULL argument");
+  if (ld_im < n_modes) return fail(SHW_E_INVALID, "ld_im %lld < n_modes %d", (long long)ld_im, n_modes);
+  if ((n_modes + 31) / 32 > 65535) return fail(SHW_E_INVALID, "n_modes %d too large", n_modes);
+  hipError_t e = launch_push_pull(d_slopes, n_modes, n_slopes, scale, d_im, ld_im, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "shw_push_pull launch");
   return ok();
 }

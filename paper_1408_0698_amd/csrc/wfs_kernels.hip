@@ -18,6 +18,11 @@
 //     before the FP32 sincos, then runs one NPX-point transform.
 //  A' column pass, same pruning, then I = |F|^2 / FFT_N^2: lane u holds
 //     column u of the spot, embedded in the CONV_N grid.
+//     With sodium sub-layers (SUB) A and A' repeat per sub-layer, each with
+//     its own wavefront, its perspective tip-tilt and defocus added to the
+//     FP64 phase, and its profile weight; the weighted spots are summed.
+//     The following Gaussian convolution is linear, so summing before it
+//     equals convolving every sub-layer spot and piling them up.
 //  B  (LGS) real column transform, per-row transform x K^ x inverse row
 //     transform, inverse column transform: J = I (*) k.
 //  C  rebin along the column in registers, then along the row via LDS.
@@ -72,7 +77,7 @@ struct FusedLayout {
 };
 
 // One group of SPB work items (one block's worth).  Every lane of the block calls it.
-template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, bool SPLIT>
+template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, bool SPLIT, bool SUB>
 __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t group, uint32_t frame_base,
                                                 float* __restrict__ s_re, float* __restrict__ s_im) {
   constexpr int L = CONV_N;                  // lanes per item
@@ -134,6 +139,13 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
     images_it = a.images ? a.images + it * (DET_N * DET_N) : nullptr;
   }
 
+  float col[CONV_N];
+#pragma unroll
+  for (int v = 0; v < CONV_N; ++v) col[v] = 0.0f;
+  const int n_sub = SUB ? a.n_sub : 1;
+#pragma unroll 1
+  for (int sl = 0; sl < n_sub; ++sl) {
+  if (SUB && sl > 0) __syncthreads();  // the previous sub-layer's column pass has read the plane
   // ---------------------------------------------------------------- A: row pass
   if (active && l < FFT_N) {
     const int y = l / R;
@@ -142,6 +154,14 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
     const float* src = opd_f + (int64_t)w * wfs_stride + (int64_t)prow * row_pitch + (int64_t)sb * NPX;
     const float ay = (float)prow + 0.5f - a.half_n;
     const float ay2 = ay * ay;
+    double c_sub = 0.0, lx = 0.0, qy = 0.0;
+    if constexpr (SUB) {
+      src += (int64_t)sl * a.sub_stride;
+      c_sub = 0.5 * a.sub_coef[2 * sl];
+      lx = a.launch_px[2 * w];
+      const double dy = (double)ay - a.launch_px[2 * w + 1];
+      qy = c_sub * dy * dy;
+    }
     float2 z[NPX];
 #pragma unroll
     for (int x = 0; x < NPX; ++x) {
@@ -151,6 +171,10 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       // waves: OPD / lambda + centring ramp (FFT_N-1)(x+y)/(2 FFT_N) - x k2 / FFT_N
       const double ramp = (double)((FFT_N - 1) * (x + y)) / (2.0 * FFT_N) - (double)(x * k2) / (double)FFT_N;
       double wv = (double)src[x] * a.inv_lambda + ramp;
+      if constexpr (SUB) {
+        const double dx = (double)ax - lx;
+        wv += qy + c_sub * dx * dx;
+      }
       wv -= floor(wv);
       // hardware sine/cosine take the argument in revolutions: exp(2 pi i wv) after the FP64 reduction
       const float fw = (float)wv;
@@ -166,10 +190,8 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   __syncthreads();
 
   // ---------------------------------------------------------------- A': column pass, |F|^2
-  float col[CONV_N];
-#pragma unroll
-  for (int v = 0; v < CONV_N; ++v) col[v] = 0.0f;
   {
+    const float wgt = SUB ? (float)a.sub_coef[2 * sl + 1] * INV_N2 : INV_N2;
     const int u = l - OFF;
     if (active && u >= 0 && u < FFT_N) {
       float2 g[NPX];
@@ -182,10 +204,18 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
         for (int y = 0; y < NPX; ++y) z[y] = twiddle_mul<FFT_N, -1>(g[y], y * k2);
         RegFFT<NPX, -1>::run(z);
 #pragma unroll
-        for (int k1 = 0; k1 < NPX; ++k1) col[OFF + k2 + R * k1] = (z[k1].x * z[k1].x + z[k1].y * z[k1].y) * INV_N2;
+        for (int k1 = 0; k1 < NPX; ++k1) {
+          const float p = (z[k1].x * z[k1].x + z[k1].y * z[k1].y) * wgt;
+          if constexpr (SUB) {
+            col[OFF + k2 + R * k1] += p;
+          } else {
+            col[OFF + k2 + R * k1] = p;
+          }
+        }
       }
     }
   }
+  }  // sub-layers
 
   // ---------------------------------------------------------------- B: convolution with k
   // J = I (*) k through the half spectrum of the real image.  Columns: real transforms as
@@ -386,25 +416,39 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       }
       det_area[p * DET_N + q0 + j] = det;
     }
-#pragma unroll 1
-    for (int j = 0; j < QB; ++j) {
-      const int pix = p * DET_N + q0 + j;
-      const float det = det_area[pix];
-      float img = det;
-      if (a.ph_scale > 0.0f) {
-        const float lam = a.ph_scale * det;
-        img = lam;
-        if (a.noise) {
-          if (lam >= 10.0f) {
-            queue[atomicAdd(&queue[QCOUNT], 1)] = pix;
-            continue;
-          }
-          const uint4 wd = philox4x32_10(make_uint4(0u, (uint32_t)pix, gsub, frame), key0, key1);
-          const int k = lam > 0.0f ? poisson_inversion(lam, u01(wd.x)) : 0;
-          img = (float)k + a.ron * read_noise_z(wd);
+  }
+  __syncthreads();
+  // every lane of the item takes pixels l, l + L, ...; two at a time so that their Philox
+  // chains interleave
+  auto finish = [&](int pix, float det, const uint4& wd) {
+    float img = det;
+    if (a.ph_scale > 0.0f) {
+      const float lam = a.ph_scale * det;
+      img = lam;
+      if (a.noise) {
+        if (lam >= 10.0f) {
+          queue[atomicAdd(&queue[QCOUNT], 1)] = pix;
+          return;
         }
+        const int k = lam > 0.0f ? poisson_inversion(lam, u01(wd.x)) : 0;
+        img = (float)k + a.ron * read_noise_z(wd);
       }
-      accumulate(pix, img);
+    }
+    accumulate(pix, img);
+  };
+  if (active) {
+    const bool need_rng = a.noise && a.ph_scale > 0.0f;
+#pragma unroll 1
+    for (int pix = l; pix < NPIX; pix += 2 * L) {
+      const int pix2 = pix + L;
+      const bool two = pix2 < NPIX;
+      uint4 w1 = make_uint4(0u, 0u, 0u, 0u), w2 = w1;
+      if (need_rng) {
+        w1 = philox4x32_10(make_uint4(0u, (uint32_t)pix, gsub, frame), key0, key1);
+        w2 = philox4x32_10(make_uint4(0u, (uint32_t)(two ? pix2 : pix), gsub, frame), key0, key1);
+      }
+      finish(pix, det_area[pix], w1);
+      if (two) finish(pix2, det_area[pix2], w2);
     }
   }
   __syncthreads();
@@ -441,7 +485,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
 
 // One-shot grid (one group per block) or persistent grid (blocks stride over the groups).
 // The frame number of the first frame comes from a.frame0_dev when set (graph replay).
-template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, int WPE, bool PERSIST, bool SPLIT>
+template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, int WPE, bool PERSIST, bool SPLIT, bool SUB>
 __global__ __launch_bounds__(SPB * CONV_N) __attribute__((amdgpu_waves_per_eu(WPE))) void wfs_fused_kernel(
     const WfsLaunch a) {
   using LY = FusedLayout<NPX, FFT_N, CONV_N, DET_N>;
@@ -451,11 +495,11 @@ __global__ __launch_bounds__(SPB * CONV_N) __attribute__((amdgpu_waves_per_eu(WP
   if constexpr (PERSIST) {
     const int64_t ngroups = (a.total + SPB - 1) / SPB;
     for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
-      wfs_fused_group<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, SPLIT>(a, g, frame_base, s_re, s_im);
+      wfs_fused_group<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, SPLIT, SUB>(a, g, frame_base, s_re, s_im);
       __syncthreads();
     }
   } else {
-    wfs_fused_group<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, SPLIT>(a, blockIdx.x, frame_base, s_re, s_im);
+    wfs_fused_group<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, SPLIT, SUB>(a, blockIdx.x, frame_base, s_re, s_im);
   }
 }
 
@@ -466,9 +510,10 @@ constexpr int items_per_block(int lanes) {
   return spb;
 }
 
-template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, int WPE, bool PERSIST, bool SPLIT>
+template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, int WPE, bool PERSIST, bool SPLIT,
+          bool SUB = false>
 static hipError_t launch_variant(const WfsLaunch& a, hipStream_t st) {
-  auto kern = wfs_fused_kernel<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, WPE, PERSIST, SPLIT>;
+  auto kern = wfs_fused_kernel<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, WPE, PERSIST, SPLIT, SUB>;
   const int64_t groups = (a.total + SPB - 1) / SPB;
   if (groups <= 0) return hipSuccess;
   int64_t blocks = groups;
@@ -492,11 +537,20 @@ static hipError_t launch_variant(const WfsLaunch& a, hipStream_t st) {
 // waves-per-EU target, persistent grid).  Variant 0 is the default.
 constexpr int kTunedVariants = 6;
 
-template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS>
+// Sub-layer kernels: whole or split row transforms, waves-per-EU target 1.
+constexpr int kSubVariants = 2;
+
+template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, bool SUB>
 static hipError_t launch_one(int variant, const WfsLaunch& a, hipStream_t st) {
   constexpr int SPB = items_per_block(CONV_N);
   constexpr bool TUNED = (CONV_N == 40 && DET_N == 16);
-  if constexpr (TUNED) {
+  if constexpr (SUB) {
+    switch (variant) {
+      case 0: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, false, true>(a, st);
+      case 1: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, true, true>(a, st);
+      default: return hipErrorInvalidValue;
+    }
+  } else if constexpr (TUNED) {
     switch (variant) {
       case 0: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, false>(a, st);
       case 1: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 4, false, false>(a, st);
@@ -512,18 +566,24 @@ static hipError_t launch_one(int variant, const WfsLaunch& a, hipStream_t st) {
   }
 }
 
-#define SHW_WFS_SHAPES(X)     \
-  X(8, 16, 16, 8, false)      \
-  X(8, 16, 16, 8, true)       \
-  X(8, 16, 16, 16, false)     \
-  X(10, 40, 40, 16, true)     \
-  X(10, 40, 40, 16, false)    \
-  X(10, 20, 40, 16, true)     \
-  X(10, 20, 20, 10, false)
+#define SHW_WFS_SHAPES(X)       \
+  X(8, 16, 16, 8, false, false) \
+  X(8, 16, 16, 8, true, false)  \
+  X(8, 16, 16, 16, false, false) \
+  X(10, 40, 40, 16, true, false) \
+  X(10, 40, 40, 16, false, false) \
+  X(10, 20, 40, 16, true, false) \
+  X(10, 20, 20, 10, false, false) \
+  X(8, 16, 16, 8, true, true)   \
+  X(10, 40, 40, 16, true, true)
+
+#define SHW_SHAPE_MATCH(np, fn, cn, dn, lg, sb)                                                   \
+  (s.npx == np && s.fft_n == fn && s.conv_n == cn && s.det_n == dn && (s.lgs != 0) == lg && \
+   (s.sub != 0) == sb)
 
 bool wfs_shape_supported(const WfsShape& s) {
-#define X(np, fn, cn, dn, lg) \
-  if (s.npx == np && s.fft_n == fn && s.conv_n == cn && s.det_n == dn && (s.lgs != 0) == lg) return true;
+#define X(np, fn, cn, dn, lg, sb) \
+  if (SHW_SHAPE_MATCH(np, fn, cn, dn, lg, sb)) return true;
   SHW_WFS_SHAPES(X)
 #undef X
   return false;
@@ -531,13 +591,13 @@ bool wfs_shape_supported(const WfsShape& s) {
 
 int wfs_variant_count(const WfsShape& s) {
   if (!wfs_shape_supported(s)) return 0;
+  if (s.sub) return kSubVariants;
   return (s.conv_n == 40 && s.det_n == 16) ? kTunedVariants : 1;
 }
 
 hipError_t launch_wfs_fused(const WfsShape& s, int variant, const WfsLaunch& a, hipStream_t st) {
-#define X(np, fn, cn, dn, lg) \
-  if (s.npx == np && s.fft_n == fn && s.conv_n == cn && s.det_n == dn && (s.lgs != 0) == lg) \
-    return launch_one<np, fn, cn, dn, lg>(variant, a, st);
+#define X(np, fn, cn, dn, lg, sb) \
+  if (SHW_SHAPE_MATCH(np, fn, cn, dn, lg, sb)) return launch_one<np, fn, cn, dn, lg, sb>(variant, a, st);
   SHW_WFS_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;

@@ -53,10 +53,14 @@ _sig = {
     "shw_wfs_geometry": (C.c_int, [C.POINTER(WfsConfigC), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                    C.POINTER(C.c_double)]),
     "shw_wfs_plan_create": (C.c_int, [C.POINTER(WfsConfigC), C.c_int32, C.POINTER(LgsGeomC), C.POINTER(_P)]),
+    "shw_wfs_plan_create_sodium": (C.c_int, [C.POINTER(WfsConfigC), C.c_int32, C.POINTER(LgsGeomC), C.c_int32,
+                                             C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(_P)]),
     "shw_wfs_plan_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_size_t)]),
     "shw_wfs_plan_kernel_spectra": (C.c_int, [_P, C.c_int32, _P, _P]),
     "sh_wfs_measure": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_uint64, C.c_uint64,
                                  _P, _P, _P, _P]),
+    "sh_wfs_measure_sodium": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_uint64,
+                                        C.c_uint64, _P, _P, _P, _P]),
     "sh_wfs_measure_batch": (C.c_int, [C.POINTER(WorkC), C.c_int32, _P]),
     "shw_wfs_plan_destroy": (C.c_int, [_P]),
     "shw_wfs_plan_variant_count": (C.c_int, [_P, C.POINTER(C.c_int32)]),
@@ -73,6 +77,8 @@ _sig = {
     "shw_psf_plan_create": (C.c_int, [C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double,
                                       C.POINTER(_P)]),
     "psf_accumulate": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int32, _P, _P, _P]),
+    "psf_accumulate_stars": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32, _P, C.c_int64,
+                                       _P, _P]),
     "shw_psf_plan_destroy": (C.c_int, [_P]),
     "shw_dm_plan_create": (C.c_int, [C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double,
                                      C.c_double, C.c_int32, C.POINTER(_P)]),
@@ -81,6 +87,9 @@ _sig = {
                                   C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "shw_dm_surface": (C.c_int, [_P, _P, _P, _P]),
     "shw_dm_plan_destroy": (C.c_int, [_P]),
+    "shw_dm_influence_opd": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64,
+                                       C.c_int64, _P]),
+    "shw_push_pull": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_float, _P, C.c_int64, _P]),
     "shw_residual_opd": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.POINTER(C.c_void_p),
                                    C.POINTER(C.c_int32), C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32), _P, C.c_int64, C.c_int64, _P]),
@@ -157,13 +166,25 @@ def _ptr(t):
 class WfsPlan:
     """n_wfs Shack-Hartmann sensors of one geometry (plan owned by the library)."""
 
-    def __init__(self, cfg, n_wfs=1, launch=None):
+    def __init__(self, cfg, n_wfs=1, launch=None, sodium=None):
+        """sodium: optional (dh_m, weight) sequences: the sodium sub-layer form of an LGS sensor."""
         self.cfg = cfg
         self.n_wfs = n_wfs
         self._c = make_config(cfg)
         arr, ptr = _geom_array(launch)
         h = C.c_void_p()
-        _check(_lib.shw_wfs_plan_create(C.byref(self._c), n_wfs, ptr, C.byref(h)), "shw_wfs_plan_create")
+        self.n_sub = 0
+        if sodium is None:
+            _check(_lib.shw_wfs_plan_create(C.byref(self._c), n_wfs, ptr, C.byref(h)), "shw_wfs_plan_create")
+        else:
+            dh, wt = (list(map(float, v)) for v in sodium)
+            n = len(dh)
+            if len(wt) != n:
+                raise ValueError("sodium heights and weights differ in length")
+            _check(_lib.shw_wfs_plan_create_sodium(C.byref(self._c), n_wfs, ptr, n, (C.c_double * max(1, n))(*dh),
+                                                   (C.c_double * max(1, n))(*wt), C.byref(h)),
+                   "shw_wfs_plan_create_sodium")
+            self.n_sub = n
         self._h = h
         nv = C.c_int32(0)
         nb = C.c_size_t(0)
@@ -227,6 +248,16 @@ class WfsPlan:
         return slopes
 
 
+    def measure_sodium(self, opd, slopes, images=None, flags=None, seed=0, frame0=0, stream=None):
+        """opd: float32 device tensor [F][W][n_sub][N][N] (a sub-layer stride of 0 shares one wavefront)."""
+        if opd.dim() != 5 or opd.stride(4) != 1:
+            raise ValueError("opd must be [frames][wfs][sub-layers][rows][cols] with contiguous rows")
+        _check(_lib.sh_wfs_measure_sodium(self._h, _ptr(opd), opd.stride(3), opd.stride(2), opd.stride(1),
+                                          opd.stride(0), opd.shape[0], seed, frame0, _ptr(slopes), _ptr(images),
+                                          _ptr(flags), _stream_ptr(stream)), "sh_wfs_measure_sodium")
+        return slopes
+
+
 def measure_batch(items, stream=None):
     """items: list of (plan, opd[W][N][N], slopes[W][2][S], images or None, seed, frame)."""
     arr = (WorkC * max(1, len(items)))()
@@ -261,6 +292,15 @@ class PsfPlan:
             raise ValueError("opd must be [frames][rows][cols] with contiguous rows")
         _check(_lib.psf_accumulate(self._h, _ptr(opd), opd.stride(1), opd.stride(0), opd.shape[0], _ptr(acc),
                                    _ptr(strehl), _stream_ptr(stream)), "psf_accumulate")
+        return acc
+
+    def accumulate_stars(self, opd, acc, strehl=None, stream=None):
+        """opd: float32 device [S][F][N][N] (rows contiguous); acc [S][M][M] (+=); strehl [S][F] or None."""
+        if opd.dim() != 4 or opd.stride(3) != 1:
+            raise ValueError("opd must be [stars][frames][rows][cols] with contiguous rows")
+        _check(_lib.psf_accumulate_stars(self._h, _ptr(opd), opd.stride(2), opd.stride(1), opd.stride(0), opd.shape[1],
+                                         opd.shape[0], _ptr(acc), acc.stride(0), _ptr(strehl), _stream_ptr(stream)),
+               "psf_accumulate_stars")
         return acc
 
 
@@ -298,6 +338,12 @@ class DmPlan:
 
     def __del__(self):
         self.close()
+
+    def influence_opd(self, act, amp, row0, col0, pupil_n, out, stream=None):
+        """out[k] = amp[k] * IF of actuator act[k] on the pupil window (row0, col0); act int32, amp float32."""
+        _check(_lib.shw_dm_influence_opd(self._h, _ptr(act), _ptr(amp), act.shape[0], row0, col0, pupil_n, _ptr(out),
+                                         out.stride(-2), out.stride(0), _stream_ptr(stream)), "shw_dm_influence_opd")
+        return out
 
     def surface(self, coefs, out, stream=None):
         """coefs: float32 device [n_act]; out: float32 device [size][size] (contiguous)."""
@@ -368,3 +414,10 @@ class _Capture:
         elif rc == OK:
             _lib.shw_graph_destroy(h)
         return False
+
+
+def push_pull(slopes, n_modes, scale, im, stream=None):
+    """im[s, m] (row pitch im.stride(0)) = (slopes[2m] - slopes[2m+1])[s] * scale; slopes [2 n_modes][n_slopes]."""
+    _check(_lib.shw_push_pull(_ptr(slopes), n_modes, slopes.shape[-1], scale, _ptr(im), im.stride(0),
+                              _stream_ptr(stream)), "shw_push_pull")
+    return im

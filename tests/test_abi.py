@@ -128,3 +128,46 @@ def test_dm_and_residual_argument_checks():
                                    None) == s.E_INVALID
     assert s._lib.shw_residual_opd(fake, 2048, 2048, 2048, 0, None, None, 800, 0, so, None, fake, 800, 640000,
                                    None) == s.OK
+
+
+def test_calibration_argument_checks():
+    """shw_dm_influence_opd and shw_push_pull reject bad windows and layouts before any launch."""
+    import ctypes as C
+
+    from paper_1408_0698_amd import shwfs as s
+    fake = C.c_void_p(0x1000)
+    assert s._lib.shw_dm_influence_opd(None, fake, fake, 1, 0, 0, 8, fake, 8, 64, None) == s.E_INVALID
+    assert s._lib.shw_push_pull(fake, 4, 10, C.c_float(1.0), fake, 3, None) == s.E_INVALID
+    assert s._lib.shw_push_pull(None, 4, 10, C.c_float(1.0), fake, 4, None) == s.E_INVALID
+    assert s._lib.shw_push_pull(fake, -1, 10, C.c_float(1.0), fake, 4, None) == s.E_INVALID
+    assert s._lib.shw_push_pull(fake, 0, 10, C.c_float(1.0), None, 4, None) == 0
+
+
+def test_sodium_plan_argument_checks():
+    """Sub-layer plans are validated on the host before any HIP call."""
+    import ctypes as C
+
+    from gen import configs as G
+    from paper_1408_0698_amd import shwfs as s
+    h = C.c_void_p()
+    launch = G.launch_positions(G.CFG1, 1)
+    geom = (s.LgsGeomC * 1)(s.LgsGeomC(*launch[0]))
+    dh = (C.c_double * 3)(-1000.0, 0.0, 1000.0)
+    wt = (C.c_double * 3)(1.0, 2.0, 1.0)
+    cfg = s.make_config(G.CFG1)
+    assert s._lib.shw_wfs_plan_create_sodium(C.byref(cfg), 1, geom, 0, dh, wt, C.byref(h)) == s.E_INVALID
+    assert s._lib.shw_wfs_plan_create_sodium(C.byref(cfg), 1, geom, 17, dh, wt, C.byref(h)) == s.E_INVALID
+    assert s._lib.shw_wfs_plan_create_sodium(C.byref(cfg), 1, geom, 3, None, wt, C.byref(h)) == s.E_INVALID
+    bad = (C.c_double * 3)(1.0, -2.0, 1.0)
+    assert s._lib.shw_wfs_plan_create_sodium(C.byref(cfg), 1, geom, 3, dh, bad, C.byref(h)) == s.E_INVALID
+    zero = (C.c_double * 3)(0.0, 0.0, 0.0)
+    assert s._lib.shw_wfs_plan_create_sodium(C.byref(cfg), 1, geom, 3, dh, zero, C.byref(h)) == s.E_INVALID
+    low = (C.c_double * 3)(-1e6, 0.0, 1000.0)
+    assert s._lib.shw_wfs_plan_create_sodium(C.byref(cfg), 1, geom, 3, low, wt, C.byref(h)) == s.E_INVALID
+    ngs = s.make_config(G.CFG0)
+    assert s._lib.shw_wfs_plan_create_sodium(C.byref(ngs), 1, geom, 3, dh, wt, C.byref(h)) == s.E_INVALID
+    mfma = s.make_config(G.CFG1.replace(flags=G.PREC_FP16X3 << 4))
+    assert s._lib.shw_wfs_plan_create_sodium(C.byref(mfma), 1, geom, 3, dh, wt, C.byref(h)) == s.E_UNSUPPORTED
+    r2 = s.make_config(G.CFG1_R2)
+    assert s._lib.shw_wfs_plan_create_sodium(C.byref(r2), 1, geom, 3, dh, wt, C.byref(h)) == s.E_UNSUPPORTED
+    assert s._lib.sh_wfs_measure_sodium(None, None, 800, 0, 0, 0, 1, 0, 0, None, None, None, None) == s.E_INVALID

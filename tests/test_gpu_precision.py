@@ -97,3 +97,21 @@ def test_precision_variant_ngs_and_noise(torch_dev):
     want2 = OW.Sensor(ngs, 6).measure(opd)
     e = _errors(sl2, im2, want2)
     assert e["image_max"] <= 1e-4 and e["slope_max_px"] <= 1e-3, e
+
+
+def test_batch_call_on_mfma_plan_is_refused_and_harmless(torch_dev, reference):
+    """A work-list call on an MFMA plan is refused before any upload; the plan's tables stay valid."""
+    from paper_1408_0698_amd import shwfs
+    cfg, launch, opd, _ = reference
+    c = cfg.replace(flags=cfg.flags | (G.PREC_FP16X3 << 4))
+    plan = shwfs.WfsPlan(c, 6, launch)
+    d = torch_dev.from_numpy(opd).cuda()
+    sl1 = torch_dev.zeros((2, 6, 2, plan.n_valid), device="cuda")
+    plan.measure(d, sl1)
+    for _ in range(2):
+        with pytest.raises(shwfs.ShwError):
+            shwfs.measure_batch([(plan, d[0], sl1[0], None, 0, 0)] * 300)
+    sl2 = torch_dev.zeros_like(sl1)
+    plan.measure(d, sl2)
+    torch_dev.cuda.synchronize()
+    assert torch_dev.equal(sl1, sl2)

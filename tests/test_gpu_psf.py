@@ -113,3 +113,22 @@ def test_zero_frames_noop_and_bad_arguments(torch_dev):
                                      None, None) == shwfs.E_INVALID
     assert shwfs._lib.psf_accumulate(plan._h, C.c_void_p(d.data_ptr()), 64, -5, 1, C.c_void_p(acc.data_ptr()),
                                      None, None) == shwfs.E_INVALID
+
+
+def test_star_batch_equals_single_calls(torch_dev):
+    """3 stars x 5 frames in one call: every star equals its own call, bitwise; one star vs the oracle."""
+    cfg = G.PsfConfig(pupil_n=160, pupil_dx_m=39.0 / 160)
+    opd = np.stack([_opd(5, 160, 0.1, seed=s) for s in (1, 2, 3)])
+    plan = _plan(cfg)
+    d = torch_dev.from_numpy(opd).cuda()
+    acc = torch_dev.zeros((3, 1600, 1600), device="cuda")
+    sr = torch_dev.zeros((3, 5), device="cuda")
+    plan.accumulate_stars(d, acc, sr)
+    torch_dev.cuda.synchronize()
+    for s in range(3):
+        a1, s1 = run_gpu(torch_dev, cfg, opd[s])
+        assert np.array_equal(acc[s].cpu().numpy(), a1.astype(np.float32))
+        assert np.array_equal(sr[s].cpu().numpy(), s1.astype(np.float32))
+    want, want_sr = OP.psf_accumulate(cfg, opd[1])
+    assert np.abs(acc[1].cpu().numpy() - want).max() <= TOL * want.max()
+    assert np.abs(sr[1].cpu().numpy() - want_sr).max() <= TOL * want_sr.max()

@@ -442,3 +442,93 @@ def test_residual_is_screen_minus_shifted_surfaces():
     out = D.residual_opd(scr, (2, 5), [s1], [(1, 3)], 8)
     assert np.array_equal(out, scr[2:10, 5:13] - s1[1:9, 3:11])
     assert D.footprint_shift_px(12700, 60, 4.875e-2) == 76 and D.footprint_shift_px(4000, -60, 4.875e-2) == -24
+
+
+# ---------------------------------------------------------------- O13 sodium sub-layers
+
+def _sodium_cfg(ns=2, **kw):
+    return C.CFG1.replace(pupil_n=10 * ns, n_subap=ns, obstruction=0.0, flags=0, photons_per_subap=0.0,
+                          threshold_e=0.0, **kw)
+
+
+@pytest.mark.parametrize("dh", [-2000.0, 1500.0])
+def test_sublayer_opd_gradient_is_parallax_angle(dh):
+    """The OPD slope equals the change of the exact 3-D direction to the beam point between heights H + dh and H."""
+    cfg = _sodium_cfg(13)
+    L = (6.1, -2.3)
+    opd = O.sublayer_opd(cfg, L, dh)
+    dx = cfg.pupil_dx_m
+    H = cfg.na_height_m
+    for (i, j) in [(3, 4), (60, 100), (120, 7)]:
+        x = (j + 0.5 - cfg.pupil_n / 2) * dx
+        y = (i + 0.5 - cfg.pupil_n / 2) * dx
+
+        def cosines(h):
+            v = np.array([L[0] - x, L[1] - y, h])
+            return v[:2] / np.linalg.norm(v)
+        want = cosines(H + dh) - cosines(H)
+        gx = (opd[i, j + 1] - opd[i, j - 1]) / (2 * dx)
+        gy = (opd[i + 1, j] - opd[i - 1, j]) / (2 * dx)
+        assert abs(gx - want[0]) < 1e-5 * abs(want[0]) and abs(gy - want[1]) < 1e-5 * abs(want[1])
+
+
+@pytest.mark.parametrize("s", [2, -3])
+def test_sublayer_integer_parallax_is_circular_shift(s):
+    """A launcher placed so that the sub-layer tilt over a sub-aperture is s FFT pixels shifts the spot by s
+    against the launcher at the sub-aperture centre (same defocus in both)."""
+    cfg = _sodium_cfg(2)
+    valid, _ = G.subap_table(cfg)
+    dh = -2000.0
+    H = cfg.na_height_m
+    kappa = 1.0 / (H + dh) - 1.0 / H
+    rc = ((0.5 * 10) - cfg.pupil_n / 2) * cfg.pupil_dx_m          # sub-aperture 0 centre, x and y
+    shift = s * cfg.wavelength_m / (cfg.fft_n * cfg.pupil_dx_m * kappa)
+    at_c = O.spot_intensity(cfg, O.subap_fields(cfg, O.sublayer_opd(cfg, (rc, rc), dh), valid[:1]))[0]
+    off = O.spot_intensity(cfg, O.subap_fields(cfg, O.sublayer_opd(cfg, (rc + shift, rc), dh), valid[:1]))[0]
+    assert np.abs(off - np.roll(at_c, s, axis=1)).max() < 1e-9 * at_c.max()
+    assert np.abs(at_c - at_c.T).max() < 1e-9 * at_c.max()      # pure defocus: symmetric in x and y
+
+
+def test_sodium_single_layer_at_focus_is_the_round_kernel_form():
+    cfg = _sodium_cfg(4)
+    L = [(1.0, -0.5)]
+    opd = np.random.default_rng(3).normal(0, 2e-7, (1, 1, 40, 40))
+    a = O.Sensor(cfg, 1, L, sodium=([0.0], [1.0])).measure(opd)
+    b = O.Sensor(cfg.replace(elong_max_arcsec=1e-12), 1, L).measure(opd)
+    assert np.abs(a["images"] - b["images"]).max() < 1e-12 * np.abs(b["images"]).max()
+
+
+def test_sodium_weights_are_normalised():
+    cfg = _sodium_cfg(3)
+    L = [(0.5, 0.7)]
+    opd = np.zeros((1, 1, 30, 30))
+    a = O.Sensor(cfg, 1, L, sodium=([-1500.0, 0.0, 1500.0], [1.0, 2.0, 1.0])).measure(opd)
+    b = O.Sensor(cfg, 1, L, sodium=([-1500.0, 0.0, 1500.0], [0.25, 0.5, 0.25])).measure(opd)
+    assert np.abs(a["images"] - b["images"]).max() < 1e-14
+
+
+def test_sodium_elongation_axis_points_from_launcher():
+    """Flat wavefront, three equal sub-layers: the spot's long axis is the launcher-to-sub-aperture direction."""
+    cfg = _sodium_cfg(20, spot_fwhm_arcsec=0.2)
+    D = cfg.diameter_m
+    L = [(D / 2, 0.0)]
+    sens = O.Sensor(cfg, 1, L, sodium=([-3000.0, 0.0, 3000.0], [1.0, 1.0, 1.0]))
+    valid = sens.valid_idx
+    xs, ys = G.subap_centres_m(cfg, valid)
+    pick = [int(np.argmin(np.hypot(xs - px, ys - py))) for (px, py) in [(-3.0, 3.0), (0.0, -4.0), (-4.5, 0.0)]]
+    r = sens.measure(np.zeros((1, 1, cfg.pupil_n, cfg.pupil_n)), subset=pick)
+    d = cfg.det_n
+    q = np.arange(d) - (d - 1) / 2
+    for k, i in enumerate(pick):
+        img = r["images"][0, 0, k]
+        m = img.sum()
+        cx = (img * q[None, :]).sum() / m
+        cy = (img * q[:, None]).sum() / m
+        cxx = (img * (q[None, :] - cx) ** 2).sum() / m
+        cyy = (img * (q[:, None] - cy) ** 2).sum() / m
+        cxy = (img * (q[None, :] - cx) * (q[:, None] - cy)).sum() / m
+        axis = 0.5 * math.atan2(2 * cxy, cxx - cyy)
+        psi = math.atan2(ys[i] - L[0][1], xs[i] - L[0][0])
+        diff = (axis - psi + math.pi / 2) % math.pi - math.pi / 2
+        assert abs(diff) < math.radians(3.0), (i, math.degrees(axis), math.degrees(psi))
+        assert cxx + cyy > 0
