@@ -144,6 +144,20 @@ def extras(stream):
                     "mfma_frac_of_2500": flops / (ms * 1e-3) / 2.5e15}
         pl.close()
     out["precision_mfma"] = mm
+    # sodium sub-layer form (3 sub-layers, shared wavefront, noise on): the form of the paper's
+    # 4.5 s per-sensor step; per-sensor ms is the time of the 6-sensor frame / 6
+    pls = shwfs.WfsPlan(G.CFG1, 6, launch, sodium=G.SODIUM)
+    sls = torch.zeros((1, 6, 2, pls.n_valid), device="cuda")
+    opds = opd1.unsqueeze(2).expand(-1, -1, G.SODIUM_NSUB, -1, -1)
+    with torch.cuda.stream(stream):
+        pls.autotune(opd1[:1], sls, reps=10, stream=stream)
+        for k in range(3):
+            pls.measure_sodium(opds[k % 2:k % 2 + 1], sls, seed=1, frame0=k, stream=stream)
+        ms = _time(lambda k: pls.measure_sodium(opds[k % 2:k % 2 + 1], sls, seed=1, frame0=k, stream=stream),
+                   20, stream)
+    out["sodium3_frames_per_s"] = 1e3 / ms
+    out["sodium3_ms_per_sensor_step"] = ms / 6
+    pls.close()
     del opd1
     # 3 NGS, 2x2 sub-apertures of 400 px padded to 512, noise on
     plan4 = shwfs.WfsPlan(G.CFG4_NGS, 3)
@@ -195,6 +209,7 @@ def extras(stream):
     del res, acc
     torch.cuda.synchronize()
     out.update(calibration(stream))
+    out.update(closed_loop(stream))
     out["served"] = served()
     out["served_load_sweep"] = [served(rate_hz=r, duration_s=1.0, warm=False) for r in (4000.0, 8000.0, 16000.0)]
     return out
@@ -227,6 +242,47 @@ def calibration(stream):
     del im
     return {"calibration_modes": int(dm.n_act), "calibration_s": dt, "calibration_frames_per_s": 2 * dm.n_act / dt,
             "calibration_finite": ok}
+
+
+def closed_loop(stream):
+    """Closed-loop step of the 39 m system on the device: 3 DM surfaces from 8219 commands, residuals of the
+    6 LGS directions, the 6-LGS measurement, the 8219 x 59,136 control-matrix product (1.94 GB, synthetic)
+    and the integrator.  Also the product alone against the HBM roofline."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from gen import configs as G
+    from gen import screens as S
+    from paper_1408_0698_amd import loop, shwfs
+    launch = G.launch_positions(G.CFG1, 6)
+    plan = shwfs.WfsPlan(G.CFG1, 6, launch)
+    dms = [(shwfs.DmPlan(800, 4.875e-2, alt, pitch, G.DM_FIELD_RADIUS_ARCSEC, G.DM_COUPLING, G.DM_PATCH), alt)
+           for alt, pitch in G.DMS]
+    n_modes = sum(d.n_act for d, _ in dms)
+    n_slopes = 6 * 2 * plan.n_valid
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(G.SCREEN_SEED)
+    cm = torch.randn((n_modes, n_slopes), device="cuda", generator=gen) * (1e-9 / math.sqrt(n_slopes))
+    scr = torch.from_numpy(S.screen_opd_m(2048, 4.875e-2).astype(np.float32)).cuda()
+    dirs = [(45 * math.cos(math.radians(60 * w)), 45 * math.sin(math.radians(60 * w))) for w in range(6)]
+    lp = loop.ClosedLoop(plan, dms, dirs, scr, cm, 0.5, seed=G.NOISE_SEED)
+    origins = lambda t: [(50 * w, 50 * w + t % 800) for w in range(6)]
+    with torch.cuda.stream(stream):
+        for t in range(3):
+            lp.step(origins(t), t, stream=stream)
+        ms = _time(lambda k: lp.step(origins(k), 3 + k, stream=stream), 20, stream)
+        sl = lp.slopes.view(-1)
+        ms_r = _time(lambda k: lp.recon.step(cm, sl, 0.5, lp.coefs, stream=stream), 20, stream)
+    ok = bool(torch.isfinite(lp.coefs).all().item())
+    nbytes = n_modes * n_slopes * 4 + n_slopes * 4 + 2 * n_modes * 4
+    out = {"loop_step_ms": ms, "loop_steps_per_s": 1e3 / ms, "loop_modes": n_modes, "loop_slopes": n_slopes,
+           "recon_ms": ms_r, "recon_GBps": nbytes / (ms_r * 1e-3) / 1e9, "recon_frac_of_8TBps": nbytes / (ms_r * 1e-3) / 8e12,
+           "loop_finite": ok}
+    del cm, lp
+    torch.cuda.synchronize()
+    return out
 
 
 def served(rate_hz=2000.0, duration_s=3.0, warm=True):

@@ -393,6 +393,30 @@ int shw_residual_opd(const float* d_screen, int32_t screen_rows, int32_t screen_
                      int32_t n_out, const int32_t* scr_origin, const int32_t* dm_origin, float* d_out,
                      int64_t out_pitch, int64_t out_stride, void* hip_stream);
 
+/*
+ * Closed-loop reconstructor and pure integrator (Sec. 3, closed-loop block:
+ * the X and Y slope vectors of every sensor are multiplied by the control
+ * matrix, which gives modal increments that a pure integrator accumulates
+ * into the commands that shape the DMs).
+ *
+ * shw_recon_plan_create: a plan for an n_modes x n_slopes control matrix
+ * (1 <= n_modes <= 2^22, n_slopes >= 1); owns a workspace of
+ * ceil(n_slopes / 4096) * n_modes floats on the current device.
+ *
+ * shw_recon_step: delta[m] = sum_s d_cm[m * ld_cm + s] * d_slopes[s], then
+ * d_coefs[m] += gain * delta[m], for m < n_modes; d_delta (nullable)
+ * receives delta.  d_cm: FP32 device, 16-byte aligned, ld_cm >= n_slopes
+ * and a multiple of 4 (SHW_E_INVALID otherwise).  FP32 products with FP32
+ * sums over chunks of 4096 slopes, the chunk sums added in a fixed order:
+ * the result does not depend on scheduling.  Asynchronous; the plan's
+ * workspace makes concurrent steps of one plan race.
+ */
+typedef struct shw_recon_plan shw_recon_plan;
+int shw_recon_plan_create(int32_t n_modes, int32_t n_slopes, shw_recon_plan** out);
+int shw_recon_step(shw_recon_plan* plan, const float* d_cm, int64_t ld_cm, const float* d_slopes, float gain,
+                   float* d_coefs, float* d_delta, void* hip_stream);
+int shw_recon_plan_destroy(shw_recon_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

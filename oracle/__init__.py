@@ -22,7 +22,7 @@ are listed in ``READINGS`` and in the design notes.  Parts with no anchor
 outside this package (the physical realism of the LGS spot) are "parity
 unpinned": only self-consistency with the readings is checked.
 """
-from . import geometry, philox, wfs, psf, dm, calib  # noqa: F401
+from . import geometry, philox, wfs, psf, dm, calib, loop  # noqa: F401
 
 READINGS = {
     "O1": "binary pupil, pixel-centre test, linear obstruction ratio",
@@ -36,4 +36,6 @@ READINGS = {
     "O9": "thresholded centre of gravity, zero slopes and a flag when nothing is left",
     "O11": "fftshift-centred PSF normalised by (sum A)^2; Strehl = on-axis sample",
     "O12": "Gaussian influence functions, integer-pixel DM and screen shifts",
+    "O13": "sodium sub-layers: point-source wavefront of each beam height against the focus height",
+    "O14": "closed loop: actuator modes, coefs += gain * CM s, push-pull columns (s+ - s-) / 2a",
 }

@@ -18,6 +18,7 @@
 #include "internal.h"
 #include "psf_internal.h"
 #include "dm_internal.h"
+#include "recon_internal.h"
 #include "big_internal.h"
 #include "mfma_internal.h"
 
@@ -1126,5 +1127,60 @@ extern "C" int shw_push_pull(const float* d_slopes, int32_t n_modes, int32_t n_s
   if ((n_modes + 31) / 32 > 65535) return fail(SHW_E_INVALID, "n_modes %d too large", n_modes);
   hipError_t e = launch_push_pull(d_slopes, n_modes, n_slopes, scale, d_im, ld_im, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "shw_push_pull launch");
+  return ok();
+}
+
+// ---------------------------------------------------------------- closed-loop reconstructor
+
+struct shw_recon_plan {
+  int32_t n_modes = 0, n_slopes = 0, n_chunks = 0;
+  int device = 0;
+  float* d_partial = nullptr;  // [n_chunks][n_modes]
+};
+
+extern "C" int shw_recon_plan_create(int32_t n_modes, int32_t n_slopes, shw_recon_plan** out) {
+  if (!out) return fail(SHW_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (n_modes < 1 || n_modes > (1 << 22)) return fail(SHW_E_INVALID, "n_modes %d outside [1, 2^22]", n_modes);
+  if (n_slopes < 1) return fail(SHW_E_INVALID, "n_slopes %d < 1", n_slopes);
+  auto* p = new shw_recon_plan();
+  p->n_modes = n_modes;
+  p->n_slopes = n_slopes;
+  p->n_chunks = recon_chunks(n_slopes);
+  hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = hipMalloc(&p->d_partial, sizeof(float) * (size_t)p->n_chunks * n_modes);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "reconstructor workspace");
+  }
+  *out = p;
+  return ok();
+}
+
+extern "C" int shw_recon_step(shw_recon_plan* p, const float* d_cm, int64_t ld_cm, const float* d_slopes, float gain,
+                              float* d_coefs, float* d_delta, void* stream) {
+  if (!p) return fail(SHW_E_INVALID, "plan is NULL");
+  if (!d_cm || !d_slopes || !d_coefs) return fail(SHW_E_INVALID, "NULL argument");
+  if (ld_cm < p->n_slopes || ld_cm % 4 != 0)
+    return fail(SHW_E_INVALID, "ld_cm %lld must be >= n_slopes %d and a multiple of 4", (long long)ld_cm,
+                p->n_slopes);
+  if (reinterpret_cast<uintptr_t>(d_cm) % 16 != 0) return fail(SHW_E_INVALID, "d_cm must be 16-byte aligned");
+  if (!is_fin(gain)) return fail(SHW_E_INVALID, "gain must be finite");
+  hipError_t e = launch_recon_partial(d_cm, ld_cm, p->n_modes, p->n_slopes, d_slopes, p->d_partial,
+                                      (hipStream_t)stream);
+  if (e == hipSuccess)
+    e = launch_recon_integrate(p->d_partial, p->n_chunks, p->n_modes, gain, d_coefs, d_delta, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "shw_recon_step launch");
+  return ok();
+}
+
+extern "C" int shw_recon_plan_destroy(shw_recon_plan* p) {
+  if (!p) return ok();
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != p->device) (void)hipSetDevice(p->device);
+  if (p->d_partial) (void)hipFree(p->d_partial);
+  if (cur != p->device) (void)hipSetDevice(cur);
+  delete p;
   return ok();
 }

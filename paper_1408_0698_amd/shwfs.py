@@ -90,6 +90,9 @@ _sig = {
     "shw_dm_influence_opd": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64,
                                        C.c_int64, _P]),
     "shw_push_pull": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_float, _P, C.c_int64, _P]),
+    "shw_recon_plan_create": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(_P)]),
+    "shw_recon_step": (C.c_int, [_P, _P, C.c_int64, _P, C.c_float, _P, _P, _P]),
+    "shw_recon_plan_destroy": (C.c_int, [_P]),
     "shw_residual_opd": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.POINTER(C.c_void_p),
                                    C.POINTER(C.c_int32), C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32), _P, C.c_int64, C.c_int64, _P]),
@@ -367,6 +370,31 @@ def residual_opd(screen, surfaces, pupil_n, scr_origin, dm_origin, out, stream=N
                                  pupil_n, n_out, so, do, _ptr(out), out.stride(1), out.stride(0),
                                  _stream_ptr(stream)), "shw_residual_opd")
     return out
+
+
+class ReconPlan:
+    """Control-matrix product and pure integrator of the closed loop."""
+
+    def __init__(self, n_modes, n_slopes):
+        h = C.c_void_p()
+        _check(_lib.shw_recon_plan_create(n_modes, n_slopes, C.byref(h)), "shw_recon_plan_create")
+        self._h = h
+        self.n_modes = n_modes
+        self.n_slopes = n_slopes
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.shw_recon_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def step(self, cm, slopes, gain, coefs, delta=None, stream=None):
+        """coefs += gain * cm @ slopes; cm float32 device [n_modes][ld] (rows contiguous), slopes [n_slopes]."""
+        _check(_lib.shw_recon_step(self._h, _ptr(cm), cm.stride(0), _ptr(slopes), gain, _ptr(coefs), _ptr(delta),
+                                   _stream_ptr(stream)), "shw_recon_step")
+        return coefs
 
 
 def counter_add(d_counter, inc=1, stream=None):
