@@ -23,8 +23,11 @@ if ROOT not in sys.path:
 # nominal FFT flops of one 40x40 complex 2-D transform: 5 N^2 log2(N^2); three per sub-aperture
 FLOP_PER_SUBAP = 3 * 5 * 40 * 40 * math.log2(40 * 40)
 PEAK_FP32_TFLOPS = 157.3
+# launch variants of the 40-point shapes whose measurement is two kernels (fused stages up to the
+# detector, then noise and centroid); the roofline time covers both
+DETECTOR_SPLIT_VARIANTS = (6, 7, 8)
 CSRC = os.path.join(ROOT, "paper_1408_0698_amd", "csrc")
-TRAFFIC = os.path.join(ROOT, "profiles", "wfs_fused_lgs39m_traffic.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "wfs_measure_lgs39m_traffic.json")
 
 
 def kernel_source_hash():
@@ -352,7 +355,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    variant = 0
+    variant = plan.variant
     tuned = None
     if not args.no_autotune:
         import tempfile
@@ -404,7 +407,8 @@ def main():
                        "per": f"launch of {B} frame(s), HIP events on the launch stream"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(B),
-                     "kernel": "wfs_fused_kernel<10,40,40,16,lgs>",
+                     "kernel": f"sh_wfs_measure launch variant {variant}: wfs_fused_kernel<10,40,40,16,lgs>"
+                               + (" + det_noise_kernel<16>" if variant in DETECTOR_SPLIT_VARIANTS else ""),
                      "avg_launch_ms": avg_launch_ms},
         "launch_variant": variant,
         "autotune_ms_per_variant": tuned["ms_per_launch"] if tuned else None,

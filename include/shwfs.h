@@ -243,14 +243,20 @@ int shw_wfs_plan_destroy(shw_wfs_plan* plan);
  * Launch variants and autotuning (batching form: every sub-aperture of every
  * sensor of every frame in one launch).  A plan has 1..n compiled launch
  * variants of its fused kernel (register/occupancy target, one-shot or
- * persistent grid); they give bitwise identical results.  Variant 0 is the
- * default.  shw_wfs_plan_autotune times every variant on the given inputs
+ * persistent grid, row transforms whole or split over lane pairs, noise and
+ * centroid in the fused kernel or in a second kernel over the detector
+ * values kept in a plan-owned workspace).  Variants with the same row
+ * transform give bitwise identical results; the two row-transform families
+ * differ by FP32 rounding (about 1e-7 of an image).  The 40-point shapes
+ * start on variant 7 (whole rows, persistent, detector split), the others on
+ * variant 0.  shw_wfs_plan_autotune times every variant on the given inputs
  * (reps launches each after two warm-up launches, HIP events on the stream;
  * synchronous), selects the fastest and returns its index in *best and the
  * per-variant milliseconds per launch in ms (nullable, n entries).
  */
 int shw_wfs_plan_variant_count(const shw_wfs_plan* plan, int32_t* n);
 int shw_wfs_plan_set_variant(shw_wfs_plan* plan, int32_t variant);
+int shw_wfs_plan_get_variant(const shw_wfs_plan* plan, int32_t* variant);
 int shw_wfs_plan_autotune(shw_wfs_plan* plan, const float* d_opd_m, int64_t row_pitch, int64_t wfs_stride,
                           int64_t frame_stride, int32_t n_frames, float* d_slopes, int32_t reps, void* hip_stream,
                           int32_t* best, float* ms);

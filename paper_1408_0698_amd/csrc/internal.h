@@ -42,6 +42,12 @@ struct WfsLaunch {
   int64_t sub_stride;          // OPD elements between the sub-layer wavefronts of a sensor (0: shared)
   const double* sub_coef;      // [n_sub][2] = (c_j waves / pixel^2, weight_j)
   const double* launch_px;     // [n_wfs][2] launcher (x, y) in pupil pixels from the axis
+  // detector split: variants that end the fused kernel at the detector values write them to
+  // det_ws[(item - item0) * det_n^2 + pixel] and run noise and centroid in a second kernel,
+  // over chunks of at most det_ws_items items starting at item0
+  float* det_ws;
+  int64_t det_ws_items;
+  int64_t item0;
 };
 
 // Shape of a compiled fused kernel.
@@ -55,6 +61,12 @@ bool wfs_shape_supported(const WfsShape& s);
 
 // Number of compiled launch variants of a shape (0 if unsupported).
 int wfs_variant_count(const WfsShape& s);
+
+// Variant a new plan starts with (the autotuner may pick another).
+int wfs_default_variant(const WfsShape& s);
+
+// True if the variant ends the fused kernel at the detector (needs a.det_ws).
+bool wfs_variant_needs_det_ws(const WfsShape& s, int variant);
 
 // Launch the fused kernel for a.total work items. Returns the HIP error.
 hipError_t launch_wfs_fused(const WfsShape& s, int variant, const WfsLaunch& a, hipStream_t st);

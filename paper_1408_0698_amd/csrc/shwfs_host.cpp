@@ -78,6 +78,9 @@ struct shw_wfs_plan {
   // sodium sub-layers: [n_sub][2] (phase coefficient, weight) then [n_wfs][2] launcher pixels
   int32_t n_sub = 0;
   double* d_sub = nullptr;
+  // detector values of the detector-split launch variants: det_ws_items items of det_n^2 floats
+  float* d_det_ws = nullptr;
+  int64_t det_ws_items = 0;
 };
 
 
@@ -300,6 +303,7 @@ extern "C" int shw_wfs_plan_destroy(shw_wfs_plan* p) {
   if (p->d_mfma_tab) (void)hipFree(p->d_mfma_tab);
   if (p->d_Jr) (void)hipFree(p->d_Jr);
   if (p->d_sub) (void)hipFree(p->d_sub);
+  if (p->d_det_ws) (void)hipFree(p->d_det_ws);
   if (cur != p->device) (void)hipSetDevice(cur);
   delete p;
   return ok();
@@ -399,7 +403,21 @@ static int plan_create(const shw_wfs_config* cfg, int32_t n_wfs, const shw_lgs_g
     }
     p->bytes += t.size() * sizeof(uint16_t);
   }
+  if (p->prec == SHW_PREC_FP32 && wfs_variant_needs_det_ws(p->shape, wfs_variant_count(p->shape) - 1)) {
+    // one chunk holds a frame of every sensor, at least 16384 and at most 65536 items
+    int64_t items = (int64_t)n_wfs * p->n_valid;
+    items = items < 16384 ? 16384 : (items > 65536 ? 65536 : items);
+    const size_t nb = sizeof(float) * (size_t)items * cfg->det_n * cfg->det_n;
+    e = hipMalloc(&p->d_det_ws, nb);
+    if (e != hipSuccess) {
+      shw_wfs_plan_destroy(p);
+      return hip_fail(e, "detector workspace");
+    }
+    p->det_ws_items = items;
+    p->bytes += nb;
+  }
   p->big = p->prec == SHW_PREC_FP32 && !wfs_shape_supported(p->shape);
+  if (p->prec == SHW_PREC_FP32 && !p->big) p->variant = wfs_default_variant(p->shape);
   if (p->big) {
     // about 128 MB of row intermediates per chunk, at least one sensor frame
     const int64_t per_item = (int64_t)p->npx * cfg->fft_n * (int64_t)sizeof(float2);
@@ -499,6 +517,8 @@ static WfsLaunch base_launch(const shw_wfs_plan* p) {
   a.n_sub = p->n_sub;
   a.sub_coef = p->d_sub;
   a.launch_px = p->d_sub ? p->d_sub + 2 * p->n_sub : nullptr;
+  a.det_ws = p->d_det_ws;
+  a.det_ws_items = p->det_ws_items;
   return a;
 }
 
@@ -972,6 +992,12 @@ extern "C" int sh_wfs_measure_devframe(shw_wfs_plan* p, const float* d_opd_m, in
 extern "C" int shw_wfs_plan_variant_count(const shw_wfs_plan* p, int32_t* n) {
   if (!p || !n) return fail(SHW_E_INVALID, "NULL argument");
   *n = p->big ? 1 : wfs_variant_count(p->shape);
+  return ok();
+}
+
+extern "C" int shw_wfs_plan_get_variant(const shw_wfs_plan* p, int32_t* variant) {
+  if (!p || !variant) return fail(SHW_E_INVALID, "NULL argument");
+  *variant = p->variant;
   return ok();
 }
 

@@ -27,7 +27,10 @@
 //     transform, inverse column transform: J = I (*) k.
 //  C  rebin along the column in registers, then along the row via LDS.
 //  D  photometry, Poisson + read noise, threshold, centre of gravity with
-//     FP64 sums, reduced over the item's lanes.
+//     FP64 sums, reduced over the item's lanes.  Detector-split variants
+//     stop after C, write the detector values to a workspace and run D in
+//     det_noise_kernel: one wavefront per item and few registers, so many
+//     more waves hide the latency of the Philox chains.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -62,6 +65,46 @@ __device__ __forceinline__ float pair_swap(float v) {
 }
 __device__ __forceinline__ float2 pair_swap(float2 v) { return make_float2(pair_swap(v.x), pair_swap(v.y)); }
 
+// Per-item output buffers and noise key: from the work list, or the launch-wide layout.
+struct ItemRef {
+  int f, w, i;
+  const float* opd_f;
+  int64_t row_pitch, wfs_stride;
+  float* slopes_fw;  // this frame and sensor: [2][n_valid]
+  float* images_it;  // this item: [det][det] or null
+  uint32_t key0, key1, frame;
+};
+
+__device__ __forceinline__ ItemRef resolve_item(const WfsLaunch& a, int64_t it, uint32_t frame_base, int npix) {
+  ItemRef r;
+  const int64_t per_frame = (int64_t)a.n_wfs * a.n_valid;
+  r.f = (int)(it / per_frame);
+  const int rem = (int)(it - (int64_t)r.f * per_frame);
+  r.w = rem / a.n_valid;
+  r.i = rem - r.w * a.n_valid;
+  r.key0 = a.key0;
+  r.key1 = a.key1;
+  r.frame = frame_base + (uint32_t)r.f;
+  if (a.list) {
+    const FrameWork& fw = a.list[r.f];
+    r.opd_f = fw.opd;
+    r.row_pitch = fw.row_pitch;
+    r.wfs_stride = fw.wfs_stride;
+    r.slopes_fw = fw.slopes + (int64_t)r.w * 2 * a.n_valid;
+    r.images_it = fw.images ? fw.images + ((int64_t)r.w * a.n_valid + r.i) * npix : nullptr;
+    r.key0 = (uint32_t)(fw.seed & 0xFFFFFFFFu);
+    r.key1 = (uint32_t)(fw.seed >> 32);
+    r.frame = (uint32_t)fw.frame;
+  } else {
+    r.opd_f = a.opd + (int64_t)r.f * a.frame_stride;
+    r.row_pitch = a.row_pitch;
+    r.wfs_stride = a.wfs_stride;
+    r.slopes_fw = a.slopes + ((int64_t)r.f * a.n_wfs + r.w) * 2 * a.n_valid;
+    r.images_it = a.images ? a.images + it * npix : nullptr;
+  }
+  return r;
+}
+
 // LDS floats per item for the given shape.
 template <int NPX, int FFT_N, int CONV_N, int DET_N>
 struct FusedLayout {
@@ -77,7 +120,7 @@ struct FusedLayout {
 };
 
 // One group of SPB work items (one block's worth).  Every lane of the block calls it.
-template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, bool SPLIT, bool SUB>
+template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, bool SPLIT, bool SUB, bool DSPLIT>
 __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t group, uint32_t frame_base,
                                                 float* __restrict__ s_re, float* __restrict__ s_im) {
   constexpr int L = CONV_N;                  // lanes per item
@@ -101,43 +144,21 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   const int tid = threadIdx.x;
   const int s = tid / L;
   const int l = tid - s * L;
-  const int64_t item = group * SPB + s;
+  const int64_t item = a.item0 + group * SPB + s;
   const bool active = item < a.total;
-  const int64_t per_frame = (int64_t)a.n_wfs * a.n_valid;
-  const int64_t it = active ? item : 0;
-  const int f = (int)(it / per_frame);
-  const int rem = (int)(it - (int64_t)f * per_frame);
-  const int w = rem / a.n_valid;
-  const int i = rem - w * a.n_valid;
+  const int64_t it = active ? item : a.item0;
+  const ItemRef ref = resolve_item(a, it, frame_base, DET_N * DET_N);
+  const int w = ref.w, i = ref.i;
   const int sidx = a.valid_idx[i];
   const int sa = sidx / a.n_subap;
   const int sb = sidx - sa * a.n_subap;
   float* re = s_re + s * PLANE;
   float* im = s_im + s * PLANE;
-  // per-frame buffers and noise key: from the work list, or the launch-wide layout
-  const float* opd_f;
-  int64_t row_pitch, wfs_stride;
-  float* slopes_fw;   // this frame and sensor: [2][n_valid]
-  float* images_it;   // this item: [det][det] or null
-  uint32_t key0 = a.key0, key1 = a.key1;
-  uint32_t frame = frame_base + (uint32_t)f;
-  if (a.list) {
-    const FrameWork& fw = a.list[f];
-    opd_f = fw.opd;
-    row_pitch = fw.row_pitch;
-    wfs_stride = fw.wfs_stride;
-    slopes_fw = fw.slopes + (int64_t)w * 2 * a.n_valid;
-    images_it = fw.images ? fw.images + ((int64_t)w * a.n_valid + i) * (DET_N * DET_N) : nullptr;
-    key0 = (uint32_t)(fw.seed & 0xFFFFFFFFu);
-    key1 = (uint32_t)(fw.seed >> 32);
-    frame = (uint32_t)fw.frame;
-  } else {
-    opd_f = a.opd + (int64_t)f * a.frame_stride;
-    row_pitch = a.row_pitch;
-    wfs_stride = a.wfs_stride;
-    slopes_fw = a.slopes + ((int64_t)f * a.n_wfs + w) * 2 * a.n_valid;
-    images_it = a.images ? a.images + it * (DET_N * DET_N) : nullptr;
-  }
+  const float* opd_f = ref.opd_f;
+  const int64_t row_pitch = ref.row_pitch, wfs_stride = ref.wfs_stride;
+  float* slopes_fw = ref.slopes_fw;
+  float* images_it = ref.images_it;
+  const uint32_t key0 = ref.key0, key1 = ref.key1, frame = ref.frame;
 
   float col[CONV_N];
 #pragma unroll
@@ -399,6 +420,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
     sy += (double)((float)p - CD) * t;
   };
   float* det_area = im + DETA;
+  if constexpr (DSPLIT) det_area = a.det_ws + (it - a.item0) * NPIX;
   if (active && l < DET_N * G) {
     const int p = l / G;
     const int q0 = QB * (l - p * G);
@@ -417,6 +439,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       det_area[p * DET_N + q0 + j] = det;
     }
   }
+  if constexpr (DSPLIT) return;  // noise and centroid: det_noise_kernel
   __syncthreads();
   // every lane of the item takes pixels l, l + L, ...; two at a time so that their Philox
   // chains interleave
@@ -485,7 +508,8 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
 
 // One-shot grid (one group per block) or persistent grid (blocks stride over the groups).
 // The frame number of the first frame comes from a.frame0_dev when set (graph replay).
-template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, int WPE, bool PERSIST, bool SPLIT, bool SUB>
+template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, int WPE, bool PERSIST, bool SPLIT, bool SUB,
+          bool DSPLIT>
 __global__ __launch_bounds__(SPB * CONV_N) __attribute__((amdgpu_waves_per_eu(WPE))) void wfs_fused_kernel(
     const WfsLaunch a) {
   using LY = FusedLayout<NPX, FFT_N, CONV_N, DET_N>;
@@ -493,13 +517,61 @@ __global__ __launch_bounds__(SPB * CONV_N) __attribute__((amdgpu_waves_per_eu(WP
   __shared__ __align__(16) float s_im[SPB * LY::PLANE];
   const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev : a.frame0;
   if constexpr (PERSIST) {
-    const int64_t ngroups = (a.total + SPB - 1) / SPB;
+    const int64_t ngroups = (a.total - a.item0 + SPB - 1) / SPB;
     for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
-      wfs_fused_group<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, SPLIT, SUB>(a, g, frame_base, s_re, s_im);
+      wfs_fused_group<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, SPLIT, SUB, DSPLIT>(a, g, frame_base, s_re, s_im);
       __syncthreads();
     }
   } else {
-    wfs_fused_group<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, SPLIT, SUB>(a, blockIdx.x, frame_base, s_re, s_im);
+    wfs_fused_group<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, SPLIT, SUB, DSPLIT>(a, blockIdx.x, frame_base, s_re, s_im);
+  }
+}
+
+// Stage D of the detector-split variants: one wavefront per item, each lane takes pixels
+// l, l + 64, ... of the item's detector values in det_ws.  The same per-pixel noise (keyed by
+// pixel, sub-aperture and frame), threshold and FP64 centroid sums as the fused stage.
+template <int DET_N>
+__global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
+  constexpr int NPIX = DET_N * DET_N;
+  constexpr float CD = 0.5f * (float)(DET_N - 1);
+  const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev : a.frame0;
+  const int lane = threadIdx.x & 63;
+  const int64_t item = a.item0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= a.total) return;  // whole wavefronts leave together
+  const ItemRef ref = resolve_item(a, item, frame_base, NPIX);
+  const float* det = a.det_ws + (item - a.item0) * NPIX;
+  const uint32_t gsub = (uint32_t)(ref.w * a.n_valid + ref.i);
+  const bool need_rng = a.noise && a.ph_scale > 0.0f;
+  double s0 = 0.0, sx = 0.0, sy = 0.0;
+#pragma unroll
+  for (int j = 0; j < (NPIX + 63) / 64; ++j) {
+    const int pix = lane + 64 * j;
+    if (pix < NPIX) {
+      float img = det[pix];
+      if (a.ph_scale > 0.0f) {
+        const float lam = a.ph_scale * img;
+        img = need_rng ? noisy_pixel(lam, a.ron, (uint32_t)pix, gsub, ref.frame, ref.key0, ref.key1) : lam;
+      }
+      if (ref.images_it) ref.images_it[pix] = img;
+      const int p = pix / DET_N;
+      const int q = pix - p * DET_N;
+      const double t = (double)fmaxf(img - a.thr, 0.0f);
+      s0 += t;
+      sx += (double)((float)q - CD) * t;
+      sy += (double)((float)p - CD) * t;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    s0 += __shfl_xor(s0, o, 64);
+    sx += __shfl_xor(sx, o, 64);
+    sy += __shfl_xor(sy, o, 64);
+  }
+  if (lane == 0) {
+    const bool empty = !(s0 > 0.0);
+    ref.slopes_fw[ref.i] = empty ? 0.0f : (float)(sx / s0);
+    ref.slopes_fw[a.n_valid + ref.i] = empty ? 0.0f : (float)(sy / s0);
+    if (a.flags && !a.list) a.flags[item] = empty ? 1 : 0;
   }
 }
 
@@ -511,31 +583,47 @@ constexpr int items_per_block(int lanes) {
 }
 
 template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, int WPE, bool PERSIST, bool SPLIT,
-          bool SUB = false>
-static hipError_t launch_variant(const WfsLaunch& a, hipStream_t st) {
-  auto kern = wfs_fused_kernel<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, WPE, PERSIST, SPLIT, SUB>;
-  const int64_t groups = (a.total + SPB - 1) / SPB;
-  if (groups <= 0) return hipSuccess;
-  int64_t blocks = groups;
+          bool SUB = false, bool DSPLIT = false>
+static hipError_t launch_variant(const WfsLaunch& a0, hipStream_t st) {
+  auto kern = wfs_fused_kernel<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, WPE, PERSIST, SPLIT, SUB, DSPLIT>;
+  int64_t resident = 0;
   if constexpr (PERSIST) {
-    static int resident = 0;  // blocks resident on the device for this kernel (per process, device 0 shape)
-    if (resident == 0) {
+    static int per_dev = 0;  // blocks resident on the device for this kernel (per process, device 0 shape)
+    if (per_dev == 0) {
       int dev = 0, cus = 0, per_cu = 0;
       hipError_t e = hipGetDevice(&dev);
       if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
       if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, SPB * CONV_N, 0);
       if (e != hipSuccess) return e;
-      resident = (per_cu > 0 ? per_cu : 1) * cus;
+      per_dev = (per_cu > 0 ? per_cu : 1) * cus;
     }
-    if (blocks > resident) blocks = resident;
+    resident = per_dev;
   }
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(SPB * CONV_N), 0, st, a);
-  return hipGetLastError();
+  // detector-split variants run in chunks of the workspace; the others in one launch
+  const int64_t step = DSPLIT ? a0.det_ws_items : a0.total - a0.item0;
+  if (DSPLIT && (!a0.det_ws || step <= 0)) return hipErrorInvalidValue;
+  for (int64_t i0 = a0.item0; i0 < a0.total; i0 += step) {
+    WfsLaunch a = a0;
+    a.item0 = i0;
+    a.total = a0.total - i0 < step ? a0.total : i0 + step;
+    const int64_t groups = (a.total - a.item0 + SPB - 1) / SPB;
+    const int64_t blocks = PERSIST && groups > resident ? resident : groups;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(SPB * CONV_N), 0, st, a);
+    if constexpr (DSPLIT) {
+      const int64_t nb = (a.total - a.item0 + 3) / 4;
+      hipLaunchKernelGGL(det_noise_kernel<DET_N>, dim3((unsigned)nb), dim3(256), 0, st, a);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Launch variants of the 40-point shapes: (row transforms whole or split over lane pairs,
-// waves-per-EU target, persistent grid).  Variant 0 is the default.
-constexpr int kTunedVariants = 6;
+// waves-per-EU target, persistent grid, noise in the fused kernel or after it).  Variant 0
+// is the default; variants from kFirstDetSplit on end the fused kernel at the detector.
+constexpr int kTunedVariants = 9;
+constexpr int kFirstDetSplit = 6;
 
 // Sub-layer kernels: whole or split row transforms, waves-per-EU target 1.
 constexpr int kSubVariants = 2;
@@ -558,6 +646,9 @@ static hipError_t launch_one(int variant, const WfsLaunch& a, hipStream_t st) {
       case 3: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 4, false, true>(a, st);
       case 4: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, true, false>(a, st);
       case 5: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 4, true, false>(a, st);
+      case 6: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, false, false, true>(a, st);
+      case 7: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 4, true, false, false, true>(a, st);
+      case 8: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, true, false, true>(a, st);
       default: return hipErrorInvalidValue;
     }
   } else {
@@ -593,6 +684,15 @@ int wfs_variant_count(const WfsShape& s) {
   if (!wfs_shape_supported(s)) return 0;
   if (s.sub) return kSubVariants;
   return (s.conv_n == 40 && s.det_n == 16) ? kTunedVariants : 1;
+}
+
+int wfs_default_variant(const WfsShape& s) {
+  // measured on the 6-LGS frame: detector split + persistent grid is the fastest with and without noise
+  return (!s.sub && s.conv_n == 40 && s.det_n == 16) ? 7 : 0;
+}
+
+bool wfs_variant_needs_det_ws(const WfsShape& s, int variant) {
+  return !s.sub && s.conv_n == 40 && s.det_n == 16 && variant >= kFirstDetSplit;
 }
 
 hipError_t launch_wfs_fused(const WfsShape& s, int variant, const WfsLaunch& a, hipStream_t st) {

@@ -65,6 +65,7 @@ _sig = {
     "shw_wfs_plan_destroy": (C.c_int, [_P]),
     "shw_wfs_plan_variant_count": (C.c_int, [_P, C.POINTER(C.c_int32)]),
     "shw_wfs_plan_set_variant": (C.c_int, [_P, C.c_int32]),
+    "shw_wfs_plan_get_variant": (C.c_int, [_P, C.POINTER(C.c_int32)]),
     "shw_wfs_plan_autotune": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int64, C.c_int32, _P, C.c_int32, _P,
                                         C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
     "sh_wfs_measure_devframe": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_uint64, _P,
@@ -200,7 +201,7 @@ class WfsPlan:
         return self._h
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:   # the module may be torn down first
             _lib.shw_wfs_plan_destroy(self._h)
             self._h = None
 
@@ -217,6 +218,12 @@ class WfsPlan:
         n = C.c_int32(0)
         _check(_lib.shw_wfs_plan_variant_count(self._h, C.byref(n)), "shw_wfs_plan_variant_count")
         return n.value
+
+    @property
+    def variant(self):
+        v = C.c_int32(0)
+        _check(_lib.shw_wfs_plan_get_variant(self._h, C.byref(v)), "shw_wfs_plan_get_variant")
+        return v.value
 
     def set_variant(self, v):
         _check(_lib.shw_wfs_plan_set_variant(self._h, v), "shw_wfs_plan_set_variant")
@@ -282,7 +289,7 @@ class PsfPlan:
         self.pupil_n = pupil_n
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:   # the module may be torn down first
             _lib.shw_psf_plan_destroy(self._h)
             self._h = None
 
@@ -335,7 +342,7 @@ class DmPlan:
         self.size = size.value
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:   # the module may be torn down first
             _lib.shw_dm_plan_destroy(self._h)
             self._h = None
 
@@ -383,7 +390,7 @@ class ReconPlan:
         self.n_slopes = n_slopes
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:   # the module may be torn down first
             _lib.shw_recon_plan_destroy(self._h)
             self._h = None
 
@@ -416,7 +423,7 @@ class Graph:
         _check(_lib.shw_graph_launch(self._h, _stream_ptr(stream)), "shw_graph_launch")
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:   # the module may be torn down first
             _lib.shw_graph_destroy(self._h)
             self._h = None
 

@@ -22,36 +22,51 @@ def _plan(cfg, n_wfs):
     return shwfs.WfsPlan(cfg, n_wfs, G.launch_positions(cfg, n_wfs) if cfg.lgs else None)
 
 
-def test_variants_are_bitwise_identical(torch_dev):
+# Variants that share the row-transform arithmetic give bitwise-identical results; the lane-pair
+# (split) row transforms round differently (the two real rows of the half spectrum are packed into
+# one complex row), so across the two families the noise-free images agree to FP32 rounding only.
+WHOLE_ROWS = (0, 1, 4, 5, 6, 7)
+SPLIT_ROWS = (2, 3, 8)
+
+
+def _measure_variants(torch, plan, opd, variants, images=True, **kw):
+    out = {}
+    for v in variants:
+        plan.set_variant(v)
+        sl = torch.zeros((opd.shape[0], plan.n_wfs, 2, plan.n_valid), device="cuda")
+        im = (torch.zeros((opd.shape[0], plan.n_wfs, plan.n_valid, 16, 16), device="cuda") if images else None)
+        plan.measure(opd, sl, im, **kw)
+        torch.cuda.synchronize()
+        out[v] = (sl, im)
+    return out
+
+
+def test_variants_agree(torch_dev):
     cfg = G.CFG1.replace(pupil_n=170, n_subap=17)   # 220 valid: ragged last group
     plan = _plan(cfg, 3)
-    assert plan.n_variants == 6
+    assert plan.n_variants == 9
     opd = torch_dev.from_numpy(S.lgs39m_opd(3, 3, pupil_n=170)).cuda()
-    ref = None
-    for v in range(plan.n_variants):
-        plan.set_variant(v)
-        sl = torch_dev.zeros((3, 3, 2, plan.n_valid), device="cuda")
-        im = torch_dev.zeros((3, 3, plan.n_valid, 16, 16), device="cuda")
-        plan.measure(opd, sl, im, seed=7, frame0=40)
-        torch_dev.cuda.synchronize()
-        if ref is None:
-            ref = (sl.clone(), im.clone())
-        else:
-            assert torch_dev.equal(sl, ref[0]) and torch_dev.equal(im, ref[1]), f"variant {v}"
+    out = _measure_variants(torch_dev, plan, opd, range(9), seed=7, frame0=40)
+    for fam in (WHOLE_ROWS, SPLIT_ROWS):
+        for v in fam[1:]:
+            assert torch_dev.equal(out[v][0], out[fam[0]][0]) and torch_dev.equal(out[v][1], out[fam[0]][1]), v
+    quiet = _plan(cfg.replace(flags=0), 3)
+    q = _measure_variants(torch_dev, quiet, opd, (0, 2))
+    a, b = q[0][1].cpu().numpy(), q[2][1].cpu().numpy()
+    scale = abs(a).max(axis=(-1, -2), keepdims=True)
+    assert (abs(a - b) / scale).max() < 1e-6
+    assert (q[0][0] - q[2][0]).abs().max().item() < 1e-5
 
 
 def test_persistent_variant_covers_many_groups(torch_dev):
-    """More groups than resident blocks (full 6-LGS frames x 4): persistent equals one-shot."""
+    """More groups than resident blocks (full 6-LGS frames x 4): persistent equals one-shot; the
+    detector-split variants run the 4 frames in chunks of their workspace."""
     plan = _plan(G.CFG1, 6)
     opd = torch_dev.from_numpy(S.lgs39m_opd(4, 6)).cuda()
-    out = []
-    for v in (0, 4, 5):
-        plan.set_variant(v)
-        sl = torch_dev.zeros((4, 6, 2, plan.n_valid), device="cuda")
-        plan.measure(opd, sl, seed=3, frame0=0)
-        torch_dev.cuda.synchronize()
-        out.append(sl)
-    assert torch_dev.equal(out[0], out[1]) and torch_dev.equal(out[0], out[2])
+    out = _measure_variants(torch_dev, plan, opd, range(9), images=False, seed=3, frame0=0)
+    for fam in (WHOLE_ROWS, SPLIT_ROWS):
+        for v in fam[1:]:
+            assert torch_dev.equal(out[v][0], out[fam[0]][0]), v
 
 
 def test_autotune_selects_a_variant(torch_dev, tmp_path, monkeypatch):
@@ -96,3 +111,25 @@ def test_graph_replay_advances_frames(torch_dev):
         torch.cuda.synchronize()
         assert torch.equal(got[0], ref_sl) and torch.equal(got[1], ref_im), f"replay {k}"
     assert int(counter.item()) == 1004
+
+
+def test_detector_split_work_list_equals_single_calls(torch_dev):
+    """A work list of frames of two plans, run with a detector-split variant, equals per-frame calls."""
+    from paper_1408_0698_amd import shwfs
+    cfg = G.CFG1.replace(pupil_n=130, n_subap=13)
+    plan = _plan(cfg, 6)
+    opd = torch_dev.from_numpy(S.lgs39m_opd(3, 6, pupil_n=130)).cuda()
+    ref = []
+    for f in range(3):
+        sl = torch_dev.zeros((1, 6, 2, plan.n_valid), device="cuda")
+        im = torch_dev.zeros((1, 6, plan.n_valid, 16, 16), device="cuda")
+        plan.measure(opd[f:f + 1], sl, im, seed=100 + f, frame0=10 * f)
+        ref.append((sl[0], im[0]))
+    for v in (6, 7):
+        plan.set_variant(v)
+        outs = [(torch_dev.zeros((6, 2, plan.n_valid), device="cuda"),
+                 torch_dev.zeros((6, plan.n_valid, 16, 16), device="cuda")) for _ in range(3)]
+        shwfs.measure_batch([(plan, opd[f], outs[f][0], outs[f][1], 100 + f, 10 * f) for f in range(3)])
+        torch_dev.cuda.synchronize()
+        for f in range(3):
+            assert torch_dev.equal(outs[f][0], ref[f][0]) and torch_dev.equal(outs[f][1], ref[f][1]), (v, f)
