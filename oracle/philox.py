@@ -82,10 +82,15 @@ def log_factorial_f32(k):
     return out.reshape(k.shape).astype(np.float32)
 
 
+# 1/k rounded to FP32 (index 0 unused): the inversion multiplies by it instead of dividing by k
+RCP_F32 = np.array([0.0] + [1.0 / k for k in range(1, 128)], dtype=np.float64).astype(np.float32)
+
+
 def poisson_inversion_f32(lam, u):
     """Sequential-search inversion: smallest k with u <= sum_{j<=k} e^-lam lam^j / j!.
 
-    FP32: p0 = exp(-lam); p_k = (p_{k-1} * lam) / k; F_k = F_{k-1} + p_k.
+    FP32: p0 = exp(-lam); p_k = (p_{k-1} * lam) * r_k with r_k = 1/k rounded to FP32;
+    F_k = F_{k-1} + p_k (reading O8).
     """
     lam = np.asarray(lam, dtype=np.float32)
     u = np.asarray(u, dtype=np.float32)
@@ -96,7 +101,7 @@ def poisson_inversion_f32(lam, u):
     kk = 0
     while np.any(active) and kk < INVERSION_MAX_K:
         kk += 1
-        p = np.where(active, (p * lam) / np.float32(kk), p).astype(np.float32)
+        p = np.where(active, (p * lam) * RCP_F32[kk], p).astype(np.float32)
         F = np.where(active, F + p, F).astype(np.float32)
         k = np.where(active, kk, k)
         active = active & (u > F)

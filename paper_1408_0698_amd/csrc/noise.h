@@ -70,17 +70,63 @@ __device__ __forceinline__ float u01(uint32_t x) {
   return ((float)(x >> 9) + 0.5f) * 1.1920928955078125e-07f;
 }
 
+// 1/k rounded to FP32 (index 0 unused): the inversion multiplies by it instead of dividing.
+struct RcpTable {
+  float v[128];
+  constexpr RcpTable() : v() {
+    for (int k = 1; k < 128; ++k) v[k] = (float)(1.0 / (double)k);
+  }
+};
+__constant__ const RcpTable kRcp = RcpTable();
+constexpr int kInversionMaxK = 100;
+
+// Sequential search: p_0 = exp(-lam), p_k = (p_{k-1} lam) (1/k), F_k = F_{k-1} + p_k; the
+// smallest k with u <= F_k (at most kInversionMaxK).
 __device__ __forceinline__ int poisson_inversion(float lam, float u) {
 #pragma clang fp contract(off)
   float p = expf(-lam);
   float F = p;
   int k = 0;
-  while (u > F && k < 100) {
+  while (u > F && k < kInversionMaxK) {
     ++k;
-    p = (p * lam) / (float)k;
+    p = (p * lam) * kRcp.v[k];
     F = F + p;
   }
   return k;
+}
+
+// NJ independent inversions advanced in lockstep (the same arithmetic as poisson_inversion):
+// the searches of a lane overlap instead of running one after another.  Entries with
+// use[j] false keep k[j] = 0.
+template <int NJ>
+__device__ __forceinline__ void poisson_inversion_n(const float (&lam)[NJ], const float (&u)[NJ],
+                                                    const bool (&use)[NJ], int (&k)[NJ]) {
+#pragma clang fp contract(off)
+  float p[NJ], F[NJ];
+  bool act[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    p[j] = use[j] ? expf(-lam[j]) : 0.0f;
+    F[j] = p[j];
+    k[j] = 0;
+    act[j] = use[j] && u[j] > F[j];
+  }
+#pragma unroll 1
+  for (int kk = 1; kk <= kInversionMaxK; ++kk) {
+    bool any = false;
+    const float r = kRcp.v[kk];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      if (act[j]) {
+        p[j] = (p[j] * lam[j]) * r;
+        F[j] = F[j] + p[j];
+        k[j] = kk;
+        act[j] = u[j] > F[j];
+      }
+      any = any || act[j];
+    }
+    if (!any) break;
+  }
 }
 
 __device__ __forceinline__ int poisson_ptrs(float lam, float u0, float v0, uint32_t pix, uint32_t gsub,

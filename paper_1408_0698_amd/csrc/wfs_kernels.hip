@@ -105,17 +105,20 @@ __device__ __forceinline__ ItemRef resolve_item(const WfsLaunch& a, int64_t it, 
   return r;
 }
 
-// LDS floats per item for the given shape.
-template <int NPX, int FFT_N, int CONV_N, int DET_N>
+// LDS floats per item for the given shape.  Split row transforms keep N/2 spectrum rows (rows 0
+// and N/2 packed), whole ones N/2 + 1; the detector-split variants keep no detector stage in LDS.
+template <int NPX, int FFT_N, int CONV_N, int DET_N, bool SPLIT, bool DSPLIT>
 struct FusedLayout {
   static constexpr int HN = CONV_N / 2;
   static constexpr int ST = CONV_N + 1;
-  static constexpr int ROWS0 = NPX > HN + 1 ? NPX : HN + 1;
+  static constexpr int HROWS = SPLIT ? HN : HN + 1;
+  static constexpr int ROWS0 = NPX > HROWS ? NPX : HROWS;
   static constexpr int ROWS = ROWS0 > DET_N ? ROWS0 : DET_N;
   static constexpr int NPIX = DET_N * DET_N;
   static constexpr int DETA = NPIX + 1;                 // detector values, after the queue and its count
   static constexpr int RED = (DETA + NPIX + 1) & ~1;
-  static constexpr int PLANE0 = ROWS * ST > RED + 6 * CONV_N ? ROWS * ST : RED + 6 * CONV_N;
+  static constexpr int DNEED = DSPLIT ? NPIX + 1 : RED + 6 * CONV_N;
+  static constexpr int PLANE0 = ROWS * ST > DNEED ? ROWS * ST : DNEED;
   static constexpr int PLANE = (PLANE0 + 1) & ~1;
 };
 
@@ -130,7 +133,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   constexpr int ST = CONV_N + 1;             // odd LDS row stride (floats)
   constexpr int ROWS0 = NPX > HN ? NPX : HN;
   constexpr int ROWS = ROWS0 > DET_N ? ROWS0 : DET_N;
-  using LY = FusedLayout<NPX, FFT_N, CONV_N, DET_N>;
+  using LY = FusedLayout<NPX, FFT_N, CONV_N, DET_N, SPLIT, DSPLIT>;
   constexpr int NPIX = LY::NPIX;
   // stage D reuses the imaginary plane: a queue of NPIX pixel indices, its count, then 3 L doubles
   constexpr int QCOUNT = NPIX;
@@ -318,20 +321,33 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       }
       const float* kh = a.khat + ((int64_t)(w * a.n_valid + i) * H) * CONV_N + h * HN;
       if (r == 0) {
-        // packed row: Y = X (K0 + KH)/2 + conj(X[-c]) (K0 - KH)/2
-        float2 mir[HN];
-#pragma unroll
-        for (int c = 0; c < HN; ++c) mir[c] = pair_swap(x[c]);
-        float2 y[HN];
-#pragma unroll
-        for (int c = 0; c < HN; ++c) {
-          const float2 xm = cconj(c == 0 ? x[0] : mir[HN - c]);
+        // packed row: Y[c] = X[c] (K0 + KH)/2 + conj(X[-c]) (K0 - KH)/2, where X[-c] for c > 0 is the
+        // partner lane's X[N/2 - c]; updated in place pair by pair (c, N/2 - c), both partners' values
+        // read before either is written, so that few registers are live at once
+        auto kab = [&](int c, float& ka, float& kb) {
           const float k0 = kh[c], kn = kh[HN * CONV_N + c];
-          const float ka = 0.5f * (k0 + kn), kb = 0.5f * (k0 - kn);
-          y[c] = cadd(cscale(x[c], ka), cscale(xm, kb));
+          ka = 0.5f * (k0 + kn);
+          kb = 0.5f * (k0 - kn);
+        };
+        {
+          float ka, kb;
+          kab(0, ka, kb);
+          x[0] = cadd(cscale(x[0], ka), cscale(cconj(x[0]), kb));
         }
 #pragma unroll
-        for (int c = 0; c < HN; ++c) x[c] = y[c];
+        for (int c = 1; c <= HN / 2; ++c) {
+          const int d = HN - c;
+          const float2 mc = pair_swap(x[c]), md = pair_swap(x[d]);
+          float ka, kb;
+          kab(c, ka, kb);
+          const float2 yc = cadd(cscale(x[c], ka), cscale(cconj(md), kb));
+          if (d != c) {
+            float kad, kbd;
+            kab(d, kad, kbd);
+            x[d] = cadd(cscale(x[d], kad), cscale(cconj(mc), kbd));
+          }
+          x[c] = yc;
+        }
       } else {
 #pragma unroll
         for (int c = 0; c < HN; ++c) x[c] = cscale(x[c], kh[r * CONV_N + c]);
@@ -353,24 +369,25 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
     {
       // B3: real J from the half spectrum: y = IFFT_{N/2}(C), C[k] = (Z[k] + conj Z[N/2-k])
       //     + i W^-k (Z[k] - conj Z[N/2-k]); J[2m] = Re y[m], J[2m+1] = Im y[m]
-      float2 zz[HN + 1];
-      if constexpr (SPLIT) {
-        zz[0] = make_float2(re[l], 0.0f);
-        zz[HN] = make_float2(im[l], 0.0f);
-      } else {
-        zz[0] = make_float2(re[l], 0.0f);
-        zz[HN] = make_float2(re[HN * ST + l], 0.0f);
-      }
-#pragma unroll
-      for (int k = 1; k < HN; ++k) zz[k] = make_float2(re[k * ST + l], im[k * ST + l]);
+      // computed in place pair by pair (k, N/2 - k): Z[k] and Z[N/2 - k] give C[k] and C[N/2 - k]
       float2 y[HN];
+      const float z0 = re[l];
+      const float zh = SPLIT ? im[l] : re[HN * ST + l];
 #pragma unroll
-      for (int k = 0; k < HN; ++k) {
-        const float2 zk = zz[k];
-        const float2 zc = cconj(zz[HN - k]);
+      for (int k = 1; k < HN; ++k) y[k] = make_float2(re[k * ST + l], im[k * ST + l]);
+      auto cfold = [](float2 zk, float2 zm, int k) {
+        const float2 zc = cconj(zm);
         const float2 e = cadd(zk, zc);
         const float2 d = twiddle_mul<CONV_N, 1>(csub(zk, zc), k);
-        y[k] = make_float2(e.x - d.y, e.y + d.x);
+        return make_float2(e.x - d.y, e.y + d.x);
+      };
+      y[0] = cfold(make_float2(z0, 0.0f), make_float2(zh, 0.0f), 0);
+#pragma unroll
+      for (int k = 1; k <= HN / 2; ++k) {
+        const int m = HN - k;
+        const float2 a = y[k], b = y[m];
+        y[k] = cfold(a, b, k);
+        if (m != k) y[m] = cfold(b, a, m);
       }
       RegFFT<HN, 1>::run(y);
 #pragma unroll
@@ -512,7 +529,7 @@ template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, int WPE,
           bool DSPLIT>
 __global__ __launch_bounds__(SPB * CONV_N) __attribute__((amdgpu_waves_per_eu(WPE))) void wfs_fused_kernel(
     const WfsLaunch a) {
-  using LY = FusedLayout<NPX, FFT_N, CONV_N, DET_N>;
+  using LY = FusedLayout<NPX, FFT_N, CONV_N, DET_N, SPLIT, DSPLIT>;
   __shared__ __align__(16) float s_re[SPB * LY::PLANE];
   __shared__ __align__(16) float s_im[SPB * LY::PLANE];
   const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev : a.frame0;
@@ -542,15 +559,33 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   const float* det = a.det_ws + (item - a.item0) * NPIX;
   const uint32_t gsub = (uint32_t)(ref.w * a.n_valid + ref.i);
   const bool need_rng = a.noise && a.ph_scale > 0.0f;
+  constexpr int NJ = (NPIX + 63) / 64;
+  float v[NJ], u[NJ];
+  bool small[NJ];
+  uint4 wd[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int pix = lane + 64 * j;
+    v[j] = pix < NPIX ? det[pix] : 0.0f;
+    if (a.ph_scale > 0.0f) v[j] = a.ph_scale * v[j];  // expected electrons
+    wd[j] = need_rng ? philox4x32_10(make_uint4(0u, (uint32_t)pix, gsub, ref.frame), ref.key0, ref.key1)
+                     : make_uint4(0u, 0u, 0u, 0u);
+    u[j] = u01(wd[j].x);
+    small[j] = need_rng && pix < NPIX && v[j] > 0.0f && v[j] < 10.0f;
+  }
+  int k[NJ];
+  poisson_inversion_n<NJ>(v, u, small, k);
   double s0 = 0.0, sx = 0.0, sy = 0.0;
 #pragma unroll
-  for (int j = 0; j < (NPIX + 63) / 64; ++j) {
+  for (int j = 0; j < NJ; ++j) {
     const int pix = lane + 64 * j;
     if (pix < NPIX) {
-      float img = det[pix];
-      if (a.ph_scale > 0.0f) {
-        const float lam = a.ph_scale * img;
-        img = need_rng ? noisy_pixel(lam, a.ron, (uint32_t)pix, gsub, ref.frame, ref.key0, ref.key1) : lam;
+      float img = v[j];
+      if (need_rng) {
+        const int kp = v[j] >= 10.0f ? poisson_ptrs(v[j], u[j], u01(wd[j].y), (uint32_t)pix, gsub, ref.frame,
+                                                    ref.key0, ref.key1)
+                                     : k[j];
+        img = (float)kp + a.ron * read_noise_z(wd[j]);
       }
       if (ref.images_it) ref.images_it[pix] = img;
       const int p = pix / DET_N;
@@ -620,9 +655,9 @@ static hipError_t launch_variant(const WfsLaunch& a0, hipStream_t st) {
 }
 
 // Launch variants of the 40-point shapes: (row transforms whole or split over lane pairs,
-// waves-per-EU target, persistent grid, noise in the fused kernel or after it).  Variant 0
-// is the default; variants from kFirstDetSplit on end the fused kernel at the detector.
-constexpr int kTunedVariants = 9;
+// waves-per-EU target, persistent grid, noise in the fused kernel or after it).  Variants
+// from kFirstDetSplit on end the fused kernel at the detector.
+constexpr int kTunedVariants = 11;
 constexpr int kFirstDetSplit = 6;
 
 // Sub-layer kernels: whole or split row transforms, waves-per-EU target 1.
@@ -649,6 +684,8 @@ static hipError_t launch_one(int variant, const WfsLaunch& a, hipStream_t st) {
       case 6: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, false, false, true>(a, st);
       case 7: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 4, true, false, false, true>(a, st);
       case 8: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, true, false, true>(a, st);
+      case 9: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 4, true, true, false, true>(a, st);
+      case 10: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, true, true, false, true>(a, st);
       default: return hipErrorInvalidValue;
     }
   } else {
@@ -688,7 +725,7 @@ int wfs_variant_count(const WfsShape& s) {
 
 int wfs_default_variant(const WfsShape& s) {
   // measured on the 6-LGS frame: detector split + persistent grid is the fastest with and without noise
-  return (!s.sub && s.conv_n == 40 && s.det_n == 16) ? 7 : 0;
+  return (!s.sub && s.conv_n == 40 && s.det_n == 16) ? 9 : 0;
 }
 
 bool wfs_variant_needs_det_ws(const WfsShape& s, int variant) {

@@ -26,7 +26,7 @@ def _plan(cfg, n_wfs):
 # (split) row transforms round differently (the two real rows of the half spectrum are packed into
 # one complex row), so across the two families the noise-free images agree to FP32 rounding only.
 WHOLE_ROWS = (0, 1, 4, 5, 6, 7)
-SPLIT_ROWS = (2, 3, 8)
+SPLIT_ROWS = (2, 3, 8, 9, 10)
 
 
 def _measure_variants(torch, plan, opd, variants, images=True, **kw):
@@ -44,9 +44,9 @@ def _measure_variants(torch, plan, opd, variants, images=True, **kw):
 def test_variants_agree(torch_dev):
     cfg = G.CFG1.replace(pupil_n=170, n_subap=17)   # 220 valid: ragged last group
     plan = _plan(cfg, 3)
-    assert plan.n_variants == 9
+    assert plan.n_variants == 11
     opd = torch_dev.from_numpy(S.lgs39m_opd(3, 3, pupil_n=170)).cuda()
-    out = _measure_variants(torch_dev, plan, opd, range(9), seed=7, frame0=40)
+    out = _measure_variants(torch_dev, plan, opd, range(11), seed=7, frame0=40)
     for fam in (WHOLE_ROWS, SPLIT_ROWS):
         for v in fam[1:]:
             assert torch_dev.equal(out[v][0], out[fam[0]][0]) and torch_dev.equal(out[v][1], out[fam[0]][1]), v
@@ -63,7 +63,7 @@ def test_persistent_variant_covers_many_groups(torch_dev):
     detector-split variants run the 4 frames in chunks of their workspace."""
     plan = _plan(G.CFG1, 6)
     opd = torch_dev.from_numpy(S.lgs39m_opd(4, 6)).cuda()
-    out = _measure_variants(torch_dev, plan, opd, range(9), images=False, seed=3, frame0=0)
+    out = _measure_variants(torch_dev, plan, opd, range(11), images=False, seed=3, frame0=0)
     for fam in (WHOLE_ROWS, SPLIT_ROWS):
         for v in fam[1:]:
             assert torch_dev.equal(out[v][0], out[fam[0]][0]), v
