@@ -10,10 +10,25 @@
 // transforms.  The fftshift centring (-1)^(x+y) is folded into the FP64
 // phase as (x + y)/2 waves.
 //
-// Row pass: 8 rows per block of 320 lanes, intermediate T[f][y][u] (complex
-// FP32).  Column pass: 8 columns per block, frames accumulated in registers,
-// one read-modify-write of the accumulator per call; the on-axis sample of
-// each frame is the Strehl ratio.
+// Every line (a row in the row pass, a column in the column pass) is
+// transformed by 40 lane pairs (q, h).  First step: lane (n2 = q, h) runs the
+// 20-point transform of residue h of the pruned 40-point transform over n1,
+// giving Y[k1] for k1 = 2k + h, and applies its four-step twiddles.  After a
+// transpose through LDS, lane (k1 = q, h) holds the samples n2 = 2t + h of
+// row k1, and the 40-point transform over n2 is split radix-2 across the
+// pair: 20-point transforms, twiddle, butterfly with the partner through
+// DPP; lane h ends with outputs k2 = c + 20 h.  A lane thus keeps 20 complex
+// values instead of 40, which keeps the kernels free of register spills.
+//
+// Row pass: 4 rows per block of 320 lanes; each lane of a pair computes half
+// of the row's phases and swaps them with its partner.  The intermediate is
+// stored in column blocks of 8: element (frame f, row y, column u) of T sits
+// at ((f * M/8 + u/8) * pupil_n + y) * 8 + u % 8, so that rows write whole
+// 64-byte runs and the 8 columns of a column block are one contiguous region.
+// Column pass: 4 columns per block, the two halves of a column block launched
+// 8 blocks apart (the same XCD), frames accumulated in registers, one
+// read-modify-write of the accumulator per call; the on-axis sample of each
+// frame is the Strehl ratio.
 #include <hip/hip_runtime.h>
 
 #include "psf_internal.h"
@@ -24,83 +39,98 @@ namespace shw {
 namespace {
 
 constexpr int kM = 1600;
-constexpr int kQ = 40;        // M = kQ * kQ
-constexpr int kNZ = kM / 2 / kQ;  // non-zero n1 (20)
-constexpr int kLines = 8;      // transforms per block
-constexpr int kST = kQ + 1;    // odd LDS stride
+constexpr int kQ = 40;            // M = kQ * kQ
+constexpr int kNZ = kM / 2 / kQ;  // non-zero n1 (20) = outputs per lane of the second step
+constexpr int kP = 2 * kQ;        // lanes per line
+constexpr int kLines = 4;         // lines per block
+constexpr int kST = kQ + 1;       // odd LDS stride
+constexpr int kCB = 8;            // columns per block of the intermediate
 
-// Y[k1] *= W_M^(n2 k1) = exp(-2 pi i n2 k1 / M); exact angles every 8 steps, products in between.
-__device__ __forceinline__ void four_step_twiddle(float2* Y, int n2) {
-  float ss, cs;
-  sincospif(-2.0f * (float)n2 / (float)kM, &ss, &cs);
-  const float2 step = make_float2(cs, ss);
+// Offset of element (star-frame sf, row y, column u) of the intermediate.
+__device__ __forceinline__ int64_t t_index(int64_t sf, int pupil_n, int y, int u) {
+  return ((sf * (kM / kCB) + (u >> 3)) * pupil_n + y) * kCB + (u & (kCB - 1));
+}
+
+// Value of the same register in the partner lane t ^ 1 (DPP quad permutation 1, 0, 3, 2).
+__device__ __forceinline__ float pair_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float2 pair_swap(float2 v) { return make_float2(pair_swap(v.x), pair_swap(v.y)); }
+
+// One M-point transform of a line with at most M/2 non-zero inputs v[n1] (sample 40 n1 + q),
+// on lane pair (q, h) of the line; pl is the line's LDS plane.  On return lane (q, h) holds
+// X[q + 40 (c + 20 h)] in x[c], c < 20.  Every lane of the block must call it.
+__device__ __forceinline__ void line_transform(const float2 (&v)[kNZ], float2 (&x)[kNZ], float* pl, int q, int h) {
+  float2 z[kNZ];
 #pragma unroll
-  for (int a = 0; a < kQ / 8; ++a) {
-    const int m = (n2 * 8 * a) % kM;
-    float sb, cb;
-    sincospif(-2.0f * (float)m / (float)kM, &sb, &cb);
-    float2 t = make_float2(cb, sb);
+  for (int n1 = 0; n1 < kNZ; ++n1) z[n1] = h ? twiddle_mul<kQ, -1>(v[n1], n1) : v[n1];
+  RegFFT<kNZ, -1>::run(z);
+  // four-step twiddle W_M^(n2 k1), k1 = 2k + h: exact every 4 steps, products of W_M^(2 n2) between
+  {
+    const int n2 = q;
+    const float sr = -(float)((2 * n2) % kM) / (float)kM;
+    const float2 step = make_float2(__builtin_amdgcn_cosf(sr), __builtin_amdgcn_sinf(sr));
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int k1 = 8 * a + b;
-      if (k1 != 0) Y[k1] = cmul(Y[k1], t);
-      t = cmul(t, step);
+    for (int b = 0; b < kNZ / 4; ++b) {
+      const float rev = -(float)((n2 * (8 * b + h)) % kM) / (float)kM;
+      float2 t = make_float2(__builtin_amdgcn_cosf(rev), __builtin_amdgcn_sinf(rev));
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        z[4 * b + e] = cmul(z[4 * b + e], t);
+        t = cmul(t, step);
+      }
     }
   }
-}
-
-// First step on lane n2: inputs v[n1] (n1 < kNZ, zero beyond), output Y[k1], k1 < 40, twiddled.
-__device__ __forceinline__ void first_step(const float2* v, float2* Y, int n2) {
+  // transpose: lane (n2, h) holds Y[2k + h]; lane (k1, h) takes samples n2 = 2t + h
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    float2 z[kNZ];
+  for (int k = 0; k < kNZ; ++k) pl[(2 * k + h) * kST + q] = z[k].x;
+  __syncthreads();
 #pragma unroll
-    for (int n1 = 0; n1 < kNZ; ++n1) z[n1] = twiddle_mul<kQ, -1>(v[n1], n1 * r);
-    RegFFT<kNZ, -1>::run(z);
+  for (int t = 0; t < kNZ; ++t) x[t].x = pl[q * kST + 2 * t + h];
+  __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kNZ; ++k) Y[2 * k + r] = z[k];
+  for (int k = 0; k < kNZ; ++k) pl[(2 * k + h) * kST + q] = z[k].y;
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < kNZ; ++t) x[t].y = pl[q * kST + 2 * t + h];
+  __syncthreads();
+  RegFFT<kNZ, -1>::run(x);
+  if (h) {
+#pragma unroll
+    for (int c = 0; c < kNZ; ++c) x[c] = twiddle_mul<kQ, -1>(x[c], c);
   }
-  four_step_twiddle(Y, n2);
-}
-
-// Transpose one 40 x 40 complex tile of a line through one float plane: lane n2 holds
-// Y[k1]; afterwards lane k1 holds z[n2] = Y_(lane n2)[k1].  Real parts, then imaginary.
-__device__ __forceinline__ void transpose_tile(float* pl, const float2* Y, float2* z, int lane) {
 #pragma unroll
-  for (int k1 = 0; k1 < kQ; ++k1) pl[k1 * kST + lane] = Y[k1].x;
-  __syncthreads();
-#pragma unroll
-  for (int n2 = 0; n2 < kQ; ++n2) z[n2].x = pl[lane * kST + n2];
-  __syncthreads();
-#pragma unroll
-  for (int k1 = 0; k1 < kQ; ++k1) pl[k1 * kST + lane] = Y[k1].y;
-  __syncthreads();
-#pragma unroll
-  for (int n2 = 0; n2 < kQ; ++n2) z[n2].y = pl[lane * kST + n2];
-  __syncthreads();
+  for (int c = 0; c < kNZ; ++c) {
+    const float2 o = pair_swap(x[c]);
+    // h = 0: X[c] = E + W O (partner holds W O); h = 1: X[c + 20] = E (partner) - W O
+    x[c] = h ? csub(o, x[c]) : cadd(x[c], o);
+  }
 }
 
 }  // namespace
 
-__global__ __launch_bounds__(kLines * kQ) void psf_rows_kernel(const PsfLaunch a, int64_t f0, int nf, int64_t nrows,
+__global__ __launch_bounds__(kLines * kP) void psf_rows_kernel(const PsfLaunch a, int64_t f0, int nf, int64_t nrows,
                                                                float2* __restrict__ T) {
   __shared__ float s_pl[kLines * kQ * kST];
   const int tid = threadIdx.x;
-  const int line = tid / kQ, lane = tid - line * kQ;
+  const int line = tid / kP, j = tid - line * kP;
+  const int q = j >> 1, h = j & 1;
   const int64_t row = (int64_t)blockIdx.x * kLines + line;  // (star * nf + frame - f0) * pupil_n + y
   const bool active = row < nrows;
   const int64_t sf = active ? row / a.pupil_n : 0;
   const int y = active ? (int)(row - sf * a.pupil_n) : 0;
   const int64_t star = sf / nf, fl = sf - star * nf;
   float* pl = s_pl + line * kQ * kST;
+  // field samples x = 40 n1 + q; lane h computes those with n1 = h (mod 2), then the pair swaps
   float2 v[kNZ];
   {
     const float* src = a.opd + star * a.star_stride + (f0 + fl) * a.frame_stride + (int64_t)y * a.row_pitch;
     const float by = (float)y + 0.5f - a.half_n;
     const float by2 = by * by;
 #pragma unroll
-    for (int n1 = 0; n1 < kNZ; ++n1) {
-      const int x = kQ * n1 + lane;
+    for (int i = 0; i < kNZ / 2; ++i) {
+      const int n1 = 2 * i + h;
+      const int x = kQ * n1 + q;
       float2 e = make_float2(0.0f, 0.0f);
       if (active && x < a.pupil_n) {
         const float bx = (float)x + 0.5f - a.half_n;
@@ -108,63 +138,64 @@ __global__ __launch_bounds__(kLines * kQ) void psf_rows_kernel(const PsfLaunch a
         if (r2 <= a.r2_outer && r2 >= a.r2_inner) {
           double wv = (double)src[x] * a.inv_lambda + 0.5 * (double)(x + y);
           wv -= floor(wv);
-          float sn, c;
-          sincospif(2.0f * (float)wv, &sn, &c);
-          e = make_float2(c, sn);
+          // hardware sine and cosine take revolutions: exp(2 pi i wv) after the FP64 reduction
+          const float fw = (float)wv;
+          e = make_float2(__builtin_amdgcn_cosf(fw), __builtin_amdgcn_sinf(fw));
         }
       }
-      v[n1] = e;
+      const float2 o = pair_swap(e);  // the partner's sample 2 i + (1 - h)
+      v[2 * i] = h ? o : e;
+      v[2 * i + 1] = h ? e : o;
     }
   }
-  float2 Y[kQ];
-  first_step(v, Y, lane);
-  float2 z[kQ];
-  transpose_tile(pl, Y, z, lane);
-  RegFFT<kQ, -1>::run(z);
+  float2 x[kNZ];
+  line_transform(v, x, pl, q, h);
   if (active) {
-    float2* dst = T + row * kM;
 #pragma unroll
-    for (int k2 = 0; k2 < kQ; ++k2) dst[lane + kQ * k2] = z[k2];
+    for (int c = 0; c < kNZ; ++c) T[t_index(sf, a.pupil_n, y, q + kQ * (c + kNZ * h))] = x[c];
   }
 }
 
-__global__ __launch_bounds__(kLines * kQ) void psf_cols_kernel(const PsfLaunch a, int64_t f0, int nf,
+// Column pass.  The two halves of a column block (4 columns each) go to blocks 8 apart in launch
+// order, which the dispatcher places on the same XCD, so each 64-byte run is fetched into one L2.
+__global__ __launch_bounds__(kLines * kP) void psf_cols_kernel(const PsfLaunch a, int64_t f0, int nf,
                                                                const float2* __restrict__ T, float* __restrict__ acc,
                                                                float* __restrict__ strehl) {
   __shared__ float s_pl[kLines * kQ * kST];
   const int tid = threadIdx.x;
-  const int line = tid / kQ, lane = tid - line * kQ;
-  const int star = blockIdx.x / (kM / kLines);
-  const int u = (blockIdx.x - star * (kM / kLines)) * kLines + line;  // column of this star
+  const int line = tid / kP, j = tid - line * kP;
+  const int q = j >> 1, h = j & 1;
+  const int b = blockIdx.x;
+  const int group = (b >> 4) * 8 + (b & 7);  // column block of 8 over all stars
+  const int half = (b >> 3) & 1;
+  const int star = group / (kM / kCB);
+  const int u = (group - star * (kM / kCB)) * kCB + half * kLines + line;  // column of this star
   float* pl = s_pl + line * kQ * kST;
-  float sum[kQ];
+  float sum[kNZ];
 #pragma unroll
-  for (int k2 = 0; k2 < kQ; ++k2) sum[k2] = 0.0f;
+  for (int c = 0; c < kNZ; ++c) sum[c] = 0.0f;
   for (int fl = 0; fl < nf; ++fl) {
-    const float2* src = T + ((int64_t)star * nf + fl) * a.pupil_n * kM + u;
+    const int64_t sf = (int64_t)star * nf + fl;
     float2 v[kNZ];
 #pragma unroll
     for (int n1 = 0; n1 < kNZ; ++n1) {
-      const int y = kQ * n1 + lane;
-      v[n1] = y < a.pupil_n ? src[(int64_t)y * kM] : make_float2(0.0f, 0.0f);
+      const int yy = kQ * n1 + q;
+      v[n1] = yy < a.pupil_n ? T[t_index(sf, a.pupil_n, yy, u)] : make_float2(0.0f, 0.0f);
     }
-    float2 Y[kQ];
-    first_step(v, Y, lane);
-    float2 z[kQ];
-    transpose_tile(pl, Y, z, lane);
-    RegFFT<kQ, -1>::run(z);
+    float2 x[kNZ];
+    line_transform(v, x, pl, q, h);
 #pragma unroll
-    for (int k2 = 0; k2 < kQ; ++k2) {
-      const float p = (z[k2].x * z[k2].x + z[k2].y * z[k2].y) * a.inv_norm;
-      sum[k2] += p;
-      // on-axis sample: v = u = M/2, i.e. lane 0, k2 = 20 of column M/2
-      if (strehl && u == kM / 2 && lane == 0 && k2 == kM / 2 / kQ) strehl[(int64_t)star * a.n_frames + f0 + fl] = p;
+    for (int c = 0; c < kNZ; ++c) {
+      const float p = (x[c].x * x[c].x + x[c].y * x[c].y) * a.inv_norm;
+      sum[c] += p;
+      // on-axis sample: v = u = M/2, i.e. k1 = 0, k2 = 20 (c = 0, h = 1) of column M/2
+      if (strehl && u == kM / 2 && q == 0 && h == 1 && c == 0) strehl[(int64_t)star * a.n_frames + f0 + fl] = p;
     }
   }
 #pragma unroll
-  for (int k2 = 0; k2 < kQ; ++k2) {
-    const int v = lane + kQ * k2;
-    acc[star * a.acc_stride + (int64_t)v * kM + u] += sum[k2];
+  for (int c = 0; c < kNZ; ++c) {
+    const int vv = q + kQ * (c + kNZ * h);
+    acc[star * a.acc_stride + (int64_t)vv * kM + u] += sum[c];
   }
 }
 
@@ -174,10 +205,11 @@ hipError_t launch_psf_chunk(const PsfLaunch& a, int n_stars, int64_t f0, int nf,
                             float* strehl, hipStream_t st) {
   const int64_t nrows = (int64_t)n_stars * nf * a.pupil_n;
   const int64_t rb = (nrows + kLines - 1) / kLines;
-  hipLaunchKernelGGL(psf_rows_kernel, dim3((unsigned)rb), dim3(kLines * kQ), 0, st, a, f0, nf, nrows, T);
+  hipLaunchKernelGGL(psf_rows_kernel, dim3((unsigned)rb), dim3(kLines * kP), 0, st, a, f0, nf, nrows, T);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(psf_cols_kernel, dim3((unsigned)(n_stars * (kM / kLines))), dim3(kLines * kQ), 0, st, a, f0, nf,
+  static_assert((kM / kLines) % 16 == 0, "column blocks pair up 8 apart");
+  hipLaunchKernelGGL(psf_cols_kernel, dim3((unsigned)(n_stars * (kM / kLines))), dim3(kLines * kP), 0, st, a, f0, nf,
                      (const float2*)T, acc, strehl);
   return hipGetLastError();
 }
