@@ -130,9 +130,9 @@ __global__ __launch_bounds__(kBlock) void big_rows_kernel(const BigLaunch a, int
         const double ramp = (double)((kN - 1) * (x + y)) / (2.0 * kN);
         double wv = (double)src[x] * a.inv_lambda + ramp;
         wv -= floor(wv);
-        float sn, cs;
-        sincospif(2.0f * (float)wv, &sn, &cs);
-        e = make_float2(cs, sn);
+        // hardware sine and cosine take revolutions: exp(2 pi i wv) after the FP64 reduction
+        const float fw = (float)wv;
+        e = make_float2(__builtin_amdgcn_cosf(fw), __builtin_amdgcn_sinf(fw));
       }
     }
     v[q] = e;

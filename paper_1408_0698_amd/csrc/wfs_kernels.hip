@@ -178,6 +178,8 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
     const float* src = opd_f + (int64_t)w * wfs_stride + (int64_t)prow * row_pitch + (int64_t)sb * NPX;
     const float ay = (float)prow + 0.5f - a.half_n;
     const float ay2 = ay * ay;
+    const double rb = (double)((FFT_N - 1) * y) * (1.0 / (2.0 * FFT_N));
+    const double rx = (double)(FFT_N - 1 - 2 * k2) * (1.0 / (2.0 * FFT_N));
     double c_sub = 0.0, lx = 0.0, qy = 0.0;
     if constexpr (SUB) {
       src += (int64_t)sl * a.sub_stride;
@@ -192,9 +194,8 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       const float ax = (float)(sb * NPX + x) + 0.5f - a.half_n;
       const float r2 = ax * ax + ay2;
       const bool lit = (r2 <= a.r2_outer) && (r2 >= a.r2_inner);
-      // waves: OPD / lambda + centring ramp (FFT_N-1)(x+y)/(2 FFT_N) - x k2 / FFT_N
-      const double ramp = (double)((FFT_N - 1) * (x + y)) / (2.0 * FFT_N) - (double)(x * k2) / (double)FFT_N;
-      double wv = (double)src[x] * a.inv_lambda + ramp;
+      // waves: OPD / lambda + centring ramp (FFT_N-1)(x+y)/(2 FFT_N) - x k2 / FFT_N = rb + x rx
+      double wv = (double)src[x] * a.inv_lambda + ((double)x * rx + rb);
       if constexpr (SUB) {
         const double dx = (double)ax - lx;
         wv += qy + c_sub * dx * dx;
@@ -302,67 +303,72 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
           im[l * ST + u] = z[u].y;
         }
       }
-    } else if (active) {
-      // B2: lane pair (r, h): forward row transform, multiply by K^, inverse row transform
+    } else {
+      // B2: lane pair (r, h): forward row transform, multiply by K^, inverse row transform.  The
+      // packed row 0 mixes X[c] with conj X[-c] of the partner: its spectrum goes through LDS row
+      // 0 and each lane of the item computes one of its 40 outputs.
       const int r = l >> 1, h = l & 1;
       float2 x[HN];
+      const float* kh_item = a.khat + ((int64_t)(w * a.n_valid + i) * H) * CONV_N;
+      if (active) {
 #pragma unroll
-      for (int u = 0; u < HN; ++u) x[u] = make_float2(re[r * ST + 2 * u + h], im[r * ST + 2 * u + h]);
-      RegFFT<HN, -1>::run(x);
-      if (h) {
+        for (int u = 0; u < HN; ++u) x[u] = make_float2(re[r * ST + 2 * u + h], im[r * ST + 2 * u + h]);
+        RegFFT<HN, -1>::run(x);
+        if (h) {
 #pragma unroll
-        for (int c = 0; c < HN; ++c) x[c] = twiddle_mul<CONV_N, -1>(x[c], c);
-      }
-#pragma unroll
-      for (int c = 0; c < HN; ++c) {
-        const float2 o = pair_swap(x[c]);
-        // h = 0: X[c] = E + W O (partner holds W O); h = 1: X[c + N/2] = E (partner) - W O
-        x[c] = h ? csub(o, x[c]) : cadd(x[c], o);
-      }
-      const float* kh = a.khat + ((int64_t)(w * a.n_valid + i) * H) * CONV_N + h * HN;
-      if (r == 0) {
-        // packed row: Y[c] = X[c] (K0 + KH)/2 + conj(X[-c]) (K0 - KH)/2, where X[-c] for c > 0 is the
-        // partner lane's X[N/2 - c]; updated in place pair by pair (c, N/2 - c), both partners' values
-        // read before either is written, so that few registers are live at once
-        auto kab = [&](int c, float& ka, float& kb) {
-          const float k0 = kh[c], kn = kh[HN * CONV_N + c];
-          ka = 0.5f * (k0 + kn);
-          kb = 0.5f * (k0 - kn);
-        };
-        {
-          float ka, kb;
-          kab(0, ka, kb);
-          x[0] = cadd(cscale(x[0], ka), cscale(cconj(x[0]), kb));
+          for (int c = 0; c < HN; ++c) x[c] = twiddle_mul<CONV_N, -1>(x[c], c);
         }
 #pragma unroll
-        for (int c = 1; c <= HN / 2; ++c) {
-          const int d = HN - c;
-          const float2 mc = pair_swap(x[c]), md = pair_swap(x[d]);
-          float ka, kb;
-          kab(c, ka, kb);
-          const float2 yc = cadd(cscale(x[c], ka), cscale(cconj(md), kb));
-          if (d != c) {
-            float kad, kbd;
-            kab(d, kad, kbd);
-            x[d] = cadd(cscale(x[d], kad), cscale(cconj(mc), kbd));
+        for (int c = 0; c < HN; ++c) {
+          const float2 o = pair_swap(x[c]);
+          // h = 0: X[c] = E + W O (partner holds W O); h = 1: X[c + N/2] = E (partner) - W O
+          x[c] = h ? csub(o, x[c]) : cadd(x[c], o);
+        }
+        if (r == 0) {
+#pragma unroll
+          for (int c = 0; c < HN; ++c) {
+            re[c + h * HN] = x[c].x;
+            im[c + h * HN] = x[c].y;
           }
-          x[c] = yc;
+        } else {
+#pragma unroll
+          for (int c = 0; c < HN; ++c) x[c] = cscale(x[c], kh_item[r * CONV_N + h * HN + c]);
         }
-      } else {
-#pragma unroll
-        for (int c = 0; c < HN; ++c) x[c] = cscale(x[c], kh[r * CONV_N + c]);
       }
-      // inverse: h = 0 -> even outputs from Y[c] + Y[c+N/2]; h = 1 -> odd outputs from (Y[c] - Y[c+N/2]) W^-c
-#pragma unroll
-      for (int c = 0; c < HN; ++c) {
-        const float2 o = pair_swap(x[c]);
-        x[c] = h ? twiddle_mul<CONV_N, 1>(csub(o, x[c]), c) : cadd(x[c], o);
+      __syncthreads();
+      // packed row: Y[j] = X[j] (K0 + KH)/2 + conj(X[-j]) (K0 - KH)/2, lane l takes j = l
+      float2 yl = make_float2(0.0f, 0.0f);
+      if (active) {
+        const int m = l == 0 ? 0 : CONV_N - l;
+        const float2 xj = make_float2(re[l], im[l]);
+        const float2 xm = cconj(make_float2(re[m], im[m]));
+        const float k0 = kh_item[l], kn = kh_item[HN * CONV_N + l];
+        const float ka = 0.5f * (k0 + kn), kb = 0.5f * (k0 - kn);
+        yl = cadd(cscale(xj, ka), cscale(xm, kb));
       }
-      RegFFT<HN, 1>::run(x);
+      __syncthreads();
+      if (active) {
+        re[l] = yl.x;
+        im[l] = yl.y;
+      }
+      __syncthreads();
+      if (active) {
+        if (r == 0) {
 #pragma unroll
-      for (int u = 0; u < HN; ++u) {
-        re[r * ST + 2 * u + h] = x[u].x;
-        im[r * ST + 2 * u + h] = x[u].y;
+          for (int c = 0; c < HN; ++c) x[c] = make_float2(re[c + h * HN], im[c + h * HN]);
+        }
+        // inverse: h = 0 -> even outputs from Y[c] + Y[c+N/2]; h = 1 -> odd outputs from (Y[c] - Y[c+N/2]) W^-c
+#pragma unroll
+        for (int c = 0; c < HN; ++c) {
+          const float2 o = pair_swap(x[c]);
+          x[c] = h ? twiddle_mul<CONV_N, 1>(csub(o, x[c]), c) : cadd(x[c], o);
+        }
+        RegFFT<HN, 1>::run(x);
+#pragma unroll
+        for (int u = 0; u < HN; ++u) {
+          re[r * ST + 2 * u + h] = x[u].x;
+          im[r * ST + 2 * u + h] = x[u].y;
+        }
       }
     }
     __syncthreads();
