@@ -248,8 +248,8 @@ int shw_wfs_plan_destroy(shw_wfs_plan* plan);
  * values kept in a plan-owned workspace).  Variants with the same row
  * transform give bitwise identical results; the two row-transform families
  * differ by FP32 rounding (about 1e-7 of an image).  The 40-point shapes
- * start on variant 9 (split rows, persistent, detector split), the others on
- * variant 0.  shw_wfs_plan_autotune times every variant on the given inputs
+ * start on variant 9 (split rows, persistent, detector split), sodium
+ * sub-layer plans on variant 2 (the same arrangement), the others on variant 0.  shw_wfs_plan_autotune times every variant on the given inputs
  * (reps launches each after two warm-up launches, HIP events on the stream;
  * synchronous), selects the fastest and returns its index in *best and the
  * per-variant milliseconds per launch in ms (nullable, n entries).

@@ -557,10 +557,15 @@ template <int DET_N>
 __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   constexpr int NPIX = DET_N * DET_N;
   constexpr float CD = 0.5f * (float)(DET_N - 1);
+  // pixels with mean >= 10 (rejection sampler) queued per wavefront: pixel, mean, the two
+  // uniforms of trial 0 and the read-noise deviate, so that the sampler runs once for up to 64
+  // of them
+  __shared__ int q_pix[4][NPIX];
+  __shared__ float q_val[4][4][NPIX];
   const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev : a.frame0;
-  const int lane = threadIdx.x & 63;
-  const int64_t item = a.item0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (item >= a.total) return;  // whole wavefronts leave together
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t item = a.item0 + (int64_t)blockIdx.x * 4 + wave;
+  if (item >= a.total) return;  // whole wavefronts leave together; no block barrier below
   const ItemRef ref = resolve_item(a, item, frame_base, NPIX);
   const float* det = a.det_ws + (item - a.item0) * NPIX;
   const uint32_t gsub = (uint32_t)(ref.w * a.n_valid + ref.i);
@@ -582,25 +587,43 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   int k[NJ];
   poisson_inversion_n<NJ>(v, u, small, k);
   double s0 = 0.0, sx = 0.0, sy = 0.0;
+  auto accumulate = [&](int pix, float img) {
+    if (ref.images_it) ref.images_it[pix] = img;
+    const int p = pix / DET_N;
+    const int q = pix - p * DET_N;
+    const double t = (double)fmaxf(img - a.thr, 0.0f);
+    s0 += t;
+    sx += (double)((float)q - CD) * t;
+    sy += (double)((float)p - CD) * t;
+  };
+  const uint64_t below = (1ull << lane) - 1ull;
+  int nq = 0;
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     const int pix = lane + 64 * j;
-    if (pix < NPIX) {
-      float img = v[j];
-      if (need_rng) {
-        const int kp = v[j] >= 10.0f ? poisson_ptrs(v[j], u[j], u01(wd[j].y), (uint32_t)pix, gsub, ref.frame,
-                                                    ref.key0, ref.key1)
-                                     : k[j];
-        img = (float)kp + a.ron * read_noise_z(wd[j]);
-      }
-      if (ref.images_it) ref.images_it[pix] = img;
-      const int p = pix / DET_N;
-      const int q = pix - p * DET_N;
-      const double t = (double)fmaxf(img - a.thr, 0.0f);
-      s0 += t;
-      sx += (double)((float)q - CD) * t;
-      sy += (double)((float)p - CD) * t;
+    const bool in = pix < NPIX;
+    const bool big = need_rng && in && v[j] >= 10.0f;
+    const uint64_t m = __ballot(big);
+    if (big) {
+      const int e = nq + __popcll(m & below);
+      q_pix[wave][e] = pix;
+      q_val[wave][0][e] = v[j];
+      q_val[wave][1][e] = u[j];
+      q_val[wave][2][e] = u01(wd[j].y);
+      q_val[wave][3][e] = read_noise_z(wd[j]);
+    } else if (in) {
+      accumulate(pix, need_rng ? (float)k[j] + a.ron * read_noise_z(wd[j]) : v[j]);
     }
+    nq += __popcll(m);
+  }
+  // the queue is written and read by this wavefront only: order its LDS accesses
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int e = lane; e < nq; e += 64) {
+    const int pix = q_pix[wave][e];
+    const int kp = poisson_ptrs(q_val[wave][0][e], q_val[wave][1][e], q_val[wave][2][e], (uint32_t)pix, gsub,
+                                ref.frame, ref.key0, ref.key1);
+    accumulate(pix, (float)kp + a.ron * q_val[wave][3][e]);
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -666,8 +689,9 @@ static hipError_t launch_variant(const WfsLaunch& a0, hipStream_t st) {
 constexpr int kTunedVariants = 11;
 constexpr int kFirstDetSplit = 6;
 
-// Sub-layer kernels: whole or split row transforms, waves-per-EU target 1.
-constexpr int kSubVariants = 2;
+// Sub-layer kernels: whole or split row transforms, waves-per-EU target 1; then split rows with
+// the detector split on a persistent grid.
+constexpr int kSubVariants = 3;
 
 template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, bool SUB>
 static hipError_t launch_one(int variant, const WfsLaunch& a, hipStream_t st) {
@@ -677,6 +701,7 @@ static hipError_t launch_one(int variant, const WfsLaunch& a, hipStream_t st) {
     switch (variant) {
       case 0: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, false, true>(a, st);
       case 1: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, true, true>(a, st);
+      case 2: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 4, true, true, true, true>(a, st);
       default: return hipErrorInvalidValue;
     }
   } else if constexpr (TUNED) {
@@ -730,12 +755,15 @@ int wfs_variant_count(const WfsShape& s) {
 }
 
 int wfs_default_variant(const WfsShape& s) {
-  // measured on the 6-LGS frame: detector split + persistent grid is the fastest with and without noise
-  return (!s.sub && s.conv_n == 40 && s.det_n == 16) ? 9 : 0;
+  // measured on the 6-LGS frame: split rows + detector split + persistent grid is the fastest with
+  // and without noise, with and without sub-layers
+  if (s.sub) return 2;
+  return (s.conv_n == 40 && s.det_n == 16) ? 9 : 0;
 }
 
 bool wfs_variant_needs_det_ws(const WfsShape& s, int variant) {
-  return !s.sub && s.conv_n == 40 && s.det_n == 16 && variant >= kFirstDetSplit;
+  if (s.sub) return variant == 2;
+  return s.conv_n == 40 && s.det_n == 16 && variant >= kFirstDetSplit;
 }
 
 hipError_t launch_wfs_fused(const WfsShape& s, int variant, const WfsLaunch& a, hipStream_t st) {

@@ -114,22 +114,25 @@ def test_graph_replay_advances_frames(torch_dev):
 
 
 def test_detector_split_work_list_equals_single_calls(torch_dev):
-    """A work list of frames of two plans, run with a detector-split variant, equals per-frame calls."""
+    """A work list of three frames, run with each detector-split variant, equals per-frame calls of a
+    variant of the same row-transform family."""
     from paper_1408_0698_amd import shwfs
     cfg = G.CFG1.replace(pupil_n=130, n_subap=13)
     plan = _plan(cfg, 6)
     opd = torch_dev.from_numpy(S.lgs39m_opd(3, 6, pupil_n=130)).cuda()
-    ref = []
-    for f in range(3):
-        sl = torch_dev.zeros((1, 6, 2, plan.n_valid), device="cuda")
-        im = torch_dev.zeros((1, 6, plan.n_valid, 16, 16), device="cuda")
-        plan.measure(opd[f:f + 1], sl, im, seed=100 + f, frame0=10 * f)
-        ref.append((sl[0], im[0]))
-    for v in (6, 7):
-        plan.set_variant(v)
-        outs = [(torch_dev.zeros((6, 2, plan.n_valid), device="cuda"),
-                 torch_dev.zeros((6, plan.n_valid, 16, 16), device="cuda")) for _ in range(3)]
-        shwfs.measure_batch([(plan, opd[f], outs[f][0], outs[f][1], 100 + f, 10 * f) for f in range(3)])
-        torch_dev.cuda.synchronize()
+    for fam_ref, variants in ((0, (6, 7)), (2, (8, 9, 10))):
+        plan.set_variant(fam_ref)
+        ref = []
         for f in range(3):
-            assert torch_dev.equal(outs[f][0], ref[f][0]) and torch_dev.equal(outs[f][1], ref[f][1]), (v, f)
+            sl = torch_dev.zeros((1, 6, 2, plan.n_valid), device="cuda")
+            im = torch_dev.zeros((1, 6, plan.n_valid, 16, 16), device="cuda")
+            plan.measure(opd[f:f + 1], sl, im, seed=100 + f, frame0=10 * f)
+            ref.append((sl[0], im[0]))
+        for v in variants:
+            plan.set_variant(v)
+            outs = [(torch_dev.zeros((6, 2, plan.n_valid), device="cuda"),
+                     torch_dev.zeros((6, plan.n_valid, 16, 16), device="cuda")) for _ in range(3)]
+            shwfs.measure_batch([(plan, opd[f], outs[f][0], outs[f][1], 100 + f, 10 * f) for f in range(3)])
+            torch_dev.cuda.synchronize()
+            for f in range(3):
+                assert torch_dev.equal(outs[f][0], ref[f][0]) and torch_dev.equal(outs[f][1], ref[f][1]), (v, f)

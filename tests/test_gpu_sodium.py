@@ -100,22 +100,28 @@ def test_plain_measure_on_sodium_plan_shares_the_wavefront(torch_dev):
     assert np.array_equal(a["slopes"], sl.cpu().numpy().astype(np.float64))
 
 
-def test_variants_agree_bitwise(torch_dev):
+def test_variants_agree(torch_dev):
+    """Split-row variants (1, 2: fused and detector-split) agree bitwise; whole rows (0) to FP32 rounding."""
+    from paper_1408_0698_amd import shwfs
     cfg = small_lgs(13)
     launch = G.launch_positions(cfg, 6)
     opd = S.lgs39m_opd(1, 6, pupil_n=cfg.pupil_n)
-    from paper_1408_0698_amd import shwfs
-    plan = shwfs.WfsPlan(cfg, 6, launch, sodium=G.SODIUM)
-    assert plan.n_variants == 2
     d = torch_dev.from_numpy(opd).cuda().unsqueeze(2).expand(-1, -1, 3, -1, -1)
-    outs = []
-    for v in range(plan.n_variants):
-        plan.set_variant(v)
-        sl = torch_dev.zeros((1, 6, 2, plan.n_valid), device="cuda")
-        plan.measure_sodium(d, sl, seed=4)
-        outs.append(sl)
+    outs = {}
+    for c in (cfg, cfg.replace(flags=0)):
+        plan = shwfs.WfsPlan(c, 6, launch, sodium=G.SODIUM)
+        assert plan.n_variants == 3
+        for v in range(plan.n_variants):
+            plan.set_variant(v)
+            sl = torch_dev.zeros((1, 6, 2, plan.n_valid), device="cuda")
+            im = torch_dev.zeros((1, 6, plan.n_valid, 16, 16), device="cuda")
+            plan.measure_sodium(d, sl, im, seed=4)
+            outs[(c.flags, v)] = (sl, im)
     torch_dev.cuda.synchronize()
-    assert torch_dev.equal(outs[0], outs[1])
+    for fl in (cfg.flags, 0):
+        assert torch_dev.equal(outs[(fl, 1)][0], outs[(fl, 2)][0]) and torch_dev.equal(outs[(fl, 1)][1], outs[(fl, 2)][1])
+    a, b = outs[(0, 0)][1].cpu().numpy(), outs[(0, 1)][1].cpu().numpy()
+    assert (abs(a - b) / abs(a).max(axis=(-1, -2), keepdims=True)).max() < 1e-6
 
 
 def test_full_frame_sampled(torch_dev):
