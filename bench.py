@@ -93,9 +93,8 @@ def _time(fn, n, stream):
     return e0.elapsed_time(e1) / n
 
 
-def extras(stream):
-    """Secondary workloads: 8 m NGS frame replayed as a captured graph; 3 NGS 2x2 sub-apertures
-    of 400 px (FFT 512); science PSF of 9 stars x 20 frames including DM surfaces and residuals."""
+def ex_ngs8m(stream):
+    """8 m NGS frame: eager launch, captured graph replay, and 4096 frames per launch."""
     import numpy as np
     import torch
 
@@ -130,6 +129,18 @@ def extras(stream):
     out["ngs8m_b4096_frames_per_s"] = 4096e3 / ms_b
     out["ngs8m_b4096_tflops_nominal"] = 4096 * plan0.n_valid * 5 * 256 * math.log2(256) / (ms_b * 1e-3) / 1e12
     del opd0b, sl0b
+    return out
+
+
+def ex_precision(stream):
+    """The 6-LGS frame with the sub-aperture DFTs as MFMA GEMMs (bf16, bf16 and fp16 hi+lo)."""
+    import numpy as np
+    import torch
+
+    from gen import configs as G
+    from gen import screens as S
+    from paper_1408_0698_amd import shwfs
+    out = {}
     # precision form: the 6-LGS frame with MFMA DFT GEMMs (noise on)
     launch = G.launch_positions(G.CFG1, 6)
     opd1 = torch.from_numpy(S.lgs39m_opd(2, 6)).cuda()
@@ -147,6 +158,21 @@ def extras(stream):
                     "mfma_frac_of_2500": flops / (ms * 1e-3) / 2.5e15}
         pl.close()
     out["precision_mfma"] = mm
+    del opd1
+    return out
+
+
+def ex_sodium(stream):
+    """The 6-LGS frame in the sodium sub-layer form (3 sub-layers)."""
+    import numpy as np
+    import torch
+
+    from gen import configs as G
+    from gen import screens as S
+    from paper_1408_0698_amd import shwfs
+    out = {}
+    launch = G.launch_positions(G.CFG1, 6)
+    opd1 = torch.from_numpy(S.lgs39m_opd(2, 6)).cuda()
     # sodium sub-layer form (3 sub-layers, shared wavefront, noise on): the form of the paper's
     # 4.5 s per-sensor step; per-sensor ms is the time of the 6-sensor frame / 6
     pls = shwfs.WfsPlan(G.CFG1, 6, launch, sodium=G.SODIUM)
@@ -161,7 +187,18 @@ def extras(stream):
     out["sodium3_frames_per_s"] = 1e3 / ms
     out["sodium3_ms_per_sensor_step"] = ms / 6
     pls.close()
-    del opd1
+    return out
+
+
+def ex_ngs512(stream):
+    """3 NGS sensors of 2x2 sub-apertures of 400 px (FFT 512)."""
+    import numpy as np
+    import torch
+
+    from gen import configs as G
+    from gen import screens as S
+    from paper_1408_0698_amd import shwfs
+    out = {}
     # 3 NGS, 2x2 sub-apertures of 400 px padded to 512, noise on
     plan4 = shwfs.WfsPlan(G.CFG4_NGS, 3)
     opd4 = torch.from_numpy(S.lgs39m_opd(4, 3)).cuda()
@@ -171,6 +208,18 @@ def extras(stream):
             plan4.measure(opd4, sl4, seed=1, stream=stream)
         ms4 = _time(lambda k: plan4.measure(opd4, sl4, seed=1, frame0=4 * k, stream=stream), 20, stream)
     out["ngs512_3x2x2_frames_per_s"] = 4e3 / ms4
+    return out
+
+
+def ex_psf(stream):
+    """Science PSF of 9 stars x 20 frames: DM surfaces, residuals and PSF accumulation."""
+    import numpy as np
+    import torch
+
+    from gen import configs as G
+    from gen import screens as S
+    from paper_1408_0698_amd import shwfs
+    out = {}
     # science PSF: DM surfaces from commands, residuals for 9 stars x 20 frames, PSF accumulation
     scr = torch.from_numpy(S.screen_opd_m(2048, 4.875e-2).astype(np.float32)).cuda()
     dms, coefs, surfs = [], [], []
@@ -202,19 +251,39 @@ def extras(stream):
     with torch.cuda.stream(stream):
         psf_step(0)
         ms3 = _time(psf_step, 3, stream)
+        ms_acc = _time(lambda k: psf.accumulate_stars(res.view(9, nfr, 800, 800), acc, sr, stream=stream), 3, stream)
     out["psf_9stars_x20_star_frames_per_s"] = 9 * nfr * 1e3 / ms3
     out["psf_step_ms"] = ms3
-    # algorithmic HBM bytes per star-frame: OPD 2.56 MB + intermediate written and read 2 x 10.24 MB,
-    # plus the accumulator read and written once per star per step (2 x 10.24 MB / 20 frames)
+    out["psf_accumulate_ms"] = ms_acc
+    # algorithmic HBM bytes per star-frame of the PSF kernels: OPD 2.56 MB + intermediate written and
+    # read 2 x 10.24 MB, plus the accumulator read and written once per star per call (2 x 10.24 MB / 20)
     per_sf = 800 * 800 * 4 + 2 * 800 * 1600 * 8 + 2 * 1600 * 1600 * 4 / nfr
-    out["psf_algorithmic_GBps"] = per_sf * 9 * nfr / (ms3 * 1e-3) / 1e9
+    out["psf_accumulate_GBps"] = per_sf * 9 * nfr / (ms_acc * 1e-3) / 1e9
+    out["psf_accumulate_frac_of_8TBps"] = per_sf * 9 * nfr / (ms_acc * 1e-3) / 8e12
     out["psf_mean_strehl_last_frame"] = float(sr[:, -1].mean().item())
     del res, acc
     torch.cuda.synchronize()
-    out.update(calibration(stream))
-    out.update(closed_loop(stream))
-    out["served"] = served()
-    out["served_load_sweep"] = [served(rate_hz=r, duration_s=1.0, warm=False) for r in (4000.0, 8000.0, 16000.0)]
+    return out
+
+
+EXTRAS = ("ngs8m", "precision", "sodium", "ngs512", "psf", "calibration", "loop", "served")
+EXTRAS_DEFAULT = EXTRAS
+
+
+def extras(stream, which=EXTRAS):
+    """Secondary workloads, each timed with HIP events on its stream."""
+    import torch
+    fns = {"ngs8m": ex_ngs8m, "precision": ex_precision, "sodium": ex_sodium, "ngs512": ex_ngs512, "psf": ex_psf,
+           "calibration": calibration, "loop": closed_loop}
+    out = {}
+    for name in which:
+        if name == "served":
+            out["served"] = served()
+            out["served_load_sweep"] = [served(rate_hz=r, duration_s=1.0, warm=False)
+                                        for r in (4000.0, 8000.0, 16000.0)]
+        else:
+            out.update(fns[name](stream))
+        torch.cuda.synchronize()
     return out
 
 
@@ -319,6 +388,8 @@ def main():
     ap.add_argument("--resident-frames", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default=",".join(EXTRAS_DEFAULT),
+                    help="comma-separated secondary workloads to run after the headline")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before timing, run 5 plain device copies of this many MB (profiler counter scale)")
@@ -414,7 +485,7 @@ def main():
         "autotune_ms_per_variant": tuned["ms_per_launch"] if tuned else None,
     }
     if not args.no_extras:
-        out["extras"] = extras(stream)
+        out["extras"] = extras(stream, [w for w in args.extras.split(",") if w])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, launch, opd_host)
     print(json.dumps(out), flush=True)
