@@ -25,7 +25,7 @@ FLOP_PER_SUBAP = 3 * 5 * 40 * 40 * math.log2(40 * 40)
 PEAK_FP32_TFLOPS = 157.3
 # launch variants of the 40-point shapes whose measurement is two kernels (fused stages up to the
 # detector, then noise and centroid); the roofline time covers both
-DETECTOR_SPLIT_VARIANTS = (6, 7, 8, 9, 10)
+DETECTOR_SPLIT_VARIANTS = (6, 7, 8, 9, 10, 11, 12)
 CSRC = os.path.join(ROOT, "paper_1408_0698_amd", "csrc")
 TRAFFIC = os.path.join(ROOT, "profiles", "wfs_measure_lgs39m_traffic.json")
 

@@ -247,9 +247,13 @@ int shw_wfs_plan_destroy(shw_wfs_plan* plan);
  * centroid in the fused kernel or in a second kernel over the detector
  * values kept in a plan-owned workspace).  Variants with the same row
  * transform give bitwise identical results; the two row-transform families
- * differ by FP32 rounding (about 1e-7 of an image).  The 40-point shapes
- * start on variant 9 (split rows, persistent, detector split), sodium
- * sub-layer plans on variant 2 (the same arrangement), the others on variant 0.  shw_wfs_plan_autotune times every variant on the given inputs
+ * differ by FP32 rounding (about 1e-7 of an image).  Band-limited variants
+ * (LGS with fft_n = conv_n = 4 * sub-aperture pixels: 11 and 12, sodium
+ * plans 3 and 4) compute the column spectrum of the spot from
+ * autocorrelations of the row transforms and filter only the rows inside
+ * the spot's band.  New plans start on the fastest measured variant: 12 for
+ * band-limited 40-point shapes, 9 for the other 40-point shapes, 3 for
+ * band-limited sodium plans, 2 for the other sodium plans, 0 otherwise.  shw_wfs_plan_autotune times every variant on the given inputs
  * (reps launches each after two warm-up launches, HIP events on the stream;
  * synchronous), selects the fastest and returns its index in *best and the
  * per-variant milliseconds per launch in ms (nullable, n entries).

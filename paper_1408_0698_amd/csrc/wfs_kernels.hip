@@ -25,6 +25,14 @@
 //     equals convolving every sub-layer spot and piling them up.
 //  B  (LGS) real column transform, per-row transform x K^ x inverse row
 //     transform, inverse column transform: J = I (*) k.
+//     Band-limited variants (BL, FFT_N = CONV_N): the spot of an NPX-pixel
+//     sub-aperture has no spectrum beyond NPX - 1 samples from zero (the
+//     transfer function of the sub-aperture is its autocorrelation), so the
+//     column spectrum of I is computed directly as the autocorrelation of
+//     each row-pass column over its NPX samples, only rows 0 .. NPX-1 of the
+//     half spectrum are filtered, and the inverse column transform reads
+//     only those rows: the column pass, the real column transform and half
+//     of the row filtering are not needed.
 //  C  rebin along the column in registers, then along the row via LDS.
 //  D  photometry, Poisson + read noise, threshold, centre of gravity with
 //     FP64 sums, reduced over the item's lanes.  Detector-split variants
@@ -64,6 +72,23 @@ __device__ __forceinline__ float pair_swap(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0xB1, 0xF, 0xF, false));
 }
 __device__ __forceinline__ float2 pair_swap(float2 v) { return make_float2(pair_swap(v.x), pair_swap(v.y)); }
+
+// Value of the same register in lane t ^ 2 (DPP quad permutation 2, 3, 0, 1).
+__device__ __forceinline__ float quad_swap2(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x4E, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float2 quad_swap2(float2 v) { return make_float2(quad_swap2(v.x), quad_swap2(v.y)); }
+
+// x * exp(DIR 2 pi i q c / N) for a lane index q in 0..3 and a compile-time c: the four constants
+// are selected, not computed.
+template <int N, int DIR>
+__device__ __forceinline__ float2 quad_twiddle(float2 x, int q, int c) {
+  constexpr TwiddleTable<N> tw{};
+  const int j1 = c % N, j2 = (2 * c) % N, j3 = (3 * c) % N;
+  const float wc = q == 0 ? 1.0f : (q == 1 ? tw.c[j1] : (q == 2 ? tw.c[j2] : tw.c[j3]));
+  const float ws = q == 0 ? 0.0f : (q == 1 ? tw.s[j1] : (q == 2 ? tw.s[j2] : tw.s[j3]));
+  return cmul(x, make_float2(wc, DIR > 0 ? ws : -ws));
+}
 
 // Per-item output buffers and noise key: from the work list, or the launch-wide layout.
 struct ItemRef {
@@ -107,13 +132,15 @@ __device__ __forceinline__ ItemRef resolve_item(const WfsLaunch& a, int64_t it, 
 
 // LDS floats per item for the given shape.  Split row transforms keep N/2 spectrum rows (rows 0
 // and N/2 packed), whole ones N/2 + 1; the detector-split variants keep no detector stage in LDS.
-template <int NPX, int FFT_N, int CONV_N, int DET_N, bool SPLIT, bool DSPLIT>
+// Band-limited variants keep NPX spectrum rows and spread the rebinned detector rows over both planes.
+template <int NPX, int FFT_N, int CONV_N, int DET_N, bool SPLIT, bool DSPLIT, bool BL = false>
 struct FusedLayout {
   static constexpr int HN = CONV_N / 2;
   static constexpr int ST = CONV_N + 1;
-  static constexpr int HROWS = SPLIT ? HN : HN + 1;
+  static constexpr int HROWS = BL ? NPX : (SPLIT ? HN : HN + 1);
+  static constexpr int DROWS = BL ? (DET_N + 1) / 2 : DET_N;
   static constexpr int ROWS0 = NPX > HROWS ? NPX : HROWS;
-  static constexpr int ROWS = ROWS0 > DET_N ? ROWS0 : DET_N;
+  static constexpr int ROWS = ROWS0 > DROWS ? ROWS0 : DROWS;
   static constexpr int NPIX = DET_N * DET_N;
   static constexpr int DETA = NPIX + 1;                 // detector values, after the queue and its count
   static constexpr int RED = (DETA + NPIX + 1) & ~1;
@@ -123,17 +150,18 @@ struct FusedLayout {
 };
 
 // One group of SPB work items (one block's worth).  Every lane of the block calls it.
-template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, bool SPLIT, bool SUB, bool DSPLIT>
+template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, bool SPLIT, bool SUB, bool DSPLIT,
+          bool BL = false>
 __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t group, uint32_t frame_base,
-                                                float* __restrict__ s_re, float* __restrict__ s_im) {
+                                                float* __restrict__ s_re, float* __restrict__ s_im, int tid) {
   constexpr int L = CONV_N;                  // lanes per item
   constexpr int R = FFT_N / NPX;             // column residues of the row pass
   constexpr int H = CONV_N / 2 + 1;          // stored half spectrum rows (kernel spectra)
   constexpr int HN = CONV_N / 2;             // half length; packed spectrum rows in LDS
   constexpr int ST = CONV_N + 1;             // odd LDS row stride (floats)
-  constexpr int ROWS0 = NPX > HN ? NPX : HN;
-  constexpr int ROWS = ROWS0 > DET_N ? ROWS0 : DET_N;
-  using LY = FusedLayout<NPX, FFT_N, CONV_N, DET_N, SPLIT, DSPLIT>;
+  using LY = FusedLayout<NPX, FFT_N, CONV_N, DET_N, SPLIT, DSPLIT, BL>;
+  static_assert(!BL || (LGS && SPLIT && DSPLIT && FFT_N == CONV_N && CONV_N == 4 * NPX),
+                "band-limited path: LGS, split rows, detector split, FFT_N = CONV_N = 4 NPX");
   constexpr int NPIX = LY::NPIX;
   // stage D reuses the imaginary plane: a queue of NPIX pixel indices, its count, then 3 L doubles
   constexpr int QCOUNT = NPIX;
@@ -144,7 +172,6 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   constexpr float INV_N2 = 1.0f / (float)(FFT_N * FFT_N);
   static_assert(FFT_N % NPX == 0 && CONV_N >= FFT_N && (CONV_N - FFT_N) % 2 == 0, "shape");
 
-  const int tid = threadIdx.x;
   const int s = tid / L;
   const int l = tid - s * L;
   const int64_t item = a.item0 + group * SPB + s;
@@ -166,6 +193,9 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   float col[CONV_N];
 #pragma unroll
   for (int v = 0; v < CONV_N; ++v) col[v] = 0.0f;
+  float2 ac[BL ? NPX : 1];  // BL: column spectrum rows 0 .. NPX-1 of this lane's column
+#pragma unroll
+  for (int k = 0; k < (BL ? NPX : 1); ++k) ac[k] = make_float2(0.0f, 0.0f);
   const int n_sub = SUB ? a.n_sub : 1;
 #pragma unroll 1
   for (int sl = 0; sl < n_sub; ++sl) {
@@ -215,7 +245,31 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   __syncthreads();
 
   // ---------------------------------------------------------------- A': column pass, |F|^2
-  {
+  if constexpr (BL) {
+    // R[k] = sum_v I[v] w^(kv) = (1/N) sum_y G[y] conj(G[y + k]), k < NPX (zero for NPX <= k <= N/2)
+    constexpr float INV_N = 1.0f / (float)FFT_N;
+    const float wgt = SUB ? (float)a.sub_coef[2 * sl + 1] * INV_N : INV_N;
+    if (active) {
+      float2 g[NPX];
+#pragma unroll
+      for (int y = 0; y < NPX; ++y) g[y] = make_float2(re[y * ST + l], im[y * ST + l]);
+      float e0 = 0.0f;
+#pragma unroll
+      for (int y = 0; y < NPX; ++y) e0 += g[y].x * g[y].x + g[y].y * g[y].y;
+      ac[0].x += e0 * wgt;
+#pragma unroll
+      for (int k = 1; k < NPX; ++k) {
+        float2 t = make_float2(0.0f, 0.0f);
+#pragma unroll
+        for (int y = 0; y + k < NPX; ++y) {
+          // G[y] conj(G[y + k])
+          t.x += g[y].x * g[y + k].x + g[y].y * g[y + k].y;
+          t.y += g[y].y * g[y + k].x - g[y].x * g[y + k].y;
+        }
+        ac[k] = cadd(ac[k], cscale(t, wgt));
+      }
+    }
+  } else {
     const float wgt = SUB ? (float)a.sub_coef[2 * sl + 1] * INV_N2 : INV_N2;
     const int u = l - OFF;
     if (active && u >= 0 && u < FFT_N) {
@@ -250,7 +304,16 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   if constexpr (LGS) {
     static_assert(CONV_N % 4 == 0, "LGS convolution needs conv_n divisible by 4");
     __syncthreads();  // every lane has read the row-pass plane
-    {
+    if constexpr (BL) {
+      // rows 0 .. NPX-1 of the half spectrum; row 0 (real) packed with row N/2 (zero)
+      re[l] = ac[0].x;
+      im[l] = 0.0f;
+#pragma unroll
+      for (int k = 1; k < NPX; ++k) {
+        re[k * ST + l] = ac[k].x;
+        im[k * ST + l] = ac[k].y;
+      }
+    } else {
       // B1: R[k] = sum_v I[v] w^(kv), k = 0..N/2, from Z = FFT_{N/2}(I[2m] + i I[2m+1])
       float2 z[HN];
 #pragma unroll
@@ -310,6 +373,45 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       const int r = l >> 1, h = l & 1;
       float2 x[HN];
       const float* kh_item = a.khat + ((int64_t)(w * a.n_valid + i) * H) * CONV_N;
+      if constexpr (BL) {
+        // rows NPX .. N/2-1 are zero; row 0 holds the real row 0 only (row N/2 is zero), so its
+        // filter is the plain product by K^ row 0.  Four lanes per row (q = l & 3, row l >> 2):
+        // each transforms the samples 4t + q, a radix-4 step across the quad (DPP) completes the
+        // N-point transform; lane q holds spectral samples c + (N/4) m(q), m = (0, 2, 1, 3).
+        constexpr int M4 = CONV_N / 4;
+        const int r4 = l >> 2, q = l & 3;
+        if (active) {
+          float2 xq[M4];
+#pragma unroll
+          for (int t = 0; t < M4; ++t) xq[t] = make_float2(re[r4 * ST + 4 * t + q], im[r4 * ST + 4 * t + q]);
+          RegFFT<M4, -1>::run(xq);
+#pragma unroll
+          for (int c = 0; c < M4; ++c) {
+            float2 v = quad_twiddle<CONV_N, -1>(xq[c], q, c);
+            // 4-point transform across the quad, decimation in time: pairs q ^ 2, then q ^ 1
+            float2 o = quad_swap2(v);
+            v = (q & 2) ? csub(o, v) : cadd(v, o);
+            o = pair_swap(v);
+            v = q == 0 ? cadd(v, o) : (q == 1 ? csub(o, v) : (q == 2 ? cadd(v, cmul_i<-1>(o)) : cadd(o, cmul_i<1>(v))));
+            // filter: the spectrum is zero beyond NPX - 1 samples from 0 (band limit of the spot)
+            const int j = c + M4 * (((q & 1) << 1) | (q >> 1));
+            const bool band = j < NPX || j > CONV_N - NPX;
+            v = band ? cscale(v, kh_item[r4 * CONV_N + j]) : make_float2(0.0f, 0.0f);
+            // inverse 4-point transform across the quad (inputs in the order m(q)): pairs q ^ 1, then q ^ 2
+            o = pair_swap(v);
+            v = (q & 1) ? csub(o, v) : cadd(v, o);
+            o = quad_swap2(v);
+            v = q == 0 ? cadd(v, o) : (q == 1 ? cadd(v, cmul_i<1>(o)) : (q == 2 ? csub(o, v) : cadd(o, cmul_i<-1>(v))));
+            xq[c] = quad_twiddle<CONV_N, 1>(v, q, c);
+          }
+          RegFFT<M4, 1>::run(xq);
+#pragma unroll
+          for (int t = 0; t < M4; ++t) {
+            re[r4 * ST + 4 * t + q] = xq[t].x;
+            im[r4 * ST + 4 * t + q] = xq[t].y;
+          }
+        }
+      } else {
       if (active) {
 #pragma unroll
         for (int u = 0; u < HN; ++u) x[u] = make_float2(re[r * ST + 2 * u + h], im[r * ST + 2 * u + h]);
@@ -370,6 +472,8 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
           im[r * ST + 2 * u + h] = x[u].y;
         }
       }
+    
+      }
     }
     __syncthreads();
     {
@@ -378,9 +482,10 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       // computed in place pair by pair (k, N/2 - k): Z[k] and Z[N/2 - k] give C[k] and C[N/2 - k]
       float2 y[HN];
       const float z0 = re[l];
-      const float zh = SPLIT ? im[l] : re[HN * ST + l];
+      const float zh = BL ? 0.0f : (SPLIT ? im[l] : re[HN * ST + l]);
 #pragma unroll
-      for (int k = 1; k < HN; ++k) y[k] = make_float2(re[k * ST + l], im[k * ST + l]);
+      for (int k = 1; k < HN; ++k)
+        y[k] = (BL && k >= NPX) ? make_float2(0.0f, 0.0f) : make_float2(re[k * ST + l], im[k * ST + l]);
       auto cfold = [](float2 zk, float2 zm, int k) {
         const float2 zc = cconj(zm);
         const float2 e = cadd(zk, zc);
@@ -407,7 +512,11 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   // ---------------------------------------------------------------- C: rebin
   __syncthreads();  // the planes are free
   int* queue = reinterpret_cast<int*>(im);
-  if (l == 0) queue[QCOUNT] = 0;
+  if (!DSPLIT && l == 0) queue[QCOUNT] = 0;
+  // detector row p of the column-rebinned image: plane re, or (BL) rows from DROWS on in plane im
+  auto det_row = [&](int p) -> float* {
+    return (BL && p >= LY::DROWS) ? im + (p - LY::DROWS) * ST : re + p * ST;
+  };
 #pragma unroll
   for (int p = 0; p < DET_N; ++p) {
     float acc = 0.0f;
@@ -416,7 +525,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       const float wgt = rebin_weight(CONV_N, DET_N, p, k);
       if (wgt != 0.0f) acc += wgt * col[k];
     }
-    re[p * ST + l] = acc;
+    det_row(p)[l] = acc;
   }
   __syncthreads();
 
@@ -447,7 +556,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   if (active && l < DET_N * G) {
     const int p = l / G;
     const int q0 = QB * (l - p * G);
-    const float* row = re + p * ST + (q0 / QB) * KB;
+    const float* row = det_row(p) + (q0 / QB) * KB;
     float in[KB];
 #pragma unroll
     for (int t = 0; t < KB; ++t) in[t] = row[t];
@@ -532,21 +641,27 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
 // One-shot grid (one group per block) or persistent grid (blocks stride over the groups).
 // The frame number of the first frame comes from a.frame0_dev when set (graph replay).
 template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, int WPE, bool PERSIST, bool SPLIT, bool SUB,
-          bool DSPLIT>
+          bool DSPLIT, bool BL>
 __global__ __launch_bounds__(SPB * CONV_N) __attribute__((amdgpu_waves_per_eu(WPE))) void wfs_fused_kernel(
     const WfsLaunch a) {
-  using LY = FusedLayout<NPX, FFT_N, CONV_N, DET_N, SPLIT, DSPLIT>;
+  using LY = FusedLayout<NPX, FFT_N, CONV_N, DET_N, SPLIT, DSPLIT, BL>;
   __shared__ __align__(16) float s_re[SPB * LY::PLANE];
   __shared__ __align__(16) float s_im[SPB * LY::PLANE];
   const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev : a.frame0;
   if constexpr (PERSIST) {
     const int64_t ngroups = (a.total - a.item0 + SPB - 1) / SPB;
     for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
-      wfs_fused_group<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, SPLIT, SUB, DSPLIT>(a, g, frame_base, s_re, s_im);
+      // band-limited kernels re-derive the lane index every iteration through an opaque move, so
+      // that the compiler does not keep every per-lane address of the group live across the loop
+      int zero = 0;
+      if constexpr (BL) asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+      wfs_fused_group<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, SPLIT, SUB, DSPLIT, BL>(a, g, frame_base, s_re, s_im,
+                                                                                (int)threadIdx.x + zero);
       __syncthreads();
     }
   } else {
-    wfs_fused_group<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, SPLIT, SUB, DSPLIT>(a, blockIdx.x, frame_base, s_re, s_im);
+    wfs_fused_group<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, SPLIT, SUB, DSPLIT, BL>(a, blockIdx.x, frame_base, s_re,
+                                                                              s_im, (int)threadIdx.x);
   }
 }
 
@@ -647,9 +762,9 @@ constexpr int items_per_block(int lanes) {
 }
 
 template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, int WPE, bool PERSIST, bool SPLIT,
-          bool SUB = false, bool DSPLIT = false>
+          bool SUB = false, bool DSPLIT = false, bool BL = false>
 static hipError_t launch_variant(const WfsLaunch& a0, hipStream_t st) {
-  auto kern = wfs_fused_kernel<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, WPE, PERSIST, SPLIT, SUB, DSPLIT>;
+  auto kern = wfs_fused_kernel<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, WPE, PERSIST, SPLIT, SUB, DSPLIT, BL>;
   int64_t resident = 0;
   if constexpr (PERSIST) {
     static int per_dev = 0;  // blocks resident on the device for this kernel (per process, device 0 shape)
@@ -687,10 +802,17 @@ static hipError_t launch_variant(const WfsLaunch& a0, hipStream_t st) {
 // waves-per-EU target, persistent grid, noise in the fused kernel or after it).  Variants
 // from kFirstDetSplit on end the fused kernel at the detector.
 constexpr int kTunedVariants = 11;
+// Band-limited variants (11: persistent, WPE 4; 12: one-shot, WPE 1), for LGS shapes with FFT_N = CONV_N.
+constexpr int kBandLimitedVariants = 2;
+template <int NPX, int FFT_N, int CONV_N, bool LGS>
+constexpr bool band_limited_ok() {
+  return LGS && FFT_N == CONV_N && CONV_N == 4 * NPX;
+}
 constexpr int kFirstDetSplit = 6;
 
-// Sub-layer kernels: whole or split row transforms, waves-per-EU target 1; then split rows with
-// the detector split on a persistent grid.
+// Sub-layer kernels: whole or split row transforms, waves-per-EU target 1; split rows with the
+// detector split on a persistent grid; then (band-limited shapes) the band-limited path one-shot
+// and persistent.
 constexpr int kSubVariants = 3;
 
 template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, bool SUB>
@@ -702,6 +824,13 @@ static hipError_t launch_one(int variant, const WfsLaunch& a, hipStream_t st) {
       case 0: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, false, true>(a, st);
       case 1: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, true, true>(a, st);
       case 2: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 4, true, true, true, true>(a, st);
+      case 3:
+      case 4:
+        if constexpr (band_limited_ok<NPX, FFT_N, CONV_N, LGS>()) {
+          if (variant == 3) return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, true, true, true, true>(a, st);
+          return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 5, true, true, true, true, true>(a, st);
+        }
+        return hipErrorInvalidValue;
       default: return hipErrorInvalidValue;
     }
   } else if constexpr (TUNED) {
@@ -717,6 +846,13 @@ static hipError_t launch_one(int variant, const WfsLaunch& a, hipStream_t st) {
       case 8: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, true, false, true>(a, st);
       case 9: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 4, true, true, false, true>(a, st);
       case 10: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, true, true, false, true>(a, st);
+      case 11:
+      case 12:
+        if constexpr (band_limited_ok<NPX, FFT_N, CONV_N, LGS>()) {
+          if (variant == 11) return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 5, true, true, false, true, true>(a, st);
+          return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, true, false, true, true>(a, st);
+        }
+        return hipErrorInvalidValue;
       default: return hipErrorInvalidValue;
     }
   } else {
@@ -750,19 +886,23 @@ bool wfs_shape_supported(const WfsShape& s) {
 
 int wfs_variant_count(const WfsShape& s) {
   if (!wfs_shape_supported(s)) return 0;
-  if (s.sub) return kSubVariants;
-  return (s.conv_n == 40 && s.det_n == 16) ? kTunedVariants : 1;
+  const bool bl = s.lgs && s.fft_n == s.conv_n && s.conv_n == 4 * s.npx;
+  if (s.sub) return kSubVariants + (bl ? kBandLimitedVariants : 0);
+  if (!(s.conv_n == 40 && s.det_n == 16)) return 1;
+  return kTunedVariants + (bl ? kBandLimitedVariants : 0);
 }
 
 int wfs_default_variant(const WfsShape& s) {
-  // measured on the 6-LGS frame: split rows + detector split + persistent grid is the fastest with
-  // and without noise, with and without sub-layers
-  if (s.sub) return 2;
-  return (s.conv_n == 40 && s.det_n == 16) ? 9 : 0;
+  // measured on the 6-LGS frame, with and without noise and sub-layers: the band-limited one-shot
+  // kernel where the shape allows it, else split rows + detector split + persistent grid
+  const bool bl = s.lgs && s.fft_n == s.conv_n && s.conv_n == 4 * s.npx;
+  if (s.sub) return bl ? 3 : 2;
+  if (!(s.conv_n == 40 && s.det_n == 16)) return 0;
+  return bl ? 12 : 9;
 }
 
 bool wfs_variant_needs_det_ws(const WfsShape& s, int variant) {
-  if (s.sub) return variant == 2;
+  if (s.sub) return variant >= 2;
   return s.conv_n == 40 && s.det_n == 16 && variant >= kFirstDetSplit;
 }
 

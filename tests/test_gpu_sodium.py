@@ -101,7 +101,8 @@ def test_plain_measure_on_sodium_plan_shares_the_wavefront(torch_dev):
 
 
 def test_variants_agree(torch_dev):
-    """Split-row variants (1, 2: fused and detector-split) agree bitwise; whole rows (0) to FP32 rounding."""
+    """Within a row-transform family the variants agree bitwise (split rows: 1, 2; band-limited: 3, 4);
+    across families the noise-free images agree to FP32 rounding."""
     from paper_1408_0698_amd import shwfs
     cfg = small_lgs(13)
     launch = G.launch_positions(cfg, 6)
@@ -110,7 +111,7 @@ def test_variants_agree(torch_dev):
     outs = {}
     for c in (cfg, cfg.replace(flags=0)):
         plan = shwfs.WfsPlan(c, 6, launch, sodium=G.SODIUM)
-        assert plan.n_variants == 3
+        assert plan.n_variants == 5
         for v in range(plan.n_variants):
             plan.set_variant(v)
             sl = torch_dev.zeros((1, 6, 2, plan.n_valid), device="cuda")
@@ -119,9 +120,33 @@ def test_variants_agree(torch_dev):
             outs[(c.flags, v)] = (sl, im)
     torch_dev.cuda.synchronize()
     for fl in (cfg.flags, 0):
-        assert torch_dev.equal(outs[(fl, 1)][0], outs[(fl, 2)][0]) and torch_dev.equal(outs[(fl, 1)][1], outs[(fl, 2)][1])
-    a, b = outs[(0, 0)][1].cpu().numpy(), outs[(0, 1)][1].cpu().numpy()
-    assert (abs(a - b) / abs(a).max(axis=(-1, -2), keepdims=True)).max() < 1e-6
+        for x, y in ((1, 2), (3, 4)):
+            assert torch_dev.equal(outs[(fl, x)][0], outs[(fl, y)][0]) and torch_dev.equal(outs[(fl, x)][1],
+                                                                                       outs[(fl, y)][1]), (fl, x, y)
+    a = outs[(0, 0)][1].cpu().numpy()
+    for v in (1, 3):
+        b = outs[(0, v)][1].cpu().numpy()
+        assert (abs(a - b) / abs(a).max(axis=(-1, -2), keepdims=True)).max() < 1e-6, v
+
+
+@pytest.mark.parametrize("variant", [2, 3])
+def test_variant_parity(torch_dev, variant):
+    """Split-row and band-limited sodium kernels against the oracle, five sub-layers of their own."""
+    cfg = small_lgs(12, flags=0)
+    launch = G.launch_positions(cfg, 3)
+    sod = G.sodium_profile(5, G.SODIUM_THICKNESS_M)
+    opd = np.stack([S.lgs39m_opd(1, 3, frame0=7 * j, pupil_n=cfg.pupil_n) for j in range(5)], axis=2)
+    from paper_1408_0698_amd import shwfs
+    plan = shwfs.WfsPlan(cfg, 3, launch, sodium=sod)
+    plan.set_variant(variant)
+    dd = torch_dev.from_numpy(np.ascontiguousarray(opd, dtype=np.float32)).cuda()
+    sl = torch_dev.zeros((1, 3, 2, plan.n_valid), device="cuda")
+    im = torch_dev.zeros((1, 3, plan.n_valid, 16, 16), device="cuda")
+    plan.measure_sodium(dd, sl, im)
+    torch_dev.cuda.synchronize()
+    want = OW.Sensor(cfg, 3, launch, sodium=sod).measure(opd)
+    assert_images_close(im.cpu().numpy().astype(np.float64), want["images"])
+    assert_slopes_close(sl.cpu().numpy().astype(np.float64), want["slopes"])
 
 
 def test_full_frame_sampled(torch_dev):

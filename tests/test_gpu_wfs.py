@@ -37,9 +37,11 @@ def small_lgs(ns=17, **kw):
     return G.CFG1.replace(pupil_n=10 * ns, n_subap=ns, **kw)
 
 
-def run_gpu(torch, cfg, n_wfs, launch, opd, seed=0, frame0=0, images=True):
+def run_gpu(torch, cfg, n_wfs, launch, opd, seed=0, frame0=0, images=True, variant=None):
     s = _lib()
     plan = s.WfsPlan(cfg, n_wfs, launch)
+    if variant is not None:
+        plan.set_variant(variant)
     d_opd = torch.from_numpy(np.ascontiguousarray(opd, dtype=np.float32)).cuda()
     nf = opd.shape[0]
     slopes = torch.full((nf, n_wfs, 2, plan.n_valid), float("nan"), device="cuda")
@@ -94,6 +96,38 @@ def test_noise_free_parity(torch_dev, cfg, n_wfs, nf):
     assert_images_close(got["images"], want["images"])
     assert_slopes_close(got["slopes"], want["slopes"])
     assert np.array_equal(got["flags"].astype(bool), want["empty"])
+
+
+@pytest.mark.parametrize("variant", [0, 2, 9, 11, 12])
+def test_launch_variant_parity(torch_dev, variant):
+    """Every row-transform family (whole, split, band-limited) against the oracle, noise off and on."""
+    cfg = small_lgs(13, flags=0)
+    launch = G.launch_positions(cfg, 6)
+    opd = screen_opd(cfg, 2, 6)
+    got = run_gpu(torch_dev, cfg, 6, launch, opd, variant=variant)
+    want = OW.Sensor(cfg, 6, launch).measure(opd)
+    assert_images_close(got["images"], want["images"])
+    assert_slopes_close(got["slopes"], want["slopes"])
+    noisy = small_lgs(13)
+    seed = G.NOISE_SEED + 5
+    got = run_gpu(torch_dev, noisy, 6, launch, opd, seed=seed, frame0=3, variant=variant)
+    sens = OW.Sensor(noisy, 6, launch)
+    want = sens.measure(opd, seed=seed, frame0=3)
+    check_noisy(noisy, 6, launch, got, want, seed, 3, lambda w: w * sens.n_valid + np.arange(sens.n_valid))
+
+
+def test_band_limited_variant_full_frame_sampled(torch_dev):
+    """The band-limited path on the full 6-LGS frame, noise off, against the oracle on sampled sub-apertures."""
+    cfg = G.CFG1.replace(flags=0)
+    launch = G.launch_positions(cfg, 6)
+    opd = screen_opd(cfg, 1, 6)
+    got = run_gpu(torch_dev, cfg, 6, launch, opd, variant=11)
+    sens = OW.Sensor(cfg, 6, launch)
+    sub = np.unique(np.concatenate([np.random.default_rng(4).choice(sens.n_valid, 60, replace=False),
+                                    [0, sens.n_valid - 1]]))
+    want = sens.measure(opd, subset=sub)
+    assert_images_close(got["images"][:, :, sub], want["images"])
+    assert_slopes_close(got["slopes"][..., sub], want["slopes"])
 
 
 def test_flat_wavefront_gives_zero_slopes(torch_dev):
