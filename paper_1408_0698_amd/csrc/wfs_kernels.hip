@@ -69,26 +69,16 @@ constexpr int det_block(int conv_n, int det_n, int lanes) {
 
 // Value of the same register in the partner lane t ^ 1 (DPP quad permutation 1, 0, 3, 2).
 __device__ __forceinline__ float pair_swap(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0xB1, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float2 pair_swap(float2 v) { return make_float2(pair_swap(v.x), pair_swap(v.y)); }
 
 // Value of the same register in lane t ^ 2 (DPP quad permutation 2, 3, 0, 1).
 __device__ __forceinline__ float quad_swap2(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x4E, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float2 quad_swap2(float2 v) { return make_float2(quad_swap2(v.x), quad_swap2(v.y)); }
 
-// x * exp(DIR 2 pi i q c / N) for a lane index q in 0..3 and a compile-time c: the four constants
-// are selected, not computed.
-template <int N, int DIR>
-__device__ __forceinline__ float2 quad_twiddle(float2 x, int q, int c) {
-  constexpr TwiddleTable<N> tw{};
-  const int j1 = c % N, j2 = (2 * c) % N, j3 = (3 * c) % N;
-  const float wc = q == 0 ? 1.0f : (q == 1 ? tw.c[j1] : (q == 2 ? tw.c[j2] : tw.c[j3]));
-  const float ws = q == 0 ? 0.0f : (q == 1 ? tw.s[j1] : (q == 2 ? tw.s[j2] : tw.s[j3]));
-  return cmul(x, make_float2(wc, DIR > 0 ? ws : -ws));
-}
 
 // Per-item output buffers and noise key: from the work list, or the launch-wide layout.
 struct ItemRef {
@@ -153,7 +143,8 @@ struct FusedLayout {
 template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, bool SPLIT, bool SUB, bool DSPLIT,
           bool BL = false>
 __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t group, uint32_t frame_base,
-                                                float* __restrict__ s_re, float* __restrict__ s_im, int tid) {
+                                                float* __restrict__ s_re, float* __restrict__ s_im, int tid,
+                                                const float2* __restrict__ qtw) {
   constexpr int L = CONV_N;                  // lanes per item
   constexpr int R = FFT_N / NPX;             // column residues of the row pass
   constexpr int H = CONV_N / 2 + 1;          // stored half spectrum rows (kernel spectra)
@@ -385,24 +376,32 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
 #pragma unroll
           for (int t = 0; t < M4; ++t) xq[t] = make_float2(re[r4 * ST + 4 * t + q], im[r4 * ST + 4 * t + q]);
           RegFFT<M4, -1>::run(xq);
+          // radix-2 x radix-2 across the quad: every butterfly is out = partner + s * own, with the
+          // internal twiddle (-i forward, +i inverse) applied by lane 3 to its own value
+          const float s2 = (q & 2) ? -1.0f : 1.0f, s1 = (q & 1) ? -1.0f : 1.0f;
+          const bool l3 = q == 3;
+          const int m = ((q & 1) << 1) | (q >> 1);
 #pragma unroll
           for (int c = 0; c < M4; ++c) {
-            float2 v = quad_twiddle<CONV_N, -1>(xq[c], q, c);
-            // 4-point transform across the quad, decimation in time: pairs q ^ 2, then q ^ 1
+            const float2 w = qtw[q * M4 + c];  // W_N^(q c)
+            float2 v = cmul(xq[c], w);
+            // forward: pairs q ^ 2, internal twiddle, pairs q ^ 1; lane q then holds sample c + (N/4) m(q)
             float2 o = quad_swap2(v);
-            v = (q & 2) ? csub(o, v) : cadd(v, o);
+            v = make_float2(o.x + s2 * v.x, o.y + s2 * v.y);
+            v = l3 ? make_float2(v.y, -v.x) : v;
             o = pair_swap(v);
-            v = q == 0 ? cadd(v, o) : (q == 1 ? csub(o, v) : (q == 2 ? cadd(v, cmul_i<-1>(o)) : cadd(o, cmul_i<1>(v))));
+            v = make_float2(o.x + s1 * v.x, o.y + s1 * v.y);
             // filter: the spectrum is zero beyond NPX - 1 samples from 0 (band limit of the spot)
-            const int j = c + M4 * (((q & 1) << 1) | (q >> 1));
+            const int j = c + M4 * m;
             const bool band = j < NPX || j > CONV_N - NPX;
             v = band ? cscale(v, kh_item[r4 * CONV_N + j]) : make_float2(0.0f, 0.0f);
-            // inverse 4-point transform across the quad (inputs in the order m(q)): pairs q ^ 1, then q ^ 2
+            // inverse: pairs q ^ 1, internal twiddle, pairs q ^ 2
             o = pair_swap(v);
-            v = (q & 1) ? csub(o, v) : cadd(v, o);
+            v = make_float2(o.x + s1 * v.x, o.y + s1 * v.y);
+            v = l3 ? make_float2(-v.y, v.x) : v;
             o = quad_swap2(v);
-            v = q == 0 ? cadd(v, o) : (q == 1 ? cadd(v, cmul_i<1>(o)) : (q == 2 ? csub(o, v) : cadd(o, cmul_i<-1>(v))));
-            xq[c] = quad_twiddle<CONV_N, 1>(v, q, c);
+            v = make_float2(o.x + s2 * v.x, o.y + s2 * v.y);
+            xq[c] = cmul(v, cconj(w));
           }
           RegFFT<M4, 1>::run(xq);
 #pragma unroll
@@ -647,6 +646,17 @@ __global__ __launch_bounds__(SPB * CONV_N) __attribute__((amdgpu_waves_per_eu(WP
   using LY = FusedLayout<NPX, FFT_N, CONV_N, DET_N, SPLIT, DSPLIT, BL>;
   __shared__ __align__(16) float s_re[SPB * LY::PLANE];
   __shared__ __align__(16) float s_im[SPB * LY::PLANE];
+  // band-limited kernels: W_N^(q c) = exp(-2 pi i q c / N), q < 4, c < N/4 (first read after a barrier)
+  constexpr int QTW = BL ? CONV_N : 1;
+  __shared__ float2 s_qtw[QTW];
+  if constexpr (BL) {
+    constexpr TwiddleTable<CONV_N> tw{};
+    if ((int)threadIdx.x < CONV_N) {
+      const int q = threadIdx.x / (CONV_N / 4), c = threadIdx.x - q * (CONV_N / 4);
+      const int j = (q * c) % CONV_N;
+      s_qtw[threadIdx.x] = make_float2(tw.c[j], -tw.s[j]);
+    }
+  }
   const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev : a.frame0;
   if constexpr (PERSIST) {
     const int64_t ngroups = (a.total - a.item0 + SPB - 1) / SPB;
@@ -656,12 +666,12 @@ __global__ __launch_bounds__(SPB * CONV_N) __attribute__((amdgpu_waves_per_eu(WP
       int zero = 0;
       if constexpr (BL) asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
       wfs_fused_group<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, SPLIT, SUB, DSPLIT, BL>(a, g, frame_base, s_re, s_im,
-                                                                                (int)threadIdx.x + zero);
+                                                                                (int)threadIdx.x + zero, s_qtw);
       __syncthreads();
     }
   } else {
     wfs_fused_group<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, SPLIT, SUB, DSPLIT, BL>(a, blockIdx.x, frame_base, s_re,
-                                                                              s_im, (int)threadIdx.x);
+                                                                              s_im, (int)threadIdx.x, s_qtw);
   }
 }
 
