@@ -111,18 +111,18 @@ __device__ __forceinline__ void poisson_inversion_n(const float (&lam)[NJ], cons
     k[j] = 0;
     act[j] = use[j] && u[j] > F[j];
   }
+  // Branch-free steps: p and F advance for every entry, which leaves the finished ones finished
+  // (F only grows), and k takes the step number while the entry is still searching.
 #pragma unroll 1
   for (int kk = 1; kk <= kInversionMaxK; ++kk) {
     bool any = false;
     const float r = kRcp.v[kk];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      if (act[j]) {
-        p[j] = (p[j] * lam[j]) * r;
-        F[j] = F[j] + p[j];
-        k[j] = kk;
-        act[j] = u[j] > F[j];
-      }
+      k[j] = act[j] ? kk : k[j];
+      p[j] = (p[j] * lam[j]) * r;
+      F[j] = F[j] + p[j];
+      act[j] = act[j] && u[j] > F[j];
       any = any || act[j];
     }
     if (!any) break;
@@ -159,10 +159,12 @@ __device__ __forceinline__ int poisson_ptrs(float lam, float u0, float v0, uint3
 }
 
 // Standard normal from words 2 and 3 of the trial-0 block (Box-Muller).  No integer
-// decision depends on it, so the hardware cosine (argument in revolutions) and log2
-// are used: their ~1e-6 relative error is far below the read-noise tolerance.
+// decision depends on it, so the hardware cosine (argument in revolutions), log2 and square
+// root are used: their ~1e-6 relative error is far below the read-noise tolerance.
 __device__ __forceinline__ float read_noise_z(uint4 w) {
-  return sqrtf(-2.0f * __logf(u01(w.z))) * __builtin_amdgcn_cosf(u01(w.w));
+  // -2 ln u = -2 ln(2) log2(u); u >= 2^-24 is a normal number, so the raw log2 needs no scaling
+  return __builtin_amdgcn_sqrtf(-1.38629436111989061f * __builtin_amdgcn_logf(u01(w.z))) *
+         __builtin_amdgcn_cosf(u01(w.w));
 }
 
 // Electrons of one pixel with mean lam: Poisson counts + ron * N(0, 1).

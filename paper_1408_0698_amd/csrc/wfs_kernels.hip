@@ -688,7 +688,8 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   __shared__ int q_pix[4][NPIX];
   __shared__ float q_val[4][4][NPIX];
   const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev : a.frame0;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: item arithmetic on the scalar unit
   const int64_t item = a.item0 + (int64_t)blockIdx.x * 4 + wave;
   if (item >= a.total) return;  // whole wavefronts leave together; no block barrier below
   const ItemRef ref = resolve_item(a, item, frame_base, NPIX);
