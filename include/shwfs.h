@@ -252,8 +252,9 @@ int shw_wfs_plan_destroy(shw_wfs_plan* plan);
  * plans 3 and 4) compute the column spectrum of the spot from
  * autocorrelations of the row transforms and filter only the rows inside
  * the spot's band.  New plans start on the fastest measured variant: 12 for
- * band-limited 40-point shapes, 9 for the other 40-point shapes, 3 for
- * band-limited sodium plans, 2 for the other sodium plans, 0 otherwise.  shw_wfs_plan_autotune times every variant on the given inputs
+ * band-limited 40-point shapes, 9 for the other 40-point shapes, 4 for
+ * band-limited sodium plans, 2 for the other sodium plans, 0 otherwise.
+ * shw_wfs_plan_autotune times every variant on the given inputs
  * (reps launches each after two warm-up launches, HIP events on the stream;
  * synchronous), selects the fastest and returns its index in *best and the
  * per-variant milliseconds per launch in ms (nullable, n entries).

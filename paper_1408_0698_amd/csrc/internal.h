@@ -26,6 +26,9 @@ struct WfsLaunch {
   uint8_t* flags;            // nullable [items]
   int64_t total;             // n_frames * n_wfs * n_valid
   int32_t n_valid, n_wfs, n_subap, pad0;
+  // division by n_wfs * n_valid, n_valid and n_subap for dividends below 2^31 (host-filled by
+  // div_magic): q = (umulhi(n, m) + n) >> s
+  uint32_t dm_frame_m, dm_frame_s, dm_valid_m, dm_valid_s, dm_subap_m, dm_subap_s;
   double inv_lambda;         // 1 / wavelength (1/m)
   float r2_outer, r2_inner;  // pupil annulus in squared pixel units
   float half_n;              // pupil_n / 2
@@ -49,6 +52,17 @@ struct WfsLaunch {
   int64_t det_ws_items;
   int64_t item0;
 };
+
+// Multiplier m and shift s for unsigned division by an invariant d (1 <= d < 2^31) of dividends
+// n < 2^31: with l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1, floor(n / d) =
+// (umulhi(n, m) + n) >> l (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994, Theorem 4.2; the sum stays below 2^32 because n < 2^31).
+inline void div_magic(uint32_t d, uint32_t* m, uint32_t* s) {
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  *m = (uint32_t)((((1ull << l) - d) << 32) / d + 1);
+  *s = l;
+}
 
 // Shape of a compiled fused kernel.
 struct WfsShape {

@@ -95,13 +95,15 @@ __device__ __forceinline__ int poisson_inversion(float lam, float u) {
   return k;
 }
 
-// NJ independent inversions advanced in lockstep (the same arithmetic as poisson_inversion):
-// the searches of a lane overlap instead of running one after another.  Entries with
-// use[j] false keep k[j] = 0.
-template <int NJ>
-__device__ __forceinline__ void poisson_inversion_n(const float (&lam)[NJ], const float (&u)[NJ],
-                                                    const bool (&use)[NJ], int (&k)[NJ]) {
+// The first STEPS steps of NJ independent inversions, advanced in lockstep with the arithmetic
+// of poisson_inversion: the searches of a lane overlap instead of running one after another.
+// Entries with use[j] false keep k[j] = 0.  more[j] is set for an entry still searching after
+// STEPS steps; poisson_inversion run on it from the start then gives its count (the same steps).
+template <int NJ, int STEPS>
+__device__ __forceinline__ void poisson_inversion_head(const float (&lam)[NJ], const float (&u)[NJ],
+                                                       const bool (&use)[NJ], int (&k)[NJ], bool (&more)[NJ]) {
 #pragma clang fp contract(off)
+  static_assert(STEPS < kInversionMaxK, "head steps");
   float p[NJ], F[NJ];
   bool act[NJ];
 #pragma unroll
@@ -113,9 +115,8 @@ __device__ __forceinline__ void poisson_inversion_n(const float (&lam)[NJ], cons
   }
   // Branch-free steps: p and F advance for every entry, which leaves the finished ones finished
   // (F only grows), and k takes the step number while the entry is still searching.
-#pragma unroll 1
-  for (int kk = 1; kk <= kInversionMaxK; ++kk) {
-    bool any = false;
+#pragma unroll
+  for (int kk = 1; kk <= STEPS; ++kk) {
     const float r = kRcp.v[kk];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
@@ -123,10 +124,10 @@ __device__ __forceinline__ void poisson_inversion_n(const float (&lam)[NJ], cons
       p[j] = (p[j] * lam[j]) * r;
       F[j] = F[j] + p[j];
       act[j] = act[j] && u[j] > F[j];
-      any = any || act[j];
     }
-    if (!any) break;
   }
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) more[j] = act[j];
 }
 
 __device__ __forceinline__ int poisson_ptrs(float lam, float u0, float v0, uint32_t pix, uint32_t gsub,

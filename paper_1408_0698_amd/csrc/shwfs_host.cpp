@@ -505,6 +505,9 @@ static WfsLaunch base_launch(const shw_wfs_plan* p) {
   a.n_valid = p->n_valid;
   a.n_wfs = p->n_wfs;
   a.n_subap = c.n_subap;
+  div_magic((uint32_t)(p->n_wfs * p->n_valid), &a.dm_frame_m, &a.dm_frame_s);
+  div_magic((uint32_t)p->n_valid, &a.dm_valid_m, &a.dm_valid_s);
+  div_magic((uint32_t)c.n_subap, &a.dm_subap_m, &a.dm_subap_s);
   a.inv_lambda = 1.0 / c.wavelength_m;
   const double h = c.pupil_n / 2.0;
   a.r2_outer = (float)(h * h);

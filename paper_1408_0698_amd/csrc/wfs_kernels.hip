@@ -80,6 +80,32 @@ __device__ __forceinline__ float quad_swap2(float v) {
 __device__ __forceinline__ float2 quad_swap2(float2 v) { return make_float2(quad_swap2(v.x), quad_swap2(v.y)); }
 
 
+// floor(n / d) for n < 2^31, with (m, s) from div_magic(d).
+__device__ __forceinline__ uint32_t udiv_magic(uint32_t n, uint32_t m, uint32_t s) {
+  return (__umulhi(n, m) + n) >> s;
+}
+
+// v + (v of the lane selected by the DPP control), FP64 as two 32-bit moves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_add_f64(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+  return v + __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+// Sum over the 64 lanes of a wavefront (all lanes active), the same value in every lane: lane
+// pairs and quads (quad permutations), rows of 16 (rotations by 4 and 8), then the four rows.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = dpp_add_f64<0xB1>(v);   // quad_perm 1, 0, 3, 2
+  v = dpp_add_f64<0x4E>(v);   // quad_perm 2, 3, 0, 1
+  v = dpp_add_f64<0x124>(v);  // row_ror 4
+  v = dpp_add_f64<0x128>(v);  // row_ror 8
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
 // Per-item output buffers and noise key: from the work list, or the launch-wide layout.
 struct ItemRef {
   int f, w, i;
@@ -93,10 +119,18 @@ struct ItemRef {
 __device__ __forceinline__ ItemRef resolve_item(const WfsLaunch& a, int64_t it, uint32_t frame_base, int npix) {
   ItemRef r;
   const int64_t per_frame = (int64_t)a.n_wfs * a.n_valid;
-  r.f = (int)(it / per_frame);
-  const int rem = (int)(it - (int64_t)r.f * per_frame);
-  r.w = rem / a.n_valid;
-  r.i = rem - r.w * a.n_valid;
+  if (it < (int64_t)0x80000000) {
+    const uint32_t n = (uint32_t)it;
+    r.f = (int)udiv_magic(n, a.dm_frame_m, a.dm_frame_s);
+    const uint32_t rem = n - (uint32_t)r.f * (uint32_t)per_frame;
+    r.w = (int)udiv_magic(rem, a.dm_valid_m, a.dm_valid_s);
+    r.i = (int)rem - r.w * a.n_valid;
+  } else {
+    r.f = (int)(it / per_frame);
+    const int rem = (int)(it - (int64_t)r.f * per_frame);
+    r.w = rem / a.n_valid;
+    r.i = rem - r.w * a.n_valid;
+  }
   r.key0 = a.key0;
   r.key1 = a.key1;
   r.frame = frame_base + (uint32_t)r.f;
@@ -171,7 +205,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   const ItemRef ref = resolve_item(a, it, frame_base, DET_N * DET_N);
   const int w = ref.w, i = ref.i;
   const int sidx = a.valid_idx[i];
-  const int sa = sidx / a.n_subap;
+  const int sa = (int)udiv_magic((uint32_t)sidx, a.dm_subap_m, a.dm_subap_s);
   const int sb = sidx - sa * a.n_subap;
   float* re = s_re + s * PLANE;
   float* im = s_im + s * PLANE;
@@ -197,6 +231,10 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
     const int k2 = l - y * R;
     const int prow = sa * NPX + y;
     const float* src = opd_f + (int64_t)w * wfs_stride + (int64_t)prow * row_pitch + (int64_t)sb * NPX;
+    // sub-layer kernels: the column offset passes through an opaque move in every sub-layer, so
+    // that the per-pixel coordinates are recomputed there rather than kept live across the loop
+    int x0 = sb * NPX;
+    if constexpr (SUB) asm volatile("" : "+v"(x0));
     const float ay = (float)prow + 0.5f - a.half_n;
     const float ay2 = ay * ay;
     const double rb = (double)((FFT_N - 1) * y) * (1.0 / (2.0 * FFT_N));
@@ -209,14 +247,20 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       const double dy = (double)ay - a.launch_px[2 * w + 1];
       qy = c_sub * dy * dy;
     }
+    // every OPD sample of the row is inside the pupil grid: load them all first, so that the
+    // loads are in flight together, and mask unlit pixels by amplitude (no branch per pixel)
+    float ov[NPX];
+#pragma unroll
+    for (int x = 0; x < NPX; ++x) ov[x] = src[x];
     float2 z[NPX];
 #pragma unroll
     for (int x = 0; x < NPX; ++x) {
-      const float ax = (float)(sb * NPX + x) + 0.5f - a.half_n;
+      const float ax = (float)(x0 + x) + 0.5f - a.half_n;
       const float r2 = ax * ax + ay2;
       const bool lit = (r2 <= a.r2_outer) && (r2 >= a.r2_inner);
+      const float amp = lit ? 1.0f : 0.0f;
       // waves: OPD / lambda + centring ramp (FFT_N-1)(x+y)/(2 FFT_N) - x k2 / FFT_N = rb + x rx
-      double wv = (double)src[x] * a.inv_lambda + ((double)x * rx + rb);
+      double wv = (double)ov[x] * a.inv_lambda + ((double)x * rx + rb);
       if constexpr (SUB) {
         const double dx = (double)ax - lx;
         wv += qy + c_sub * dx * dx;
@@ -224,7 +268,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       wv -= floor(wv);
       // hardware sine/cosine take the argument in revolutions: exp(2 pi i wv) after the FP64 reduction
       const float fw = (float)wv;
-      z[x] = lit ? make_float2(__builtin_amdgcn_cosf(fw), __builtin_amdgcn_sinf(fw)) : make_float2(0.0f, 0.0f);
+      z[x] = make_float2(amp * __builtin_amdgcn_cosf(fw), amp * __builtin_amdgcn_sinf(fw));
     }
     RegFFT<NPX, -1>::run(z);
 #pragma unroll
@@ -244,20 +288,30 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       float2 g[NPX];
 #pragma unroll
       for (int y = 0; y < NPX; ++y) g[y] = make_float2(re[y * ST + l], im[y * ST + l]);
-      float e0 = 0.0f;
+      // one FMA per real product: 4 per complex term
+      float e0 = g[0].x * g[0].x;
+      e0 = fmaf(g[0].y, g[0].y, e0);
 #pragma unroll
-      for (int y = 0; y < NPX; ++y) e0 += g[y].x * g[y].x + g[y].y * g[y].y;
-      ac[0].x += e0 * wgt;
+      for (int y = 1; y < NPX; ++y) {
+        e0 = fmaf(g[y].x, g[y].x, e0);
+        e0 = fmaf(g[y].y, g[y].y, e0);
+      }
+      ac[0].x = fmaf(e0, wgt, ac[0].x);
 #pragma unroll
       for (int k = 1; k < NPX; ++k) {
-        float2 t = make_float2(0.0f, 0.0f);
+        // G[y] conj(G[y + k])
+        float tx = g[0].x * g[k].x, ty = g[0].y * g[k].x;
+        tx = fmaf(g[0].y, g[k].y, tx);
+        ty = fmaf(-g[0].x, g[k].y, ty);
 #pragma unroll
-        for (int y = 0; y + k < NPX; ++y) {
-          // G[y] conj(G[y + k])
-          t.x += g[y].x * g[y + k].x + g[y].y * g[y + k].y;
-          t.y += g[y].y * g[y + k].x - g[y].x * g[y + k].y;
+        for (int y = 1; y + k < NPX; ++y) {
+          tx = fmaf(g[y].x, g[y + k].x, tx);
+          tx = fmaf(g[y].y, g[y + k].y, tx);
+          ty = fmaf(g[y].y, g[y + k].x, ty);
+          ty = fmaf(-g[y].x, g[y + k].y, ty);
         }
-        ac[k] = cadd(ac[k], cscale(t, wgt));
+        ac[k].x = fmaf(tx, wgt, ac[k].x);
+        ac[k].y = fmaf(ty, wgt, ac[k].y);
       }
     }
   } else {
@@ -372,6 +426,17 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
         constexpr int M4 = CONV_N / 4;
         const int r4 = l >> 2, q = l & 3;
         if (active) {
+          const int m = ((q & 1) << 1) | (q >> 1);
+          // K^ row r4 at the lane's spectral samples c + (N/4) m, zero outside the spot's band;
+          // loaded unconditionally (in bounds for every lane) before the forward transform
+          float khv[M4];
+#pragma unroll
+          for (int c = 0; c < M4; ++c) khv[c] = kh_item[r4 * CONV_N + c + M4 * m];
+#pragma unroll
+          for (int c = 0; c < M4; ++c) {
+            const int j = c + M4 * m;
+            khv[c] = (j < NPX || j > CONV_N - NPX) ? khv[c] : 0.0f;
+          }
           float2 xq[M4];
 #pragma unroll
           for (int t = 0; t < M4; ++t) xq[t] = make_float2(re[r4 * ST + 4 * t + q], im[r4 * ST + 4 * t + q]);
@@ -380,7 +445,6 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
           // internal twiddle (-i forward, +i inverse) applied by lane 3 to its own value
           const float s2 = (q & 2) ? -1.0f : 1.0f, s1 = (q & 1) ? -1.0f : 1.0f;
           const bool l3 = q == 3;
-          const int m = ((q & 1) << 1) | (q >> 1);
 #pragma unroll
           for (int c = 0; c < M4; ++c) {
             const float2 w = qtw[q * M4 + c];  // W_N^(q c)
@@ -392,9 +456,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
             o = pair_swap(v);
             v = make_float2(o.x + s1 * v.x, o.y + s1 * v.y);
             // filter: the spectrum is zero beyond NPX - 1 samples from 0 (band limit of the spot)
-            const int j = c + M4 * m;
-            const bool band = j < NPX || j > CONV_N - NPX;
-            v = band ? cscale(v, kh_item[r4 * CONV_N + j]) : make_float2(0.0f, 0.0f);
+            v = cscale(v, khv[c]);
             // inverse: pairs q ^ 1, internal twiddle, pairs q ^ 2
             o = pair_swap(v);
             v = make_float2(o.x + s1 * v.x, o.y + s1 * v.y);
@@ -682,9 +744,9 @@ template <int DET_N>
 __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   constexpr int NPIX = DET_N * DET_N;
   constexpr float CD = 0.5f * (float)(DET_N - 1);
-  // pixels with mean >= 10 (rejection sampler) queued per wavefront: pixel, mean, the two
-  // uniforms of trial 0 and the read-noise deviate, so that the sampler runs once for up to 64
-  // of them
+  // per-wavefront pixel queues: long inversions (pixel, mean, uniform, read-noise deviate) from
+  // the front, means >= 10 for the rejection sampler (pixel, mean, the two uniforms of trial 0,
+  // read-noise deviate) from the back, so that each runs once for up to 64 pixels
   __shared__ int q_pix[4][NPIX];
   __shared__ float q_val[4][4][NPIX];
   const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev : a.frame0;
@@ -710,8 +772,14 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
     u[j] = u01(wd[j].x);
     small[j] = need_rng && pix < NPIX && v[j] > 0.0f && v[j] < 10.0f;
   }
+  // Inversions: a few lockstep steps for the lane's pixels (most means are small and end there);
+  // the ones still searching go to queue A and restart one per lane, so that the lane's long
+  // searches do not hold its other pixels.  Means >= 10 go to queue B (rejection sampler).  Both
+  // queues share the LDS arrays: A from the front, B from the back.
+  constexpr int HEAD = 4;
   int k[NJ];
-  poisson_inversion_n<NJ>(v, u, small, k);
+  bool more[NJ];
+  poisson_inversion_head<NJ, HEAD>(v, u, small, k, more);
   double s0 = 0.0, sx = 0.0, sy = 0.0;
   auto accumulate = [&](int pix, float img) {
     if (ref.images_it) ref.images_it[pix] = img;
@@ -723,15 +791,22 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
     sy += (double)((float)p - CD) * t;
   };
   const uint64_t below = (1ull << lane) - 1ull;
-  int nq = 0;
+  int na = 0, nq = 0;
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     const int pix = lane + 64 * j;
     const bool in = pix < NPIX;
     const bool big = need_rng && in && v[j] >= 10.0f;
-    const uint64_t m = __ballot(big);
-    if (big) {
-      const int e = nq + __popcll(m & below);
+    const uint64_t ma = __ballot(more[j]);
+    const uint64_t mb = __ballot(big);
+    if (more[j]) {
+      const int e = na + __popcll(ma & below);
+      q_pix[wave][e] = pix;
+      q_val[wave][0][e] = v[j];
+      q_val[wave][1][e] = u[j];
+      q_val[wave][3][e] = read_noise_z(wd[j]);
+    } else if (big) {
+      const int e = NPIX - 1 - (nq + __popcll(mb & below));
       q_pix[wave][e] = pix;
       q_val[wave][0][e] = v[j];
       q_val[wave][1][e] = u[j];
@@ -740,23 +815,28 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
     } else if (in) {
       accumulate(pix, need_rng ? (float)k[j] + a.ron * read_noise_z(wd[j]) : v[j]);
     }
-    nq += __popcll(m);
+    na += __popcll(ma);
+    nq += __popcll(mb);
   }
-  // the queue is written and read by this wavefront only: order its LDS accesses
+  // the queues are written and read by this wavefront only: order its LDS accesses
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  for (int e = lane; e < nq; e += 64) {
+  for (int e = lane; e < na; e += 64) {
+    const int kp = poisson_inversion(q_val[wave][0][e], q_val[wave][1][e]);
+    accumulate(q_pix[wave][e], (float)kp + a.ron * q_val[wave][3][e]);
+  }
+  for (int t = lane; t < nq; t += 64) {
+    const int e = NPIX - 1 - t;
     const int pix = q_pix[wave][e];
     const int kp = poisson_ptrs(q_val[wave][0][e], q_val[wave][1][e], q_val[wave][2][e], (uint32_t)pix, gsub,
                                 ref.frame, ref.key0, ref.key1);
     accumulate(pix, (float)kp + a.ron * q_val[wave][3][e]);
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    s0 += __shfl_xor(s0, o, 64);
-    sx += __shfl_xor(sx, o, 64);
-    sy += __shfl_xor(sy, o, 64);
-  }
+  // every lane of the wavefront is active here: sums within rows of 16 lanes by DPP, then the
+  // four row sums
+  s0 = wave_sum(s0);
+  sx = wave_sum(sx);
+  sy = wave_sum(sy);
   if (lane == 0) {
     const bool empty = !(s0 > 0.0);
     ref.slopes_fw[ref.i] = empty ? 0.0f : (float)(sx / s0);
@@ -904,10 +984,11 @@ int wfs_variant_count(const WfsShape& s) {
 }
 
 int wfs_default_variant(const WfsShape& s) {
-  // measured on the 6-LGS frame, with and without noise and sub-layers: the band-limited one-shot
-  // kernel where the shape allows it, else split rows + detector split + persistent grid
+  // measured on the 6-LGS frame, with and without noise and sub-layers: the band-limited kernel
+  // where the shape allows it (one-shot; persistent with sub-layers), else split rows + detector
+  // split + persistent grid
   const bool bl = s.lgs && s.fft_n == s.conv_n && s.conv_n == 4 * s.npx;
-  if (s.sub) return bl ? 3 : 2;
+  if (s.sub) return bl ? 4 : 2;
   if (!(s.conv_n == 40 && s.det_n == 16)) return 0;
   return bl ? 12 : 9;
 }
