@@ -32,7 +32,7 @@ READINGS = {
     "O5": "elongated Gaussian, hexagonal edge launchers, periodised on a symmetric lattice",
     "O6": "circular convolution by DFT multiply",
     "O7": "area-overlap rebin",
-    "O8": "photometry scaled by illuminated fraction; Philox4x32-10 Poisson + read noise",
+    "O8": "photometry scaled by illuminated fraction; Philox4x32-10 pair blocks: Poisson + read noise",
     "O9": "thresholded centre of gravity, zero slopes and a flag when nothing is left",
     "O11": "fftshift-centred PSF normalised by (sum A)^2; Strehl = on-axis sample",
     "O12": "Gaussian influence functions, integer-pixel DM and screen shifts",

@@ -16,10 +16,17 @@ than by consumption order (reading O8):
   Insurance: Mathematics and Economics 12 (1993) 39-45, for lambda >= 10.
   Both decide an integer, so they run in FP32 arithmetic, the precision
   the GPU path takes the same decision in.
-* Read noise: Box-Muller on words 2 and 3 of the trial-0 block.
+* Read noise: Box-Muller on words 2 and 3 of a pair block, both of its
+  normal deviates used.
 
-Counter of pixel p of global sub-aperture g in frame f at trial t:
-(t, p, g, f); key: (seed mod 2^32, seed div 2^32).
+Counters (key: (seed mod 2^32, seed div 2^32)), for a sub-aperture image of
+n pixels, h = ceil(n / 2), global sub-aperture g, frame f:
+* pair block b < h: counter (0, b, g, f).  It serves pixels b and b + h (the
+  latter if b + h < n): word 0 is the inversion uniform of pixel b, word 1
+  that of pixel b + h; Box-Muller on words 2 and 3 gives r cos(theta) to
+  pixel b and r sin(theta) to pixel b + h.
+* rejection-sampler trial t = 1, 2, ... of pixel p: counter (t, p, g, f),
+  words 0 and 1 the trial's two uniforms.
 """
 from __future__ import annotations
 
@@ -138,31 +145,40 @@ def ptrs_trial_f32(lam, u, v):
     return kc, accept
 
 
-def poisson_counts(lam, seed, pix, gsub, frame):
-    """Poisson counts for expected values lam (any shape) at the given counters."""
+def pair_block(seed, pix, npix, gsub, frame):
+    """Words of the pair block that serves each pixel, and whether the pixel is the second of its pair."""
+    pix = np.asarray(pix, dtype=np.uint64)
+    h = np.uint64((int(npix) + 1) // 2)
+    second = pix >= h
+    b = np.where(second, pix - h, pix)
+    return noise_words(seed, np.zeros_like(b), b, gsub, frame), second
+
+
+def _flat(shape, v):
+    return np.broadcast_to(np.asarray(v, dtype=np.uint64), shape).ravel()
+
+
+def poisson_counts(lam, seed, pix, gsub, frame, npix):
+    """Poisson counts for expected values lam (any shape) of pixels pix of n = npix-pixel images."""
     lam = np.asarray(lam, dtype=np.float32)
     shape = lam.shape
     lam = lam.ravel()
-    pix = np.broadcast_to(np.asarray(pix, dtype=np.uint64), shape).ravel()
-    gsub = np.broadcast_to(np.asarray(gsub, dtype=np.uint64), shape).ravel()
-    frame = np.broadcast_to(np.asarray(frame, dtype=np.uint64), shape).ravel()
+    pix, gsub, frame = (_flat(shape, v) for v in (pix, gsub, frame))
+    assert np.all(pix < np.uint64(npix))
     out = np.zeros(lam.shape, dtype=np.int64)
-    w = noise_words(seed, np.zeros_like(pix), pix, gsub, frame)
+    w, second = pair_block(seed, pix, npix, gsub, frame)
     small = (lam > 0) & (lam < POISSON_SPLIT)
     if np.any(small):
-        out[small] = poisson_inversion_f32(lam[small], uniform_f32(w[0][small]))
+        u = uniform_f32(np.where(second, w[1], w[0]))
+        out[small] = poisson_inversion_f32(lam[small], u[small])
     big = np.nonzero(lam >= POISSON_SPLIT)[0]
     done = np.zeros(big.shape, dtype=bool)
-    for t in range(PTRS_MAX_TRIALS):
+    for t in range(1, PTRS_MAX_TRIALS + 1):
         idx = big[~done]
         if idx.size == 0:
             break
-        if t == 0:
-            u, v = w[0][idx], w[1][idx]
-        else:
-            wt = noise_words(seed, np.full(idx.shape, t, np.uint64), pix[idx], gsub[idx], frame[idx])
-            u, v = wt[0], wt[1]
-        k, acc = ptrs_trial_f32(lam[idx], uniform_f32(u), uniform_f32(v))
+        wt = noise_words(seed, np.full(idx.shape, t, np.uint64), pix[idx], gsub[idx], frame[idx])
+        k, acc = ptrs_trial_f32(lam[idx], uniform_f32(wt[0]), uniform_f32(wt[1]))
         out[idx[acc]] = k[acc]
         sel = np.nonzero(~done)[0]
         done[sel[acc]] = True
@@ -172,17 +188,17 @@ def poisson_counts(lam, seed, pix, gsub, frame):
     return out.reshape(shape)
 
 
-def read_noise(seed, pix, gsub, frame):
-    """Standard normal per pixel: sqrt(-2 ln u1) cos(2 pi u2) from words 2, 3 of trial 0 (FP64)."""
+def read_noise(seed, pix, gsub, frame, npix):
+    """Standard normal per pixel (FP64): r cos(theta) or r sin(theta) of its pair block's Box-Muller,
+    r = sqrt(-2 ln u2), theta = 2 pi u3."""
     pix = np.asarray(pix, dtype=np.uint64)
     shape = np.broadcast_shapes(pix.shape, np.shape(gsub), np.shape(frame))
-    pix = np.broadcast_to(pix, shape).ravel()
-    gsub = np.broadcast_to(np.asarray(gsub, dtype=np.uint64), shape).ravel()
-    frame = np.broadcast_to(np.asarray(frame, dtype=np.uint64), shape).ravel()
-    w = noise_words(seed, np.zeros_like(pix), pix, gsub, frame)
-    u1 = uniform_f32(w[2]).astype(np.float64)
-    u2 = uniform_f32(w[3]).astype(np.float64)
-    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    pix, gsub, frame = (_flat(shape, v) for v in (pix, gsub, frame))
+    assert np.all(pix < np.uint64(npix))
+    w, second = pair_block(seed, pix, npix, gsub, frame)
+    r = np.sqrt(-2.0 * np.log(uniform_f32(w[2]).astype(np.float64)))
+    theta = 2.0 * np.pi * uniform_f32(w[3]).astype(np.float64)
+    z = r * np.where(second, np.sin(theta), np.cos(theta))
     return z.reshape(shape)
 
 

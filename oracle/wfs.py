@@ -111,8 +111,8 @@ def add_noise(cfg, lam, seed, gsub, frame):
     S, d, _ = lam.shape
     pix = np.arange(d * d, dtype=np.uint64).reshape(1, d, d)
     g = np.asarray(gsub, dtype=np.uint64).reshape(S, 1, 1)
-    counts = P.poisson_counts(lam.astype(np.float32), seed, pix, g, np.uint64(frame))
-    z = P.read_noise(seed, pix, g, np.uint64(frame))
+    counts = P.poisson_counts(lam.astype(np.float32), seed, pix, g, np.uint64(frame), d * d)
+    z = P.read_noise(seed, pix, g, np.uint64(frame), d * d)
     return counts.astype(np.float64) + cfg.ron_e * z, counts
 
 

@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void big_detect_kernel(const BigLaunch a, int6
     float img = det;
     if (a.ph_scale > 0.0f) {
       const float lam = a.ph_scale * det;
-      img = a.noise ? noisy_pixel(lam, a.ron, (uint32_t)pix, gsub, frame, key0, key1) : lam;
+      img = a.noise ? noisy_pixel(lam, a.ron, (uint32_t)pix, (uint32_t)npix, gsub, frame, key0, key1) : lam;
     }
     if (images_it) images_it[pix] = img;
     const double t = (double)fmaxf(img - a.thr, 0.0f);

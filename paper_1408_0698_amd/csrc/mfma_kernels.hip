@@ -371,7 +371,7 @@ __global__ __launch_bounds__(64 * kWaves) void wfs_mfma_kernel(const WfsLaunch a
     float img = det[r];
     if (a.ph_scale > 0.0f) {
       const float lam = a.ph_scale * det[r];
-      img = a.noise ? noisy_pixel(lam, a.ron, (uint32_t)pix, gsub, frame, a.key0, a.key1) : lam;
+      img = a.noise ? noisy_pixel(lam, a.ron, (uint32_t)pix, 256u, gsub, frame, a.key0, a.key1) : lam;
     }
     if (a.images) a.images[item * 256 + pix] = img;
     const double t = (double)fmaxf(img - a.thr, 0.0f);

@@ -7,6 +7,12 @@
 // random variables" (1993) from mean 10; Gaussian read noise by
 // Box-Muller.  The integer decisions are taken in FP32 with contraction
 // off, operation by operation in the order written.
+//
+// Counters (key = seed), for an image of n pixels, h = ceil(n / 2), global
+// sub-aperture g, frame f: the pair block (0, b, g, f), b < h, serves pixels
+// b and b + h: words x and y are their inversion uniforms, and Box-Muller on
+// words z and w gives r cos(theta) to pixel b and r sin(theta) to pixel b + h.
+// Rejection-sampler trial t >= 1 of pixel p draws block (t, p, g, f).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -130,8 +136,10 @@ __device__ __forceinline__ void poisson_inversion_head(const float (&lam)[NJ], c
   for (int j = 0; j < NJ; ++j) more[j] = act[j];
 }
 
-__device__ __forceinline__ int poisson_ptrs(float lam, float u0, float v0, uint32_t pix, uint32_t gsub,
-                                         uint32_t frame, uint32_t k0, uint32_t k1) {
+// PTRS for mean lam >= 10 at pixel pix: trial t = 1 .. 64 takes the uniforms (u, v) from words x
+// and y of block (t, pix, gsub, frame); after 64 rejections, floor(lam + 1/2).
+__device__ __forceinline__ int poisson_ptrs(float lam, uint32_t pix, uint32_t gsub, uint32_t frame, uint32_t k0,
+                                            uint32_t k1) {
 #pragma clang fp contract(off)
   const float slam = sqrtf(lam);
   const float loglam = logf(lam);
@@ -139,15 +147,10 @@ __device__ __forceinline__ int poisson_ptrs(float lam, float u0, float v0, uint3
   const float a = -0.059f + 0.02483f * b;
   const float invalpha = 1.1239f + 1.1328f / (b - 3.4f);
   const float vr = 0.9277f - 3.6224f / (b - 2.0f);
-  float u = u0, v = v0;
-  for (uint32_t t = 0; t < 64u; ++t) {
-    if (t) {
-      const uint4 w = philox4x32_10(make_uint4(t, pix, gsub, frame), k0, k1);
-      u = u01(w.x);
-      v = u01(w.y);
-    }
-    const float U = u - 0.5f;
-    const float V = v;
+  for (uint32_t t = 1; t <= 64u; ++t) {
+    const uint4 w = philox4x32_10(make_uint4(t, pix, gsub, frame), k0, k1);
+    const float U = u01(w.x) - 0.5f;
+    const float V = u01(w.y);
     const float us = 0.5f - fabsf(U);
     const float kf = floorf((2.0f * a / us + b) * U + lam + 0.43f);
     if (us >= 0.07f && V <= vr) return kf > 0.0f ? (int)kf : 0;
@@ -159,27 +162,38 @@ __device__ __forceinline__ int poisson_ptrs(float lam, float u0, float v0, uint3
   return (int)floorf(lam + 0.5f);
 }
 
-// Standard normal from words 2 and 3 of the trial-0 block (Box-Muller).  No integer
-// decision depends on it, so the hardware cosine (argument in revolutions), log2 and square
-// root are used: their ~1e-6 relative error is far below the read-noise tolerance.
-__device__ __forceinline__ float read_noise_z(uint4 w) {
-  // -2 ln u = -2 ln(2) log2(u); u >= 2^-24 is a normal number, so the raw log2 needs no scaling
-  return __builtin_amdgcn_sqrtf(-1.38629436111989061f * __builtin_amdgcn_logf(u01(w.z))) *
-         __builtin_amdgcn_cosf(u01(w.w));
+// Pair block b of an image (serves pixels b and b + h).
+__device__ __forceinline__ uint4 pair_block(uint32_t b, uint32_t gsub, uint32_t frame, uint32_t k0, uint32_t k1) {
+  return philox4x32_10(make_uint4(0u, b, gsub, frame), k0, k1);
 }
 
-// Electrons of one pixel with mean lam: Poisson counts + ron * N(0, 1).
-__device__ __forceinline__ float noisy_pixel(float lam, float ron, uint32_t pix, uint32_t gsub, uint32_t frame,
-                                             uint32_t k0, uint32_t k1) {
-  const uint4 w = philox4x32_10(make_uint4(0u, pix, gsub, frame), k0, k1);
+// The two standard normals of a pair block (Box-Muller on words z and w): x for the first pixel
+// of the pair, y for the second.  No integer decision depends on them, so the hardware sine and
+// cosine (argument in revolutions), log2 and square root are used: their ~1e-6 relative error is
+// far below the read-noise tolerance.
+__device__ __forceinline__ float2 read_noise_pair(uint4 w) {
+  // -2 ln u = -2 ln(2) log2(u); u >= 2^-24 is a normal number, so the raw log2 needs no scaling
+  const float r = __builtin_amdgcn_sqrtf(-1.38629436111989061f * __builtin_amdgcn_logf(u01(w.z)));
+  const float t = u01(w.w);
+  return make_float2(r * __builtin_amdgcn_cosf(t), r * __builtin_amdgcn_sinf(t));
+}
+
+// Electrons of pixel pix of an npix-pixel image with mean lam: Poisson count + ron * N(0, 1).
+// Computes the pixel's pair block itself (kernels that hold both pixels of a pair share it).
+__device__ __forceinline__ float noisy_pixel(float lam, float ron, uint32_t pix, uint32_t npix, uint32_t gsub,
+                                             uint32_t frame, uint32_t k0, uint32_t k1) {
+  const uint32_t h = (npix + 1u) >> 1;
+  const bool second = pix >= h;
+  const uint4 w = pair_block(second ? pix - h : pix, gsub, frame, k0, k1);
   int k = 0;
   if (lam > 0.0f) {
     if (lam < 10.0f)
-      k = poisson_inversion(lam, u01(w.x));
+      k = poisson_inversion(lam, u01(second ? w.y : w.x));
     else
-      k = poisson_ptrs(lam, u01(w.x), u01(w.y), pix, gsub, frame, k0, k1);
+      k = poisson_ptrs(lam, pix, gsub, frame, k0, k1);
   }
-  return (float)k + ron * read_noise_z(w);
+  const float2 z = read_noise_pair(w);
+  return (float)k + ron * (second ? z.y : z.x);
 }
 
 }  // namespace shw

@@ -634,9 +634,10 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   }
   if constexpr (DSPLIT) return;  // noise and centroid: det_noise_kernel
   __syncthreads();
-  // every lane of the item takes pixels l, l + L, ...; two at a time so that their Philox
-  // chains interleave
-  auto finish = [&](int pix, float det, const uint4& wd) {
+  // every lane of the item takes pair blocks b = l, l + L, ... < h: pixels b and b + h share one
+  // Philox block (their two uniforms and the two Box-Muller deviates)
+  constexpr int PH = (NPIX + 1) / 2;
+  auto finish = [&](int pix, float det, float u, float z) {
     float img = det;
     if (a.ph_scale > 0.0f) {
       const float lam = a.ph_scale * det;
@@ -646,8 +647,8 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
           queue[atomicAdd(&queue[QCOUNT], 1)] = pix;
           return;
         }
-        const int k = lam > 0.0f ? poisson_inversion(lam, u01(wd.x)) : 0;
-        img = (float)k + a.ron * read_noise_z(wd);
+        const int k = lam > 0.0f ? poisson_inversion(lam, u) : 0;
+        img = (float)k + a.ron * z;
       }
     }
     accumulate(pix, img);
@@ -655,16 +656,15 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   if (active) {
     const bool need_rng = a.noise && a.ph_scale > 0.0f;
 #pragma unroll 1
-    for (int pix = l; pix < NPIX; pix += 2 * L) {
-      const int pix2 = pix + L;
-      const bool two = pix2 < NPIX;
-      uint4 w1 = make_uint4(0u, 0u, 0u, 0u), w2 = w1;
+    for (int b = l; b < PH; b += L) {
+      uint4 wd = make_uint4(0u, 0u, 0u, 0u);
+      float2 z = make_float2(0.0f, 0.0f);
       if (need_rng) {
-        w1 = philox4x32_10(make_uint4(0u, (uint32_t)pix, gsub, frame), key0, key1);
-        w2 = philox4x32_10(make_uint4(0u, (uint32_t)(two ? pix2 : pix), gsub, frame), key0, key1);
+        wd = pair_block((uint32_t)b, gsub, frame, key0, key1);
+        z = read_noise_pair(wd);
       }
-      finish(pix, det_area[pix], w1);
-      if (two) finish(pix2, det_area[pix2], w2);
+      finish(b, det_area[b], u01(wd.x), z.x);
+      if (b + PH < NPIX) finish(b + PH, det_area[b + PH], u01(wd.y), z.y);
     }
   }
   __syncthreads();
@@ -674,9 +674,10 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
     for (int e = l; e < nq; e += L) {
       const int pix = queue[e];
       const float lam = a.ph_scale * det_area[pix];
-      const uint4 wd = philox4x32_10(make_uint4(0u, (uint32_t)pix, gsub, frame), key0, key1);
-      const int k = poisson_ptrs(lam, u01(wd.x), u01(wd.y), (uint32_t)pix, gsub, frame, key0, key1);
-      accumulate(pix, (float)k + a.ron * read_noise_z(wd));
+      const bool second = pix >= PH;
+      const float2 z = read_noise_pair(pair_block((uint32_t)(second ? pix - PH : pix), gsub, frame, key0, key1));
+      const int k = poisson_ptrs(lam, (uint32_t)pix, gsub, frame, key0, key1);
+      accumulate(pix, (float)k + a.ron * (second ? z.y : z.x));
     }
   }
   double* red = reinterpret_cast<double*>(im + RED);
@@ -745,10 +746,10 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   constexpr int NPIX = DET_N * DET_N;
   constexpr float CD = 0.5f * (float)(DET_N - 1);
   // per-wavefront pixel queues: long inversions (pixel, mean, uniform, read-noise deviate) from
-  // the front, means >= 10 for the rejection sampler (pixel, mean, the two uniforms of trial 0,
-  // read-noise deviate) from the back, so that each runs once for up to 64 pixels
+  // the front, means >= 10 for the rejection sampler (pixel, mean, read-noise deviate) from the
+  // back, so that each runs once for up to 64 pixels
   __shared__ int q_pix[4][NPIX];
-  __shared__ float q_val[4][4][NPIX];
+  __shared__ float q_val[4][3][NPIX];
   const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev : a.frame0;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: item arithmetic on the scalar unit
@@ -759,18 +760,45 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   const uint32_t gsub = (uint32_t)(ref.w * a.n_valid + ref.i);
   const bool need_rng = a.noise && a.ph_scale > 0.0f;
   constexpr int NJ = (NPIX + 63) / 64;
-  float v[NJ], u[NJ];
+  // pair blocks serve pixels b and b + h; when h is a whole number of 64-pixel rounds
+  // (n = 128 m), pixel lane + 64 j pairs with lane + 64 (j + NJ / 2) of the same lane, which
+  // then draws one block for both
+  constexpr int PH = (NPIX + 1) / 2;
+  constexpr bool PAIRED = NJ % 2 == 0 && PH == 64 * (NJ / 2);
+  float v[NJ], u[NJ], z[NJ];
   bool small[NJ];
-  uint4 wd[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     const int pix = lane + 64 * j;
     v[j] = pix < NPIX ? det[pix] : 0.0f;
     if (a.ph_scale > 0.0f) v[j] = a.ph_scale * v[j];  // expected electrons
-    wd[j] = need_rng ? philox4x32_10(make_uint4(0u, (uint32_t)pix, gsub, ref.frame), ref.key0, ref.key1)
-                     : make_uint4(0u, 0u, 0u, 0u);
-    u[j] = u01(wd[j].x);
     small[j] = need_rng && pix < NPIX && v[j] > 0.0f && v[j] < 10.0f;
+  }
+  if (need_rng) {
+    if constexpr (PAIRED) {
+#pragma unroll
+      for (int j = 0; j < NJ / 2; ++j) {
+        const uint4 w = pair_block((uint32_t)(lane + 64 * j), gsub, ref.frame, ref.key0, ref.key1);
+        const float2 zz = read_noise_pair(w);
+        u[j] = u01(w.x);
+        z[j] = zz.x;
+        u[j + NJ / 2] = u01(w.y);
+        z[j + NJ / 2] = zz.y;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int pix = lane + 64 * j;
+        const bool second = pix >= PH;
+        const uint4 w = pair_block((uint32_t)(second ? pix - PH : pix), gsub, ref.frame, ref.key0, ref.key1);
+        const float2 zz = read_noise_pair(w);
+        u[j] = u01(second ? w.y : w.x);
+        z[j] = second ? zz.y : zz.x;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) u[j] = z[j] = 0.0f;
   }
   // Inversions: a few lockstep steps for the lane's pixels (most means are small and end there);
   // the ones still searching go to queue A and restart one per lane, so that the lane's long
@@ -804,16 +832,14 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
       q_pix[wave][e] = pix;
       q_val[wave][0][e] = v[j];
       q_val[wave][1][e] = u[j];
-      q_val[wave][3][e] = read_noise_z(wd[j]);
+      q_val[wave][2][e] = z[j];
     } else if (big) {
       const int e = NPIX - 1 - (nq + __popcll(mb & below));
       q_pix[wave][e] = pix;
       q_val[wave][0][e] = v[j];
-      q_val[wave][1][e] = u[j];
-      q_val[wave][2][e] = u01(wd[j].y);
-      q_val[wave][3][e] = read_noise_z(wd[j]);
+      q_val[wave][2][e] = z[j];
     } else if (in) {
-      accumulate(pix, need_rng ? (float)k[j] + a.ron * read_noise_z(wd[j]) : v[j]);
+      accumulate(pix, need_rng ? (float)k[j] + a.ron * z[j] : v[j]);
     }
     na += __popcll(ma);
     nq += __popcll(mb);
@@ -823,14 +849,13 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   __builtin_amdgcn_wave_barrier();
   for (int e = lane; e < na; e += 64) {
     const int kp = poisson_inversion(q_val[wave][0][e], q_val[wave][1][e]);
-    accumulate(q_pix[wave][e], (float)kp + a.ron * q_val[wave][3][e]);
+    accumulate(q_pix[wave][e], (float)kp + a.ron * q_val[wave][2][e]);
   }
   for (int t = lane; t < nq; t += 64) {
     const int e = NPIX - 1 - t;
     const int pix = q_pix[wave][e];
-    const int kp = poisson_ptrs(q_val[wave][0][e], q_val[wave][1][e], q_val[wave][2][e], (uint32_t)pix, gsub,
-                                ref.frame, ref.key0, ref.key1);
-    accumulate(pix, (float)kp + a.ron * q_val[wave][3][e]);
+    const int kp = poisson_ptrs(q_val[wave][0][e], (uint32_t)pix, gsub, ref.frame, ref.key0, ref.key1);
+    accumulate(pix, (float)kp + a.ron * q_val[wave][2][e]);
   }
   // every lane of the wavefront is active here: sums within rows of 16 lanes by DPP, then the
   // four row sums

@@ -180,11 +180,11 @@ def test_kernel_spectra_match_oracle(torch_dev):
 
 # ---------------------------------------------------------------- noise parity
 
-def _explained(lam_oracle, count_gpu, seed, pix, gsub, frame):
+def _explained(lam_oracle, count_gpu, seed, pix, gsub, frame, npix):
     """True if the oracle sampler gives count_gpu for an expected value within 1e-5 relative."""
     for d in (-1e-5, -3e-6, -1e-6, -3e-7, 3e-7, 1e-6, 3e-6, 1e-5):
         k = OP.poisson_counts(np.array([lam_oracle * (1 + d)], np.float32), seed, np.array([pix], np.uint64),
-                              np.array([gsub], np.uint64), np.uint64(frame))[0]
+                              np.array([gsub], np.uint64), np.uint64(frame), npix)[0]
         if k == count_gpu:
             return True
     return False
@@ -203,7 +203,7 @@ def check_noisy(cfg, n_wfs, launch, got, want, seed, frame0, gsub_of):
         for w in range(n_wfs):
             gi = gsub_of(w)
             pix = np.arange(d * d, dtype=np.uint64).reshape(1, d, d)
-            z = OP.read_noise(seed, pix, gi.astype(np.uint64).reshape(-1, 1, 1), np.uint64(frame0 + f))
+            z = OP.read_noise(seed, pix, gi.astype(np.uint64).reshape(-1, 1, 1), np.uint64(frame0 + f), d * d)
             cg = got["images"][f, w] - ron * z
             co = want["images"][f, w] - ron * z
             kg = np.rint(cg)
@@ -215,7 +215,7 @@ def check_noisy(cfg, n_wfs, launch, got, want, seed, frame0, gsub_of):
             for s_, p_, q_ in zip(*diff):
                 mism += 1
                 lam = want["lam"][f, w, s_, p_, q_]
-                assert _explained(lam, int(kg[s_, p_, q_]), seed, p_ * d + q_, gi[s_], frame0 + f), \
+                assert _explained(lam, int(kg[s_, p_, q_]), seed, p_ * d + q_, gi[s_], frame0 + f, d * d), \
                     f"unexplained count mismatch at frame {f} wfs {w} subap {s_} pixel ({p_},{q_}) lam {lam}"
                 bad_subaps[f, w, s_] = True
     assert mism <= max(2, 1e-5 * total), f"{mism} tie mismatches in {total} pixels"

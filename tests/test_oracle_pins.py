@@ -266,8 +266,9 @@ def test_uniform_is_exact_and_open():
 
 
 def _poisson_sample(lam, n, seed=77):
+    # one image of n pixels: pixels b and b + n/2 share a pair block
     pix = np.arange(n, dtype=np.uint64)
-    return P.poisson_counts(np.full(n, lam, np.float32), seed, pix, 5, 9)
+    return P.poisson_counts(np.full(n, lam, np.float32), seed, pix, 5, 9, n)
 
 
 @pytest.mark.parametrize("lam", [0.3, 2.5, 9.5, 10.0, 31.7, 250.0])
@@ -285,6 +286,10 @@ def test_poisson_moments_and_pmf(lam):
     chi2 = (((obs[m] - exp[m]) ** 2) / exp[m]).sum()
     dof = m.sum() - 1
     assert chi2 < dof + 6 * math.sqrt(2 * dof)
+    # the two pixels of a pair block draw independent counts (words 0 and 1, or their own trials)
+    h = n // 2
+    r = np.corrcoef(k[:h].astype(np.float64), k[h:].astype(np.float64))[0, 1]
+    assert abs(r) < 5 / math.sqrt(h)
 
 
 def test_poisson_inversion_small_uniform_gives_zero():
@@ -310,17 +315,40 @@ def test_inversion_matches_fp64_search_away_from_ties():
 
 
 def test_read_noise_unit_variance():
-    z = P.read_noise(11, np.arange(300_000, dtype=np.uint64), 2, 4)
+    n = 300_000
+    z = P.read_noise(11, np.arange(n, dtype=np.uint64), 2, 4, n)
     assert abs(z.mean()) < 0.01 and abs(z.var() - 1) < 0.01
     assert abs(np.mean(z ** 4) - 3) < 0.05
+    # both deviates of a Box-Muller pair: each standard normal, uncorrelated, and uncorrelated in
+    # their squares (r cos and r sin of one draw are independent)
+    h = n // 2
+    c, s_ = z[:h], z[h:]
+    for half in (c, s_):
+        assert abs(half.mean()) < 0.015 and abs(half.var() - 1) < 0.015
+    assert abs(np.corrcoef(c, s_)[0, 1]) < 5 / math.sqrt(h)
+    assert abs(np.corrcoef(c ** 2, s_ ** 2)[0, 1]) < 5 / math.sqrt(h)
+
+
+def test_pair_block_assignment():
+    # n = 5 pixels: h = 3; pixels (0, 3) and (1, 4) share blocks 0 and 1, pixel 2 has block 2 alone
+    pix = np.arange(5, dtype=np.uint64)
+    w, second = P.pair_block(21, pix, 5, 7, 3)
+    assert list(second) == [False, False, False, True, True]
+    w0 = P.noise_words(21, np.zeros(3, np.uint64), np.arange(3, dtype=np.uint64), 7, 3)
+    for i, b in enumerate([0, 1, 2, 0, 1]):
+        assert all(int(w[j][i]) == int(w0[j][b]) for j in range(4))
+    z = P.read_noise(21, pix, 7, 3, 5)
+    r = np.sqrt(-2.0 * np.log(P.uniform_f32(w0[2]).astype(np.float64)))
+    th = 2.0 * np.pi * P.uniform_f32(w0[3]).astype(np.float64)
+    assert np.allclose(z[:3] ** 2 + np.r_[z[3:], 0.0] ** 2, r ** 2 * np.r_[1.0, 1.0, np.cos(th[2]) ** 2])
 
 
 def test_noise_counters_are_independent_of_batching():
     lam = np.full((3, 4, 4), 5.0, np.float32)
     a = P.poisson_counts(lam, 9, np.arange(16, dtype=np.uint64).reshape(1, 4, 4),
-                         np.arange(3, dtype=np.uint64).reshape(3, 1, 1), 2)
+                         np.arange(3, dtype=np.uint64).reshape(3, 1, 1), 2, 16)
     b = P.poisson_counts(lam[1:2], 9, np.arange(16, dtype=np.uint64).reshape(1, 4, 4),
-                         np.array([1], np.uint64).reshape(1, 1, 1), 2)
+                         np.array([1], np.uint64).reshape(1, 1, 1), 2, 16)
     assert np.array_equal(a[1:2], b)
 
 
