@@ -324,6 +324,92 @@ int psf_accumulate_stars(shw_psf_plan* plan, const float* d_opd_m, int64_t row_p
 
 int shw_psf_plan_destroy(shw_psf_plan* plan);
 
+/*
+ * psf_encircled_energy - encircled energy of n_psf PSFs of the plan's size M
+ * (Sec. 3 PSF block: encircled energy in the chosen radius).  PSF s is the
+ * M x M FP32 array at d_psf + s*psf_stride (psf_stride >= M^2 when n_psf > 1),
+ * e.g. an accumulator of psf_accumulate.  For each radius r_px[k] (pixels,
+ * host array of 1 <= n_r <= 64 values >= 0):
+ *   d_ee[s*n_r + k] = sum of P over pixels (v, u) with (u - M/2)^2 + (v - M/2)^2 <= r^2
+ *                     divided by the sum of P over the whole array
+ * (FP64 sums in a fixed order: the same inputs give the same result).  M <=
+ * 4096 (SHW_E_UNSUPPORTED otherwise).  The plan keeps a workspace of n_psf *
+ * 64 * (n_r + 1) doubles; growing it synchronises the device.  Asynchronous
+ * otherwise; calls on one plan must not overlap.
+ */
+int psf_encircled_energy(shw_psf_plan* plan, const float* d_psf, int32_t n_psf, int64_t psf_stride, int32_t n_r,
+                         const double* r_px, double* d_ee, void* hip_stream);
+
+/*
+ * psf_resample_accumulate - put a PSF computed at wavelength lambda_i on the
+ * angular grid of a reference wavelength lambda_ref (both M x M, on-axis at
+ * pixel (M/2, M/2)) and add it with a weight (Sec. 3 PSF block: PSFs at
+ * several wavelengths combined by the colour of the object):
+ *   d_dst[v*M + u] += weight * S(M/2 + (v - M/2) scale, M/2 + (u - M/2) scale),
+ * scale = lambda_ref / lambda_i, S the bilinear interpolation of d_src
+ * (sample (y, x) at row y, column x); points outside [0, M-1]^2 add nothing.
+ * The PSF values are intensities relative to the diffraction-limited peak,
+ * so the on-axis value of the sum is the weighted sum of the Strehl ratios.
+ * d_src and d_dst must not overlap (SHW_E_INVALID).  Asynchronous.
+ */
+int psf_resample_accumulate(int32_t fft_m, const float* d_src, double scale, float weight, float* d_dst,
+                            void* hip_stream);
+
+
+/*
+ * Open-loop wavefronts of finite-altitude sources (Sec. 4 open-loop
+ * generation: shifted phase screens piled up per direction; an LGS sodium
+ * sub-layer is a source at its own altitude, whose pupil projection on each
+ * layer changes with the layer's altitude - the cone effect).
+ *
+ * Layers (1 <= n_layers <= 16): layer l is an FP32 OPD screen (metres) on the
+ * device at d_screen[l], screen_rows[l] x screen_cols[l] samples (both >= 2),
+ * rows screen_pitch[l] >= screen_cols[l] floats apart; layer_params[4l ..
+ * 4l+3] = (sample spacing m > 0, altitude m >= 0, x0, y0): the point above the
+ * telescope axis is at screen coordinates (x0, y0) in samples (sample (r, c)
+ * at coordinates (x, y) = (c, r)).  Host arrays.
+ *
+ * shw_project_layers - for target t (host target_params[3t .. 3t+2] =
+ * direction theta_x, theta_y in radians, source altitude H in metres, 0 for
+ * a source at infinity) and pupil pixel (i, j) of a pupil_n x pupil_n grid of
+ * spacing dx_m (centre r = ((j + 1/2 - pupil_n/2) dx, (i + 1/2 - pupil_n/2) dx)):
+ *   d_out[t*out_stride + i*out_pitch + j] =
+ *       sum_l S_l(x0_l + p_x / spacing_l, y0_l + p_y / spacing_l) + tilt_t . r,
+ *   p = (1 - h_l/H) r + h_l theta   (p = r + h_l theta for H = 0),
+ * S_l the bilinear interpolation of layer l, tilt_t = d_tilt[2t .. 2t+1]
+ * (radians, device, nullable: no tilt) - e.g. the uplink tilts below.  Every
+ * footprint must stay inside its screen and every finite-altitude target
+ * above every layer (SHW_E_INVALID otherwise); out_pitch >= pupil_n, and
+ * out_stride >= out_pitch * pupil_n when n_targets > 1.  FP64 positions and
+ * sums, FP32 output.  Asynchronous.
+ */
+int shw_project_layers(int32_t n_layers, const float* const* d_screen, const int32_t* screen_rows,
+                       const int32_t* screen_cols, const int64_t* screen_pitch, const double* layer_params,
+                       int32_t pupil_n, double dx_m, int32_t n_targets, const double* target_params,
+                       const double* d_tilt, float* d_out, int64_t out_pitch, int64_t out_stride, void* hip_stream);
+
+/*
+ * shw_uplink_tilt - tip-tilt picked up by each laser beam on its way up to
+ * the sodium layer (Sec. 4: the projection of the beam on the sodium layer is
+ * shifted by the tip-tilt integrated over the upward path).  LGS k (host
+ * lgs_params[5k .. 5k+4] = launcher position x, y in the pupil plane (m),
+ * direction theta_x, theta_y (rad), sodium altitude H > every layer's (m)):
+ * the beam, of diameter llt_diameter_m, is centred at launcher (1 - h/H) +
+ * h theta at altitude h.  It is sampled on an n_samples x n_samples grid
+ * (2..256) over the square of side llt_diameter_m, keeping the points inside
+ * the disc; the OPD at a sample is the sum over layers of the bilinear screen
+ * values (as for shw_project_layers), and the tilt is its least-squares
+ * slope over the samples (the sample set is symmetric, so it is
+ * sum(s_x OPD) / sum(s_x^2) and likewise in y):
+ *   d_tilt[2k], d_tilt[2k+1] = tilt in x and y, radians (device, FP64).
+ * Every beam footprint must stay inside its screen (SHW_E_INVALID).
+ * Asynchronous.  Adding the tilt to the sensor's wavefront (d_tilt of
+ * shw_project_layers) moves the spots of every sub-aperture by that angle.
+ */
+int shw_uplink_tilt(int32_t n_layers, const float* const* d_screen, const int32_t* screen_rows,
+                    const int32_t* screen_cols, const int64_t* screen_pitch, const double* layer_params,
+                    int32_t n_lgs, const double* lgs_params, double llt_diameter_m, int32_t n_samples,
+                    double* d_tilt, void* hip_stream);
 
 /*
  * Deformable mirrors and residual OPD (Sec. 3 closed-loop block: the residual

@@ -14,7 +14,10 @@ Each function cites the passage of the paper it follows:
   by convolution with a Gaussian, noise, centroid -> slopes.
 * Sec. 3, closed-loop block: X- and Y-slope vectors from the residual
   phase (open-loop wavefront minus the DM).
-* Sec. 3, PSF block: PSF at the chosen wavelength, Strehl ratio.
+* Sec. 3, PSF block: PSF at the chosen wavelength(s) weighted by the object's
+  colour, Strehl ratio and encircled energy.
+* Sec. 4, open-loop generation: screens piled up per direction, the cone
+  effect of finite-altitude sources and the LGS uplink tip-tilt.
 * Sec. 2: the 800x800 pupil at 4.875e-2 m/px and the ~5000/1400/1800 DM modes.
 
 The paper prints no equations, so each formula is a reading; the readings
@@ -22,7 +25,7 @@ are listed in ``READINGS`` and in the design notes.  Parts with no anchor
 outside this package (the physical realism of the LGS spot) are "parity
 unpinned": only self-consistency with the readings is checked.
 """
-from . import geometry, philox, wfs, psf, dm, calib, loop  # noqa: F401
+from . import geometry, philox, wfs, psf, dm, calib, loop, openloop  # noqa: F401
 
 READINGS = {
     "O1": "binary pupil, pixel-centre test, linear obstruction ratio",
@@ -38,4 +41,6 @@ READINGS = {
     "O12": "Gaussian influence functions, integer-pixel DM and screen shifts",
     "O13": "sodium sub-layers: point-source wavefront of each beam height against the focus height",
     "O14": "closed loop: actuator modes, coefs += gain * CM s, push-pull columns (s+ - s-) / 2a",
+    "O15": "cone effect: layer sampled at (1 - h/H) r + h theta, bilinear; uplink tilt = LS tilt over the launch beam",
+    "O16": "polychromatic PSF: PSFs resampled bilinearly to the reference wavelength's grid and weighted; EE in pixels",
 }

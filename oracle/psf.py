@@ -53,3 +53,52 @@ def strehl_direct(cfg, opd_m):
     e = A * np.exp(2j * np.pi * np.asarray(opd_m, dtype=np.float64) / cfg.wavelength_m)
     s = e.sum()
     return (s.real ** 2 + s.imag ** 2) / (A.sum() ** 2)
+
+
+def encircled_energy(P, radii_px):
+    """Fraction of sum P inside each radius (pixels) around the on-axis pixel (M/2, M/2) (Sec. 3 PSF
+    block): pixels (v, u) with (u - M/2)^2 + (v - M/2)^2 <= r^2."""
+    P = np.asarray(P, dtype=np.float64)
+    M = P.shape[-1]
+    c = M // 2
+    d = np.arange(M, dtype=np.float64) - c
+    d2 = d[None, :] ** 2 + d[:, None] ** 2
+    tot = P.sum()
+    return np.array([P[d2 <= float(r) ** 2].sum() / tot for r in radii_px])
+
+
+def resample(P, scale):
+    """PSF P put on the angular grid of another wavelength: Q[v, u] = P sampled bilinearly at
+    (M/2 + (v - M/2) scale, M/2 + (u - M/2) scale), 0 where that point leaves the grid
+    (reading O16; scale = lambda_ref / lambda of P)."""
+    P = np.asarray(P, dtype=np.float64)
+    M = P.shape[-1]
+    c = M // 2
+    g = c + (np.arange(M, dtype=np.float64) - c) * scale
+    X, Y = np.meshgrid(g, g)
+    ok = (X >= 0) & (Y >= 0) & (X <= M - 1) & (Y <= M - 1)
+    ix = np.minimum(np.floor(np.where(ok, X, 0)).astype(np.int64), M - 2)
+    iy = np.minimum(np.floor(np.where(ok, Y, 0)).astype(np.int64), M - 2)
+    fx = np.where(ok, X, 0) - ix
+    fy = np.where(ok, Y, 0) - iy
+    Q = ((1 - fy) * ((1 - fx) * P[iy, ix] + fx * P[iy, ix + 1])
+         + fy * ((1 - fx) * P[iy + 1, ix] + fx * P[iy + 1, ix + 1]))
+    return np.where(ok, Q, 0.0)
+
+
+def polychromatic(cfgs, weights, opd_frames):
+    """Colour-weighted PSF on the grid of cfgs[0]'s wavelength: sum_i w_i resample(sum_f P_i,f)."""
+    out = None
+    for cfg, w in zip(cfgs, weights):
+        acc, _ = psf_accumulate(cfg, opd_frames)
+        q = w * resample(acc, cfgs[0].wavelength_m / cfg.wavelength_m)
+        out = q if out is None else out + q
+    return out
+
+
+def airy_encircled_energy(r_px, pupil_n, fft_m):
+    """Encircled energy of the PSF of an unobstructed circular pupil of pupil_n samples on an M grid:
+    1 - J0(x)^2 - J1(x)^2, x = pi r pupil_n / M (the continuous-pupil closed form)."""
+    from scipy.special import j0, j1
+    x = np.pi * np.asarray(r_px, dtype=np.float64) * pupil_n / fft_m
+    return 1.0 - j0(x) ** 2 - j1(x) ** 2

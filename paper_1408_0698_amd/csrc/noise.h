@@ -87,15 +87,18 @@ __constant__ const RcpTable kRcp = RcpTable();
 constexpr int kInversionMaxK = 100;
 
 // Sequential search: p_0 = exp(-lam), p_k = (p_{k-1} lam) (1/k), F_k = F_{k-1} + p_k; the
-// smallest k with u <= F_k (at most kInversionMaxK).
+// smallest k with u <= F_k (at most kInversionMaxK).  The step counter is the loop counter, the
+// same in every lane still searching, so 1/k is a scalar load rather than one load per lane.
 __device__ __forceinline__ int poisson_inversion(float lam, float u) {
 #pragma clang fp contract(off)
   float p = expf(-lam);
   float F = p;
   int k = 0;
-  while (u > F && k < kInversionMaxK) {
-    ++k;
-    p = (p * lam) * kRcp.v[k];
+#pragma unroll 1
+  for (int kk = 1; kk <= kInversionMaxK; ++kk) {
+    if (!(u > F)) break;
+    k = kk;
+    p = (p * lam) * kRcp.v[kk];
     F = F + p;
   }
   return k;

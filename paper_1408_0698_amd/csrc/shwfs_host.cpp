@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "geom_internal.h"
 #include "internal.h"
 #include "psf_internal.h"
 #include "dm_internal.h"
@@ -663,6 +664,8 @@ struct shw_psf_plan {
   int32_t chunk = 0;          // frames per row/column pass pair
   float2* d_work = nullptr;   // chunk * pupil_n * fft_m complex
   size_t bytes = 0;
+  double* d_ee_ws = nullptr;  // encircled-energy row-group sums
+  size_t ee_bytes = 0;
 };
 
 extern "C" int shw_psf_plan_destroy(shw_psf_plan* p) {
@@ -671,6 +674,7 @@ extern "C" int shw_psf_plan_destroy(shw_psf_plan* p) {
   (void)hipGetDevice(&cur);
   if (cur != p->device) (void)hipSetDevice(p->device);
   if (p->d_work) (void)hipFree(p->d_work);
+  if (p->d_ee_ws) (void)hipFree(p->d_ee_ws);
   if (cur != p->device) (void)hipSetDevice(cur);
   delete p;
   return ok();
@@ -1211,5 +1215,188 @@ extern "C" int shw_recon_plan_destroy(shw_recon_plan* p) {
   if (p->d_partial) (void)hipFree(p->d_partial);
   if (cur != p->device) (void)hipSetDevice(cur);
   delete p;
+  return ok();
+}
+
+// ---------------------------------------------------------------- open-loop geometry, PSF extras
+
+static int fill_layers(LayerSet& S, int32_t n_layers, const float* const* d_screen, const int32_t* rows,
+                       const int32_t* cols, const int64_t* pitch, const double* params) {
+  if (n_layers < 1 || n_layers > kMaxLayers) return fail(SHW_E_INVALID, "n_layers %d outside [1, %d]", n_layers, kMaxLayers);
+  if (!d_screen || !rows || !cols || !pitch || !params) return fail(SHW_E_INVALID, "NULL layer argument");
+  S = LayerSet{};
+  S.n_layers = n_layers;
+  for (int l = 0; l < n_layers; ++l) {
+    const double* q = params + 4 * l;
+    if (!d_screen[l]) return fail(SHW_E_INVALID, "layer %d screen is NULL", l);
+    if (rows[l] < 2 || cols[l] < 2 || pitch[l] < cols[l]) return fail(SHW_E_INVALID, "layer %d: bad screen size", l);
+    if (!(is_fin(q[0]) && q[0] > 0) || !(is_fin(q[1]) && q[1] >= 0) || !is_fin(q[2]) || !is_fin(q[3]))
+      return fail(SHW_E_INVALID, "layer %d: pitch must be > 0, altitude >= 0, origin finite", l);
+    LayerDesc& L = S.layer[l];
+    L.screen = d_screen[l];
+    L.rows = rows[l];
+    L.cols = cols[l];
+    L.pitch = pitch[l];
+    L.pitch_m = q[0];
+    L.alt_m = q[1];
+    L.x0 = q[2];
+    L.y0 = q[3];
+  }
+  return SHW_OK;
+}
+
+// True if the screen coordinates of the square [xa, xb] x [ya, yb] (metres, before the layer's
+// scale 1/pitch and origin) stay inside layer L's samples.
+static bool footprint_inside(const LayerDesc& L, double xa, double xb, double ya, double yb) {
+  const double Xa = L.x0 + xa / L.pitch_m, Xb = L.x0 + xb / L.pitch_m;
+  const double Ya = L.y0 + ya / L.pitch_m, Yb = L.y0 + yb / L.pitch_m;
+  const double lo_x = Xa < Xb ? Xa : Xb, hi_x = Xa < Xb ? Xb : Xa;
+  const double lo_y = Ya < Yb ? Ya : Yb, hi_y = Ya < Yb ? Yb : Ya;
+  return lo_x >= 0.0 && lo_y >= 0.0 && hi_x <= (double)(L.cols - 1) && hi_y <= (double)(L.rows - 1);
+}
+
+extern "C" int shw_project_layers(int32_t n_layers, const float* const* d_screen, const int32_t* screen_rows,
+                                  const int32_t* screen_cols, const int64_t* screen_pitch, const double* layer_params,
+                                  int32_t pupil_n, double dx_m, int32_t n_targets, const double* target_params,
+                                  const double* d_tilt, float* d_out, int64_t out_pitch, int64_t out_stride,
+                                  void* stream) {
+  ProjectLaunch a{};
+  int e = fill_layers(a.L, n_layers, d_screen, screen_rows, screen_cols, screen_pitch, layer_params);
+  if (e != SHW_OK) return e;
+  if (pupil_n < 1 || pupil_n > 16384) return fail(SHW_E_INVALID, "pupil_n %d outside [1, 16384]", pupil_n);
+  if (!(is_fin(dx_m) && dx_m > 0)) return fail(SHW_E_INVALID, "dx_m must be > 0");
+  if (n_targets < 0) return fail(SHW_E_INVALID, "n_targets < 0");
+  if (n_targets == 0) return ok();
+  if (!target_params || !d_out) return fail(SHW_E_INVALID, "NULL argument");
+  if (out_pitch < pupil_n) return fail(SHW_E_INVALID, "out_pitch < pupil_n");
+  if (n_targets > 1 && out_stride < out_pitch * pupil_n) return fail(SHW_E_INVALID, "targets' outputs overlap");
+  const double half = (0.5 * pupil_n - 0.5) * dx_m;  // pupil pixel centres span [-half, half]
+  for (int t = 0; t < n_targets; ++t) {
+    const double* q = target_params + 3 * t;
+    if (!is_fin(q[0]) || !is_fin(q[1]) || !(is_fin(q[2]) && q[2] >= 0))
+      return fail(SHW_E_INVALID, "target %d: direction must be finite, altitude >= 0", t);
+    for (int l = 0; l < n_layers; ++l) {
+      const LayerDesc& L = a.L.layer[l];
+      if (q[2] > 0 && !(q[2] > L.alt_m)) return fail(SHW_E_INVALID, "target %d is not above layer %d", t, l);
+      const double s = q[2] > 0 ? 1.0 - L.alt_m / q[2] : 1.0;
+      const double cx = L.alt_m * q[0], cy = L.alt_m * q[1];
+      if (!footprint_inside(L, cx - s * half, cx + s * half, cy - s * half, cy + s * half))
+        return fail(SHW_E_INVALID, "target %d: footprint leaves layer %d", t, l);
+    }
+  }
+  a.pupil_n = pupil_n;
+  a.dx = dx_m;
+  a.out_pitch = out_pitch;
+  a.out_stride = out_stride;
+  hipStream_t st = (hipStream_t)stream;
+  for (int t0 = 0; t0 < n_targets; t0 += kProjectChunk) {
+    const int nt = n_targets - t0 < kProjectChunk ? n_targets - t0 : kProjectChunk;
+    a.n_t = nt;
+    for (int k = 0; k < nt; ++k) {
+      const double* q = target_params + 3 * (t0 + k);
+      a.theta[k][0] = q[0];
+      a.theta[k][1] = q[1];
+      a.inv_h[k] = q[2] > 0 ? 1.0 / q[2] : 0.0;
+    }
+    a.tilt = d_tilt ? d_tilt + 2 * t0 : nullptr;
+    a.out = d_out + t0 * out_stride;
+    hipError_t he = launch_project_layers(a, st);
+    if (he != hipSuccess) return hip_fail(he, "project layers");
+  }
+  return ok();
+}
+
+extern "C" int shw_uplink_tilt(int32_t n_layers, const float* const* d_screen, const int32_t* screen_rows,
+                               const int32_t* screen_cols, const int64_t* screen_pitch, const double* layer_params,
+                               int32_t n_lgs, const double* lgs_params, double llt_diameter_m, int32_t n_samples,
+                               double* d_tilt, void* stream) {
+  UplinkLaunch a{};
+  int e = fill_layers(a.L, n_layers, d_screen, screen_rows, screen_cols, screen_pitch, layer_params);
+  if (e != SHW_OK) return e;
+  if (n_lgs < 0) return fail(SHW_E_INVALID, "n_lgs < 0");
+  if (n_lgs == 0) return ok();
+  if (!lgs_params || !d_tilt) return fail(SHW_E_INVALID, "NULL argument");
+  if (!(is_fin(llt_diameter_m) && llt_diameter_m > 0)) return fail(SHW_E_INVALID, "llt_diameter_m must be > 0");
+  if (n_samples < 2 || n_samples > 256) return fail(SHW_E_INVALID, "n_samples %d outside [2, 256]", n_samples);
+  const double half = 0.5 * llt_diameter_m;
+  for (int k = 0; k < n_lgs; ++k) {
+    const double* q = lgs_params + 5 * k;
+    for (int j = 0; j < 4; ++j)
+      if (!is_fin(q[j])) return fail(SHW_E_INVALID, "LGS %d: launcher and direction must be finite", k);
+    if (!(is_fin(q[4]) && q[4] > 0)) return fail(SHW_E_INVALID, "LGS %d: sodium altitude must be > 0", k);
+    for (int l = 0; l < n_layers; ++l) {
+      const LayerDesc& L = a.L.layer[l];
+      if (!(q[4] > L.alt_m)) return fail(SHW_E_INVALID, "LGS %d is not above layer %d", k, l);
+      const double f = L.alt_m / q[4];
+      const double cx = q[0] * (1.0 - f) + L.alt_m * q[2], cy = q[1] * (1.0 - f) + L.alt_m * q[3];
+      if (!footprint_inside(L, cx - half, cx + half, cy - half, cy + half))
+        return fail(SHW_E_INVALID, "LGS %d: beam leaves layer %d", k, l);
+    }
+  }
+  a.n_s = n_samples;
+  a.d = llt_diameter_m;
+  hipStream_t st = (hipStream_t)stream;
+  for (int k0 = 0; k0 < n_lgs; k0 += kProjectChunk) {
+    const int nk = n_lgs - k0 < kProjectChunk ? n_lgs - k0 : kProjectChunk;
+    a.n = nk;
+    for (int k = 0; k < nk; ++k)
+      for (int j = 0; j < 5; ++j) a.lgs[k][j] = lgs_params[5 * (k0 + k) + j];
+    a.tilt = d_tilt + 2 * k0;
+    hipError_t he = launch_uplink_tilt(a, st);
+    if (he != hipSuccess) return hip_fail(he, "uplink tilt");
+  }
+  return ok();
+}
+
+extern "C" int psf_encircled_energy(shw_psf_plan* plan, const float* d_psf, int32_t n_psf, int64_t psf_stride,
+                                    int32_t n_r, const double* r_px, double* d_ee, void* stream) {
+  if (!plan) return fail(SHW_E_INVALID, "plan is NULL");
+  const int M = plan->fft_m;
+  if (M > 4096) return fail(SHW_E_UNSUPPORTED, "encircled energy supports fft_m <= 4096");
+  if (n_psf < 0) return fail(SHW_E_INVALID, "n_psf < 0");
+  if (n_psf == 0) return ok();
+  if (!d_psf || !r_px || !d_ee) return fail(SHW_E_INVALID, "NULL argument");
+  if (n_psf > 1 && psf_stride < (int64_t)M * M) return fail(SHW_E_INVALID, "psf_stride < fft_m^2");
+  if (n_r < 1 || n_r > kMaxRadii) return fail(SHW_E_INVALID, "n_r %d outside [1, %d]", n_r, kMaxRadii);
+  EeLaunch a{};
+  for (int k = 0; k < n_r; ++k) {
+    if (!(is_fin(r_px[k]) && r_px[k] >= 0)) return fail(SHW_E_INVALID, "radius %d must be finite and >= 0", k);
+    a.r2[k] = r_px[k] * r_px[k];
+  }
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != plan->device) return fail(SHW_E_INVALID, "the current device is not the plan's device");
+  const size_t need = (size_t)n_psf * kEeGroups * (n_r + 1) * sizeof(double);
+  if (need > plan->ee_bytes) {
+    hipError_t he = hipDeviceSynchronize();
+    if (he != hipSuccess) return hip_fail(he, "synchronise before growing the workspace");
+    if (plan->d_ee_ws) (void)hipFree(plan->d_ee_ws);
+    plan->d_ee_ws = nullptr;
+    plan->ee_bytes = 0;
+    he = hipMalloc((void**)&plan->d_ee_ws, need);
+    if (he != hipSuccess) return fail(SHW_E_NOMEM, "encircled-energy workspace of %zu bytes", need);
+    plan->ee_bytes = need;
+  }
+  a.psf = d_psf;
+  a.psf_stride = psf_stride;
+  a.m = M;
+  a.n_psf = n_psf;
+  a.n_r = n_r;
+  a.ws = plan->d_ee_ws;
+  a.ee = d_ee;
+  hipError_t he = launch_encircled_energy(a, (hipStream_t)stream);
+  if (he != hipSuccess) return hip_fail(he, "encircled energy");
+  return ok();
+}
+
+extern "C" int psf_resample_accumulate(int32_t fft_m, const float* d_src, double scale, float weight, float* d_dst,
+                                       void* stream) {
+  if (fft_m < 2 || fft_m > 16384) return fail(SHW_E_INVALID, "fft_m %d outside [2, 16384]", fft_m);
+  if (!d_src || !d_dst) return fail(SHW_E_INVALID, "NULL argument");
+  if (!(is_fin(scale) && scale > 0) || !std::isfinite(weight)) return fail(SHW_E_INVALID, "scale must be > 0, weight finite");
+  const int64_t n = (int64_t)fft_m * fft_m;
+  if (d_src < d_dst + n && d_dst < d_src + n) return fail(SHW_E_INVALID, "source and destination overlap");
+  hipError_t he = launch_psf_resample(d_src, fft_m, scale, weight, d_dst, (hipStream_t)stream);
+  if (he != hipSuccess) return hip_fail(he, "psf resample");
   return ok();
 }

@@ -97,6 +97,14 @@ _sig = {
     "shw_residual_opd": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.POINTER(C.c_void_p),
                                    C.POINTER(C.c_int32), C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32), _P, C.c_int64, C.c_int64, _P]),
+    "shw_project_layers": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int64), C.POINTER(C.c_double), C.c_int32, C.c_double, C.c_int32,
+                                     C.POINTER(C.c_double), _P, _P, C.c_int64, C.c_int64, _P]),
+    "shw_uplink_tilt": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_int64), C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
+                                  C.c_double, C.c_int32, _P, _P]),
+    "psf_encircled_energy": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_int32, C.POINTER(C.c_double), _P, _P]),
+    "psf_resample_accumulate": (C.c_int, [C.c_int32, _P, C.c_double, C.c_float, _P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -287,6 +295,7 @@ class PsfPlan:
         self._h = h
         self.fft_m = fft_m
         self.pupil_n = pupil_n
+        self.wavelength_m = wavelength_m
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:   # the module may be torn down first
@@ -312,6 +321,85 @@ class PsfPlan:
                                          opd.shape[0], _ptr(acc), acc.stride(0), _ptr(strehl), _stream_ptr(stream)),
                "psf_accumulate_stars")
         return acc
+
+
+    def encircled_energy(self, psf, radii_px, out=None, stream=None):
+        """psf: float32 device [M][M] or [S][M][M]; radii in pixels -> float64 device [S][n_r] (or [n_r])."""
+        import torch
+        single = psf.dim() == 2
+        p3 = psf.unsqueeze(0) if single else psf
+        if p3.dim() != 3 or p3.shape[1:] != (self.fft_m, self.fft_m) or p3.stride(2) != 1 or p3.stride(1) != self.fft_m:
+            raise ValueError("psf must be [S][M][M] with contiguous rows of the plan's size")
+        r = (C.c_double * len(radii_px))(*[float(v) for v in radii_px])
+        if out is None:
+            out = torch.empty((p3.shape[0], len(radii_px)), dtype=torch.float64, device=psf.device)
+        _check(_lib.psf_encircled_energy(self._h, _ptr(p3), p3.shape[0], p3.stride(0), len(radii_px), r, _ptr(out),
+                                         _stream_ptr(stream)), "psf_encircled_energy")
+        return out[0] if single else out
+
+
+def psf_resample_accumulate(src, scale, weight, dst, stream=None):
+    """dst[M][M] += weight * src (a PSF at wavelength lambda_i) on the grid of lambda_ref, scale = lambda_ref / lambda_i."""
+    m = src.shape[-1]
+    if src.shape != (m, m) or dst.shape != (m, m) or not src.is_contiguous() or not dst.is_contiguous():
+        raise ValueError("src and dst must be contiguous [M][M]")
+    _check(_lib.psf_resample_accumulate(m, _ptr(src), float(scale), float(weight), _ptr(dst), _stream_ptr(stream)),
+           "psf_resample_accumulate")
+    return dst
+
+
+def polychromatic_psf(plans, weights, opd, out, strehl=None, stream=None):
+    """Colour-weighted PSF on the angular grid of plans[0]'s wavelength (Sec. 3 PSF block).
+
+    plans: PsfPlan per wavelength (same pupil and M); weights: the object's colour, one per plan;
+    opd: float32 device [F][N][N]; out [M][M] += sum_i w_i sum_f P_i,f resampled to plans[0]'s grid.
+    strehl: optional float32 device [len(plans)][F] of per-wavelength Strehl ratios.  Device work
+    runs in the library (accumulation per wavelength, then psf_resample_accumulate).
+    """
+    import torch
+    m = plans[0].fft_m
+    tmp = torch.empty((m, m), dtype=torch.float32, device=out.device)
+    for i, (p, w) in enumerate(zip(plans, weights)):
+        if p.fft_m != m:
+            raise ValueError("all plans must have the same M")
+        tmp.zero_()
+        p.accumulate(opd, tmp, None if strehl is None else strehl[i], stream=stream)
+        psf_resample_accumulate(tmp, plans[0].wavelength_m / p.wavelength_m, w, out, stream=stream)
+    return out
+
+
+def _layer_args(layers):
+    """layers: sequence of (screen float32 device [R][C] with unit column stride, spacing_m, altitude_m, x0, y0)."""
+    n = len(layers)
+    ptrs = (C.c_void_p * n)(*[_ptr(l[0]) for l in layers])
+    rows = (C.c_int32 * n)(*[l[0].shape[0] for l in layers])
+    cols = (C.c_int32 * n)(*[l[0].shape[1] for l in layers])
+    pitch = (C.c_int64 * n)(*[l[0].stride(0) for l in layers])
+    for l in layers:
+        if l[0].dim() != 2 or l[0].stride(1) != 1:
+            raise ValueError("screens must be [rows][cols] with unit column stride")
+    par = (C.c_double * (4 * n))(*[float(v) for l in layers for v in l[1:5]])
+    return n, ptrs, rows, cols, pitch, par
+
+
+def project_layers(layers, pupil_n, dx_m, targets, out, tilt=None, stream=None):
+    """Cone-effect open-loop wavefronts: targets = [(theta_x, theta_y, altitude_m or 0)], out float32 [T][N][N]."""
+    n, ptrs, rows, cols, pitch, par = _layer_args(layers)
+    tp = (C.c_double * (3 * max(1, len(targets))))(*[float(v) for t in targets for v in t])
+    if out.dim() != 3 or out.stride(2) != 1:
+        raise ValueError("out must be [targets][rows][cols] with contiguous rows")
+    _check(_lib.shw_project_layers(n, ptrs, rows, cols, pitch, par, pupil_n, dx_m, len(targets), tp, _ptr(tilt),
+                                   _ptr(out), out.stride(1), out.stride(0), _stream_ptr(stream)), "shw_project_layers")
+    return out
+
+
+def uplink_tilt(layers, lgs, llt_diameter_m, n_samples, out, stream=None):
+    """lgs = [(launch_x_m, launch_y_m, theta_x, theta_y, sodium_altitude_m)]; out float64 device [n][2] radians."""
+    n, ptrs, rows, cols, pitch, par = _layer_args(layers)
+    lp = (C.c_double * (5 * max(1, len(lgs))))(*[float(v) for g in lgs for v in g])
+    _check(_lib.shw_uplink_tilt(n, ptrs, rows, cols, pitch, par, len(lgs), lp, llt_diameter_m, n_samples, _ptr(out),
+                                _stream_ptr(stream)), "shw_uplink_tilt")
+    return out
 
 
 def dm_geometry(pupil_n, pupil_dx_m, alt_m, pitch_px, field_radius_arcsec):

@@ -171,3 +171,42 @@ def test_sodium_plan_argument_checks():
     r2 = s.make_config(G.CFG1_R2)
     assert s._lib.shw_wfs_plan_create_sodium(C.byref(r2), 1, geom, 3, dh, wt, C.byref(h)) == s.E_UNSUPPORTED
     assert s._lib.sh_wfs_measure_sodium(None, None, 800, 0, 0, 0, 1, 0, 0, None, None, None, None) == s.E_INVALID
+
+
+def test_geometry_and_psf_extras_argument_checks():
+    """Layer projection, uplink tilt, encircled energy and resampling validate on the host."""
+    s = _lib()
+    fake = C.c_void_p(0x1000)
+    ptrs = (C.c_void_p * 2)(0x1000, 0x2000)
+    rows = (C.c_int32 * 2)(400, 400)
+    cols = (C.c_int32 * 2)(400, 400)
+    pitch = (C.c_int64 * 2)(400, 400)
+    # (spacing, altitude, x0, y0): a ground layer and one at 8 km, axis at the screen centre
+    par = (C.c_double * 8)(0.1, 0.0, 200.0, 200.0, 0.1, 8000.0, 200.0, 200.0)
+    tgt = (C.c_double * 3)(0.0, 0.0, 90000.0)
+    args = (2, ptrs, rows, cols, pitch, par)
+    # a 20 m pupil (200 samples of 0.1 m) fits; 50 m leaves the 40 m screens
+    ok_call = s._lib.shw_project_layers(*args, 200, 0.1, 0, tgt, None, fake, 200, 40000, None)
+    assert ok_call == s.OK   # no targets: nothing to do
+    assert s._lib.shw_project_layers(*args, 500, 0.1, 1, tgt, None, fake, 500, 250000, None) == s.E_INVALID
+    low = (C.c_double * 3)(0.0, 0.0, 5000.0)   # source below the 8 km layer
+    assert s._lib.shw_project_layers(*args, 200, 0.1, 1, low, None, fake, 200, 40000, None) == s.E_INVALID
+    tilted = (C.c_double * 3)(2e-3, 0.0, 0.0)  # 8 km x 2 mrad = 16 m: the footprint leaves the screen
+    assert s._lib.shw_project_layers(*args, 200, 0.1, 1, tilted, None, fake, 200, 40000, None) == s.E_INVALID
+    assert s._lib.shw_project_layers(*args, 200, 0.1, 2, (C.c_double * 6)(*[0.0] * 6), None, fake, 200, 100,
+                                     None) == s.E_INVALID   # outputs overlap
+    bad = (C.c_double * 8)(0.0, 0.0, 200.0, 200.0, 0.1, 8000.0, 200.0, 200.0)
+    assert s._lib.shw_project_layers(2, ptrs, rows, cols, pitch, bad, 200, 0.1, 1, tgt, None, fake, 200, 40000,
+                                     None) == s.E_INVALID
+    assert s._lib.shw_project_layers(17, ptrs, rows, cols, pitch, par, 200, 0.1, 1, tgt, None, fake, 200, 40000,
+                                     None) == s.E_INVALID
+    lgs = (C.c_double * 5)(19.0, 0.0, 0.0, 0.0, 90000.0)
+    far = (C.c_double * 5)(25.0, 0.0, 0.0, 0.0, 90000.0)  # launcher 25 m off axis: beam leaves the 20 m half-width
+    assert s._lib.shw_uplink_tilt(*args, 1, far, 0.4, 32, fake, None) == s.E_INVALID
+    assert s._lib.shw_uplink_tilt(*args, 1, lgs, 0.0, 32, fake, None) == s.E_INVALID
+    assert s._lib.shw_uplink_tilt(*args, 1, lgs, 0.4, 1, fake, None) == s.E_INVALID
+    assert s._lib.shw_uplink_tilt(*args, 0, lgs, 0.4, 32, None, None) == s.OK
+    assert s._lib.psf_encircled_energy(None, fake, 1, 0, 1, (C.c_double * 1)(3.0), fake, None) == s.E_INVALID
+    assert s._lib.psf_resample_accumulate(1, fake, 1.0, C.c_float(1.0), C.c_void_p(0x9000), None) == s.E_INVALID
+    assert s._lib.psf_resample_accumulate(64, fake, 0.0, C.c_float(1.0), C.c_void_p(0x90000), None) == s.E_INVALID
+    assert s._lib.psf_resample_accumulate(64, fake, 1.0, C.c_float(1.0), C.c_void_p(0x1100), None) == s.E_INVALID

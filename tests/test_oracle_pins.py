@@ -560,3 +560,110 @@ def test_sodium_elongation_axis_points_from_launcher():
         diff = (axis - psi + math.pi / 2) % math.pi - math.pi / 2
         assert abs(diff) < math.radians(3.0), (i, math.degrees(axis), math.degrees(psi))
         assert cxx + cyy > 0
+
+
+# ---------------------------------------------------------------- O15 cone effect and uplink tilt
+
+from oracle import openloop as OL  # noqa: E402
+
+
+def _plane(rows, cols, a, b, c):
+    X, Y = np.meshgrid(np.arange(cols, dtype=np.float64), np.arange(rows, dtype=np.float64))
+    return a + b * X + c * Y
+
+
+def test_projection_of_a_plane_is_the_plane_at_the_cone_footprint():
+    # bilinear interpolation reproduces a plane exactly, so the projection is a closed form
+    N, dx = 24, 0.5
+    layers = [(_plane(200, 220, 1e-7, 2e-9, -3e-9), 0.25, 0.0, 110.3, 99.7),
+              (_plane(300, 300, -2e-7, 5e-9, 1e-9), 0.5, 8000.0, 150.0, 149.5)]
+    theta, H = (3e-5, -2e-5), 90000.0
+    got = OL.project(layers, N, dx, theta, H)
+    x, y = OL.pupil_coords(N, dx)
+    want = np.zeros_like(x)
+    for S, p, h, x0, y0 in layers:
+        s = 1 - h / H
+        X = x0 + (s * x + h * theta[0]) / p
+        Y = y0 + (s * y + h * theta[1]) / p
+        a, b, c = S[0, 0], S[0, 1] - S[0, 0], S[1, 0] - S[0, 0]
+        want += a + b * X + c * Y
+    assert np.abs(got - want).max() < 1e-18
+
+
+def test_projection_ground_layer_integer_origin_is_a_window():
+    # h = 0 and pupil pixel centres on integer screen samples: the OPD is a plain window
+    rng = np.random.default_rng(4)
+    S = rng.normal(size=(64, 64))
+    N, dx = 16, 1.0
+    got = OL.project([(S, 1.0, 0.0, 20.5 + N / 2 - 0.5 + 0.5, 10.0 + N / 2)], N, dx, (0.0, 0.0), 0.0)
+    # pixel j centre x = j + 1/2 - N/2 -> X = 20.5 + N/2 + (j + 1/2 - N/2) = 21 + j; Y = 10 + N/2 + y = 10.5 + i
+    X0, Y0 = 21.0, 10.5
+    assert X0 == int(X0)
+    want_rows = 0.5 * (S[10:10 + N, 21:21 + N] + S[11:11 + N, 21:21 + N])
+    assert np.allclose(got, want_rows, rtol=0, atol=1e-15)
+
+
+def test_cone_shrinks_the_footprint_by_one_minus_h_over_H():
+    # a plane of slope b per metre on a layer at h seen by a source at H = 2h has slope b / 2
+    N, dx, h = 20, 0.5, 5000.0
+    layer = (_plane(100, 100, 0.0, 1e-8, 0.0), 0.5, h, 50.0, 50.0)
+    near = OL.project([layer], N, dx, (0.0, 0.0), 2 * h)
+    far = OL.project([layer], N, dx, (0.0, 0.0), 0.0)
+    assert np.allclose(np.diff(near, axis=1), 0.5 * np.diff(far, axis=1), rtol=1e-12, atol=0)
+
+
+def test_uplink_tilt_of_planes_and_quadratics():
+    # least squares over a symmetric sample set: a plane gives its slope, a quadratic the slope at the centre
+    pitch = 0.1
+    lay = [(_plane(400, 400, 3e-7, 4e-9, -1e-9), pitch, 0.0, 200.0, 200.0),
+           (_plane(400, 400, 0.0, -2e-9, 6e-9), pitch, 6000.0, 200.0, 200.0)]
+    tx, ty = OL.uplink_tilt(lay, (10.0, -5.0), (2e-5, 1e-5), 90000.0, 0.4, 32)
+    assert abs(tx - (4e-9 - 2e-9) / pitch) < 1e-18 and abs(ty - (-1e-9 + 6e-9) / pitch) < 1e-18
+    X, Y = np.meshgrid(np.arange(400.0), np.arange(400.0))
+    q = 1e-9 * ((X - 180.0) ** 2 + 0.5 * (Y - 230.0) ** 2)   # gradient (2 (X - 180), (Y - 230)) e-9 per sample
+    lx, ly = 3.0, -2.0                                         # beam centre at (200 + 30, 200 - 20) samples, h = 0
+    tx, ty = OL.uplink_tilt([(q, pitch, 0.0, 200.0, 200.0)], (lx, ly), (0.0, 0.0), 90000.0, 0.4, 40)
+    # bilinear interpolation of a quadratic adds a periodic error; its LS slope over the beam is small
+    assert abs(tx - 2e-9 * (230.0 - 180.0) / pitch) < 2e-3 * abs(2e-9 * 50 / pitch)
+    assert abs(ty - 1e-9 * (180.0 - 230.0) / pitch) < 2e-3 * abs(1e-9 * 50 / pitch)
+
+
+# ---------------------------------------------------------------- O16 encircled energy, polychromatic PSF
+
+from oracle import psf as OPSF  # noqa: E402
+from gen.configs import PsfConfig  # noqa: E402
+
+
+def test_encircled_energy_matches_the_airy_closed_form():
+    cfg = PsfConfig(pupil_n=64, pupil_dx_m=0.1, obstruction=0.0, fft_m=512, wavelength_m=1e-6)
+    acc, _ = OPSF.psf_accumulate(cfg, [np.zeros((64, 64))])
+    r = np.array([4.0, 8.0, 12.0, 20.0, 40.0])   # lambda/D is 8 px
+    ee = OPSF.encircled_energy(acc, r)
+    want = OPSF.airy_encircled_energy(r, 64, 512)
+    # pixelated pupil, pixelated radii and the periodic M grid: agreement to ~1 %
+    assert np.abs(ee - want).max() < 0.015
+    assert np.all(np.diff(ee) > 0)
+    assert OPSF.encircled_energy(acc, [1e9])[0] == 1.0
+    assert OPSF.encircled_energy(acc, [0.0])[0] == acc[256, 256] / acc.sum()
+
+
+def test_resample_identity_and_scaled_gaussian():
+    rng = np.random.default_rng(8)
+    P = rng.random((32, 32))
+    assert np.array_equal(OPSF.resample(P, 1.0), P)
+    # a wide Gaussian: resampling by s reads it at s times the distance from the centre
+    M, c = 128, 64
+    d = np.arange(M, dtype=np.float64) - c
+    G = np.exp(-(d[None, :] ** 2 + d[:, None] ** 2) / (2 * 15.0 ** 2))
+    Q = OPSF.resample(G, 0.8)
+    want = np.exp(-((0.8 * d[None, :]) ** 2 + (0.8 * d[:, None]) ** 2) / (2 * 15.0 ** 2))
+    assert np.abs(Q - want).max() < 2e-3
+
+
+def test_polychromatic_strehl_of_a_flat_wavefront_is_the_weight_sum():
+    base = PsfConfig(pupil_n=32, pupil_dx_m=0.1, obstruction=0.14, fft_m=128, wavelength_m=1.65e-6)
+    cfgs = [base, base.__class__(**{**base.__dict__, "wavelength_m": 1.5e-6}),
+            base.__class__(**{**base.__dict__, "wavelength_m": 1.8e-6})]
+    w = [0.5, 0.2, 0.3]
+    P = OPSF.polychromatic(cfgs, w, [np.zeros((32, 32))])
+    assert abs(P[64, 64] - sum(w)) < 1e-12
