@@ -266,7 +266,97 @@ def ex_psf(stream):
     return out
 
 
-EXTRAS = ("ngs8m", "precision", "sodium", "ngs512", "psf", "calibration", "loop", "served")
+def ex_openloop(stream):
+    """LGS wavefronts from the atmosphere: 6 LGS x 3 sodium sub-layers projected through three 2048^2
+    layers with the cone effect, plus each laser's uplink tilt, then the sodium-layer measurement."""
+    import numpy as np
+    import torch
+
+    from gen import configs as G
+    from gen import screens as S
+    from paper_1408_0698_amd import shwfs
+    cfg = G.CFG1
+    out = {}
+    layers = [(torch.from_numpy(S.screen_opd_m(2048, cfg.pupil_dx_m, G.SCREEN_SEED + k).astype(np.float32)).cuda(),
+               cfg.pupil_dx_m, h, 1023.5, 1023.5) for k, h in enumerate((0.0, 4000.0, 12700.0))]
+    launch = G.launch_positions(cfg, 6)
+    ang = np.arange(6) * np.pi / 3
+    dirs = [(45.0 * G.ARCSEC * np.cos(a), 45.0 * G.ARCSEC * np.sin(a)) for a in ang]
+    lgs = [(lx, ly, tx, ty, cfg.na_height_m) for (lx, ly), (tx, ty) in zip(launch, dirs)]
+    targets = [(tx, ty, cfg.na_height_m + dh) for tx, ty in dirs for dh in G.SODIUM[0]]
+    tilt = torch.zeros((6, 2), dtype=torch.float64, device="cuda")
+    tilt18 = torch.zeros((18, 2), dtype=torch.float64, device="cuda")
+    opd = torch.zeros((1, 6, 3, cfg.pupil_n, cfg.pupil_n), device="cuda")
+    plan = shwfs.WfsPlan(cfg, 6, launch, sodium=G.SODIUM)
+    sl = torch.zeros((1, 6, 2, plan.n_valid), device="cuda")
+
+    def project(k):
+        shwfs.project_layers(layers, cfg.pupil_n, cfg.pupil_dx_m, targets, opd.view(18, cfg.pupil_n, cfg.pupil_n),
+                             tilt=tilt18, stream=stream)
+
+    def uplink(k):
+        shwfs.uplink_tilt(layers, lgs, 0.4, 64, tilt, stream=stream)
+        tilt18.copy_(tilt.repeat_interleave(3, dim=0))
+
+    def frame(k):
+        uplink(k)
+        project(k)
+        plan.measure_sodium(opd, sl, seed=1, frame0=k, stream=stream)
+
+    with torch.cuda.stream(stream):
+        frame(0)
+        ms_proj = _time(project, 10, stream)
+        ms_up = _time(uplink, 10, stream)
+        ms_frame = _time(frame, 10, stream)
+    out["openloop_project_18x800x800_ms"] = ms_proj
+    # gathered bytes per output sample: 3 layers x 4 taps (mostly L2 hits); written 4 B
+    out["openloop_project_Gsamples_per_s"] = 18 * cfg.pupil_n ** 2 / (ms_proj * 1e-3) / 1e9
+    out["openloop_uplink_6lgs_ms"] = ms_up
+    out["openloop_lgs_frame_ms"] = ms_frame
+    out["openloop_uplink_tilt_mas_lgs0"] = [float(v) / G.ARCSEC * 1e3 for v in tilt[0].cpu()]
+    return out
+
+
+def ex_psf_extras(stream):
+    """Encircled energy of 9 integrated 1600^2 PSFs at 20 radii, and a 3-wavelength colour-weighted PSF
+    of 20 frames of one star."""
+    import numpy as np
+    import torch
+
+    from gen import configs as G
+    from gen import screens as S
+    from paper_1408_0698_amd import shwfs
+    out = {}
+    cfg = G.CFG3
+    plans = [shwfs.PsfPlan(cfg.pupil_n, cfg.pupil_dx_m, cfg.obstruction, cfg.fft_m, l)
+             for l in (1.65e-6, 1.5e-6, 1.8e-6)]
+    scr = S.screen_opd_m(2048, cfg.pupil_dx_m)
+    opd = torch.from_numpy(np.stack([scr[:800, t:t + 800] * 0.1 for t in range(G.CFG3_FRAMES)])
+                           .astype(np.float32)).cuda()
+    poly = torch.zeros((1600, 1600), device="cuda")
+    acc = torch.zeros((9, 1600, 1600), device="cuda")
+    with torch.cuda.stream(stream):
+        plans[0].accumulate(opd, acc[0], stream=stream)
+        for s_ in range(1, 9):
+            acc[s_].copy_(acc[0])
+        radii = [2.0 * (k + 1) for k in range(20)]
+        ms_ee = _time(lambda k: plans[0].encircled_energy(acc, radii, stream=stream), 5, stream)
+        ee = plans[0].encircled_energy(acc, radii, stream=stream)
+
+        def poly_step(k):
+            poly.zero_()
+            shwfs.polychromatic_psf(plans, (0.5, 0.2, 0.3), opd, poly, stream=stream)
+
+        ms_poly = _time(poly_step, 2, stream)
+    out["ee_9psf_20radii_ms"] = ms_ee
+    out["ee_GBps"] = 9 * 1600 * 1600 * 4 / (ms_ee * 1e-3) / 1e9
+    out["ee_r2px_r10px_r40px"] = [float(ee[0, 0]), float(ee[0, 4]), float(ee[0, 19])]
+    out["poly_psf_3lambda_20frames_ms"] = ms_poly
+    return out
+
+
+EXTRAS = ("ngs8m", "precision", "sodium", "ngs512", "psf", "calibration", "loop", "openloop", "psf_extras",
+          "served")
 EXTRAS_DEFAULT = EXTRAS
 
 
@@ -274,7 +364,7 @@ def extras(stream, which=EXTRAS):
     """Secondary workloads, each timed with HIP events on its stream."""
     import torch
     fns = {"ngs8m": ex_ngs8m, "precision": ex_precision, "sodium": ex_sodium, "ngs512": ex_ngs512, "psf": ex_psf,
-           "calibration": calibration, "loop": closed_loop}
+           "calibration": calibration, "loop": closed_loop, "openloop": ex_openloop, "psf_extras": ex_psf_extras}
     out = {}
     for name in which:
         if name == "served":

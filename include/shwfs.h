@@ -334,7 +334,7 @@ int shw_psf_plan_destroy(shw_psf_plan* plan);
  *                     divided by the sum of P over the whole array
  * (FP64 sums in a fixed order: the same inputs give the same result).  M <=
  * 4096 (SHW_E_UNSUPPORTED otherwise).  The plan keeps a workspace of n_psf *
- * 64 * (n_r + 1) doubles; growing it synchronises the device.  Asynchronous
+ * 200 * (n_r + 1) doubles; growing it synchronises the device.  Asynchronous
  * otherwise; calls on one plan must not overlap.
  */
 int psf_encircled_energy(shw_psf_plan* plan, const float* d_psf, int32_t n_psf, int64_t psf_stride, int32_t n_r,

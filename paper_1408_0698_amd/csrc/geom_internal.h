@@ -10,7 +10,7 @@ namespace shw {
 constexpr int kMaxLayers = 16;
 constexpr int kProjectChunk = 32;  // targets per projection launch (their parameters travel in the arguments)
 constexpr int kMaxRadii = 64;      // encircled-energy radii per call
-constexpr int kEeGroups = 64;      // row groups of the encircled-energy pass
+constexpr int kEeGroups = 200;     // row groups of the encircled-energy pass
 
 // One phase-screen layer: FP32 OPD metres, rows of cols samples pitch apart, sample spacing
 // pitch_m metres, altitude alt_m; the point above the telescope axis sits at screen pixel

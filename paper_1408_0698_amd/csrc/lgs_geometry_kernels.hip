@@ -26,15 +26,41 @@ __device__ __forceinline__ double layer_sample(const LayerDesc& L, double X, dou
 }
 
 // Sum over the layers of the OPD seen from pupil point (x, y) metres toward direction theta of a
-// source at inverse altitude inv_h (0: infinity).
+// source at inverse altitude inv_h (0: infinity).  Layers go four at a time: the reads of a group
+// are issued first and blended afterwards, so that they are in flight together.
 __device__ __forceinline__ double piled_opd(const LayerSet& S, double x, double y, double tx, double ty,
                                             double inv_h) {
   double acc = 0.0;
-  for (int l = 0; l < S.n_layers; ++l) {
-    const LayerDesc& L = S.layer[l];
-    const double s = 1.0 - L.alt_m * inv_h;  // footprint scale of the cone at this altitude
-    const double inv_p = 1.0 / L.pitch_m;
-    acc += layer_sample(L, L.x0 + (s * x + L.alt_m * tx) * inv_p, L.y0 + (s * y + L.alt_m * ty) * inv_p);
+  for (int l0 = 0; l0 < S.n_layers; l0 += 4) {
+    float t00[4], t01[4], t10[4], t11[4];
+    double fx[4], fy[4], use[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      // past the last layer the group re-reads the last one (in bounds) and gives it weight 0:
+      // no branch, so nothing waits for a read before the next one is issued
+      const int l = l0 + q < S.n_layers ? l0 + q : S.n_layers - 1;
+      use[q] = l0 + q < S.n_layers ? 1.0 : 0.0;
+      const LayerDesc& L = S.layer[l];
+      const double s = 1.0 - L.alt_m * inv_h;  // footprint scale of the cone at this altitude
+      const double inv_p = 1.0 / L.pitch_m;
+      const double X = L.x0 + (s * x + L.alt_m * tx) * inv_p, Y = L.y0 + (s * y + L.alt_m * ty) * inv_p;
+      int ix = (int)floor(X), iy = (int)floor(Y);
+      ix = ix < 0 ? 0 : (ix > L.cols - 2 ? L.cols - 2 : ix);
+      iy = iy < 0 ? 0 : (iy > L.rows - 2 ? L.rows - 2 : iy);
+      fx[q] = X - ix;
+      fy[q] = Y - iy;
+      const float* r0 = L.screen + (int64_t)iy * L.pitch + ix;
+      t00[q] = r0[0];
+      t01[q] = r0[1];
+      t10[q] = r0[L.pitch];
+      t11[q] = r0[L.pitch + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double top = (1.0 - fx[q]) * (double)t00[q] + fx[q] * (double)t01[q];
+      const double bot = (1.0 - fx[q]) * (double)t10[q] + fx[q] * (double)t11[q];
+      acc += use[q] * ((1.0 - fy[q]) * top + fy[q] * bot);
+    }
   }
   return acc;
 }
