@@ -176,3 +176,44 @@ def test_polychromatic_psf_parity(torch_dev):
     assert np.abs(got - want).max() <= 1e-5 * want.max()
     # the on-axis value of the colour-weighted PSF is the weighted sum of the per-wavelength Strehl ratios
     assert abs(got[800, 800] - float((torch.tensor(w, device="cuda")[:, None] * sr).sum())) < 1e-5 * got[800, 800]
+
+
+def test_lgs_frame_from_layers_parity(torch_dev):
+    """End to end: uplink tilts, cone-effect wavefronts of every sodium sub-layer, sodium measurement,
+    against the oracle's projection and sensor (noise off)."""
+    from oracle import wfs as OW
+    from paper_1408_0698_amd import shwfs
+    torch = torch_dev
+    print("LGS frame from layers", flush=True)
+    cfg = G.CFG1.replace(pupil_n=130, n_subap=13, flags=0)
+    n_wfs = 6
+    launch = G.launch_positions(cfg, n_wfs)
+    scr = [(S.screen_opd_m(512, cfg.pupil_dx_m, G.SCREEN_SEED + 20 + k)[:400, :400] * 0.5).astype(np.float32)
+           for k in range(3)]
+    params = [(cfg.pupil_dx_m, h, 199.5, 200.5) for h in (0.0, 4000.0, 12700.0)]
+    gpu, host = _layers(torch, scr, params)
+    dirs = [(45.0 * G.ARCSEC * np.cos(a), 45.0 * G.ARCSEC * np.sin(a)) for a in np.arange(n_wfs) * np.pi / 3]
+    lgs = [(lx, ly, tx, ty, cfg.na_height_m) for (lx, ly), (tx, ty) in zip(launch, dirs)]
+    dh = G.SODIUM[0]
+    targets = [(tx, ty, cfg.na_height_m + d) for tx, ty in dirs for d in dh]
+    tilt = torch.zeros((n_wfs, 2), dtype=torch.float64, device="cuda")
+    shwfs.uplink_tilt(gpu, lgs, 0.4, 32, tilt)
+    tilt_t = tilt.repeat_interleave(len(dh), dim=0).contiguous()
+    opd = torch.empty((1, n_wfs, len(dh), cfg.pupil_n, cfg.pupil_n), device="cuda")
+    shwfs.project_layers(gpu, cfg.pupil_n, cfg.pupil_dx_m, targets, opd.view(-1, cfg.pupil_n, cfg.pupil_n),
+                         tilt=tilt_t)
+    plan = shwfs.WfsPlan(cfg, n_wfs, launch, sodium=G.SODIUM)
+    sl = torch.full((1, n_wfs, 2, plan.n_valid), float("nan"), device="cuda")
+    im = torch.full((1, n_wfs, plan.n_valid, 16, 16), float("nan"), device="cuda")
+    plan.measure_sodium(opd, sl, im)
+    torch.cuda.synchronize()
+    # oracle: tilts, wavefronts and sensor from the same host layers
+    want_opd = np.empty((1, n_wfs, len(dh), cfg.pupil_n, cfg.pupil_n))
+    for w, g in enumerate(lgs):
+        t = OL.uplink_tilt(host, g[:2], g[2:4], g[4], 0.4, 32)
+        for j, d in enumerate(dh):
+            want_opd[0, w, j] = OL.project(host, cfg.pupil_n, cfg.pupil_dx_m, g[2:4], cfg.na_height_m + d, t)
+    want = OW.Sensor(cfg, n_wfs, launch, sodium=G.SODIUM).measure(want_opd)
+    from test_gpu_wfs import assert_images_close, assert_slopes_close
+    assert_images_close(im.cpu().numpy().astype(np.float64), want["images"])
+    assert_slopes_close(sl.cpu().numpy().astype(np.float64), want["slopes"])
