@@ -97,7 +97,9 @@ def poisson_inversion_f32(lam, u):
     """Sequential-search inversion: smallest k with u <= sum_{j<=k} e^-lam lam^j / j!.
 
     FP32: p0 = exp(-lam); p_k = (p_{k-1} * lam) * r_k with r_k = 1/k rounded to FP32;
-    F_k = F_{k-1} + p_k (reading O8).
+    F_k = F_{k-1} + p_k (reading O8).  The FP32 sum saturates a few 1e-7 below 1 for some
+    lam; the search also stops at the first k whose term no longer changes F_k (the mass
+    beyond it is below the sum's rounding), instead of running on to the step cap.
     """
     lam = np.asarray(lam, dtype=np.float32)
     u = np.asarray(u, dtype=np.float32)
@@ -109,9 +111,10 @@ def poisson_inversion_f32(lam, u):
     while np.any(active) and kk < INVERSION_MAX_K:
         kk += 1
         p = np.where(active, (p * lam) * RCP_F32[kk], p).astype(np.float32)
-        F = np.where(active, F + p, F).astype(np.float32)
+        Fn = np.where(active, F + p, F).astype(np.float32)
         k = np.where(active, kk, k)
-        active = active & (u > F)
+        active = active & (u > Fn) & (Fn > F)
+        F = Fn
     return k
 
 

@@ -87,11 +87,14 @@ __constant__ const RcpTable kRcp = RcpTable();
 constexpr int kInversionMaxK = 100;
 
 // Sequential search: p_0 = exp(-lam), p_k = (p_{k-1} lam) (1/k), F_k = F_{k-1} + p_k; the
-// smallest k with u <= F_k (at most kInversionMaxK).  The step counter is the loop counter, the
-// same in every lane still searching, so 1/k is a scalar load rather than one load per lane.
+// smallest k with u <= F_k (at most kInversionMaxK).  The FP32 sum saturates a few 1e-7 below 1
+// for some lam, so the search also stops at the first k whose term leaves F_k unchanged (the
+// mass beyond it is below the sum's rounding) rather than running on to the cap.  The step
+// counter is the loop counter, the same in every lane still searching, so 1/k is a scalar load.
 __device__ __forceinline__ int poisson_inversion(float lam, float u) {
 #pragma clang fp contract(off)
-  float p = expf(-lam);
+  const float p0 = expf(-lam);
+  float p = p0;
   float F = p;
   int k = 0;
 #pragma unroll 1
@@ -101,6 +104,20 @@ __device__ __forceinline__ int poisson_inversion(float lam, float u) {
     p = (p * lam) * kRcp.v[kk];
     F = F + p;
   }
+  // The sum grows until its terms fall below its rounding and then never again, so a search
+  // that ran out of steps with u still above the sum saturated: its count is the first step
+  // that left the sum unchanged (found by replaying the steps; this happens about once in 1e9).
+  if (k == kInversionMaxK && u > F) {
+    p = p0;
+    F = p0;
+#pragma unroll 1
+    for (int kk = 1; kk <= kInversionMaxK; ++kk) {
+      p = (p * lam) * kRcp.v[kk];
+      const float Fn = F + p;
+      if (!(Fn > F)) return kk;
+      F = Fn;
+    }
+  }
   return k;
 }
 
@@ -108,6 +125,8 @@ __device__ __forceinline__ int poisson_inversion(float lam, float u) {
 // of poisson_inversion: the searches of a lane overlap instead of running one after another.
 // Entries with use[j] false keep k[j] = 0.  more[j] is set for an entry still searching after
 // STEPS steps; poisson_inversion run on it from the start then gives its count (the same steps).
+// The head leaves out the stop where the sum no longer grows: an entry that reaches such a step
+// has u above the sum and stays searching, so it goes to poisson_inversion, which applies it.
 template <int NJ, int STEPS>
 __device__ __forceinline__ void poisson_inversion_head(const float (&lam)[NJ], const float (&u)[NJ],
                                                        const bool (&use)[NJ], int (&k)[NJ], bool (&more)[NJ]) {

@@ -667,3 +667,17 @@ def test_polychromatic_strehl_of_a_flat_wavefront_is_the_weight_sum():
     w = [0.5, 0.2, 0.3]
     P = OPSF.polychromatic(cfgs, w, [np.zeros((32, 32))])
     assert abs(P[64, 64] - sum(w)) < 1e-12
+
+
+def test_inversion_never_runs_to_the_cap_where_the_fp32_cdf_saturates():
+    # for these means the FP32 cumulative sum ends a few 1e-7 below the largest uniform; the search
+    # stops where the sum stops growing, at a count consistent with the mean, not at the step cap
+    u = np.float32(1 - 2.0 ** -24)
+    for lam in (0.01189812, 0.0200900, 0.0536567, 3.3, 9.7):
+        lam = np.float32(lam)
+        k = int(P.poisson_inversion_f32(lam, u))
+        assert k < P.INVERSION_MAX_K
+        assert k <= lam + 12 * math.sqrt(lam) + 12
+        # the probability of k or more, in FP64, is far below the uniform's resolution
+        tail = 1.0 - sum(math.exp(-float(lam)) * float(lam) ** j / math.factorial(j) for j in range(k))
+        assert tail < 1e-6
