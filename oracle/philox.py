@@ -10,10 +10,12 @@ than by consumption order (reading O8):
 * Philox4x32-10 is the counter-based generator of Salmon, Moraes, Dror and
   Shaw, "Parallel Random Numbers: As Easy as 1, 2, 3" (SC'11), written
   here from its published definition.
-* Poisson counts: sequential-search inversion for lambda < 10 and the
+* Poisson counts: sequential-search inversion for lambda < 20 and the
   transformed-rejection method with squeeze (PTRS) of W. Hormann, "The
   transformed rejection method for generating Poisson random variables",
-  Insurance: Mathematics and Economics 12 (1993) 39-45, for lambda >= 10.
+  Insurance: Mathematics and Economics 12 (1993) 39-45, for lambda >= 20
+  (the method holds from 10; the split is where the GPU's inversion stops
+  being the cheaper one).
   Both decide an integer, so they run in FP32 arithmetic, the precision
   the GPU path takes the same decision in.
 * Read noise: Box-Muller on words 2 and 3 of a pair block, both of its
@@ -40,7 +42,7 @@ W0 = 0x9E3779B9
 W1 = 0xBB67AE85
 MASK32 = 0xFFFFFFFF
 
-POISSON_SPLIT = 10.0
+POISSON_SPLIT = 20.0
 PTRS_MAX_TRIALS = 64
 INVERSION_MAX_K = 100
 

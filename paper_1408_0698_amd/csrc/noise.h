@@ -2,9 +2,9 @@
 //
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers: As
 // Easy as 1, 2, 3", SC'11); Poisson counts by sequential-search inversion
-// below mean 10 and by the transformed rejection with squeeze (PTRS) of
+// below mean 20 and by the transformed rejection with squeeze (PTRS) of
 // W. Hormann, "The transformed rejection method for generating Poisson
-// random variables" (1993) from mean 10; Gaussian read noise by
+// random variables" (1993) from mean 20; Gaussian read noise by
 // Box-Muller.  The integer decisions are taken in FP32 with contraction
 // off, operation by operation in the order written.
 //
@@ -85,6 +85,10 @@ struct RcpTable {
 };
 __constant__ const RcpTable kRcp = RcpTable();
 constexpr int kInversionMaxK = 100;
+// Means below the split take the inversion, the others PTRS.  On the GPU the inversion's steps
+// cost less than a rejection trial's logarithms up to means of about 20-30 (measured), and in
+// FP32 e^-20 and the search up to its cap stay well within range.
+constexpr float kPoissonSplit = 20.0f;
 
 // Sequential search: p_0 = exp(-lam), p_k = (p_{k-1} lam) (1/k), F_k = F_{k-1} + p_k; the
 // smallest k with u <= F_k (at most kInversionMaxK).  The FP32 sum saturates a few 1e-7 below 1
@@ -158,8 +162,9 @@ __device__ __forceinline__ void poisson_inversion_head(const float (&lam)[NJ], c
   for (int j = 0; j < NJ; ++j) more[j] = act[j];
 }
 
-// PTRS for mean lam >= 10 at pixel pix: trial t = 1 .. 64 takes the uniforms (u, v) from words x
-// and y of block (t, pix, gsub, frame); after 64 rejections, floor(lam + 1/2).
+// PTRS for mean lam >= kPoissonSplit (the method holds from 10) at pixel pix: trial t = 1 .. 64
+// takes the uniforms (u, v) from words x and y of block (t, pix, gsub, frame); after 64
+// rejections, floor(lam + 1/2).
 __device__ __forceinline__ int poisson_ptrs(float lam, uint32_t pix, uint32_t gsub, uint32_t frame, uint32_t k0,
                                             uint32_t k1) {
 #pragma clang fp contract(off)
@@ -209,7 +214,7 @@ __device__ __forceinline__ float noisy_pixel(float lam, float ron, uint32_t pix,
   const uint4 w = pair_block(second ? pix - h : pix, gsub, frame, k0, k1);
   int k = 0;
   if (lam > 0.0f) {
-    if (lam < 10.0f)
+    if (lam < kPoissonSplit)
       k = poisson_inversion(lam, u01(second ? w.y : w.x));
     else
       k = poisson_ptrs(lam, pix, gsub, frame, k0, k1);

@@ -594,7 +594,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   // Lane l takes detector row p = l / G and the QB consecutive pixels q0 .. q0 + QB - 1,
   // q0 = QB (l % G); b QB is an integer, so the row rebin of the block reads the KB = b QB
   // inputs from k0 = b q0 with weights known at compile time.
-  // Pass 1 handles every pixel except noisy ones with mean >= 10, which are queued in LDS;
+  // Pass 1 handles every pixel except noisy ones with mean >= kPoissonSplit, queued in LDS;
   // pass 2 runs the rejection sampler on the queue with the item's lanes side by side.
   constexpr int QB = det_block(CONV_N, DET_N, L);
   constexpr int G = DET_N / QB;
@@ -643,7 +643,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       const float lam = a.ph_scale * det;
       img = lam;
       if (a.noise) {
-        if (lam >= 10.0f) {
+        if (lam >= kPoissonSplit) {
           queue[atomicAdd(&queue[QCOUNT], 1)] = pix;
           return;
         }
@@ -746,7 +746,7 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   constexpr int NPIX = DET_N * DET_N;
   constexpr float CD = 0.5f * (float)(DET_N - 1);
   // per-wavefront pixel queues: long inversions (pixel, mean, uniform, read-noise deviate) from
-  // the front, means >= 10 for the rejection sampler (pixel, mean, read-noise deviate) from the
+  // the front, means >= kPoissonSplit for the rejection sampler (pixel, mean, read-noise deviate) from the
   // back, so that each runs once for up to 64 pixels
   __shared__ int q_pix[4][NPIX];
   __shared__ float q_val[4][3][NPIX];
@@ -772,7 +772,7 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
     const int pix = lane + 64 * j;
     v[j] = pix < NPIX ? det[pix] : 0.0f;
     if (a.ph_scale > 0.0f) v[j] = a.ph_scale * v[j];  // expected electrons
-    small[j] = need_rng && pix < NPIX && v[j] > 0.0f && v[j] < 10.0f;
+    small[j] = need_rng && pix < NPIX && v[j] > 0.0f && v[j] < kPoissonSplit;
   }
   if (need_rng) {
     if constexpr (PAIRED) {
@@ -802,7 +802,7 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   }
   // Inversions: a few lockstep steps for the lane's pixels (most means are small and end there);
   // the ones still searching go to queue A and restart one per lane, so that the lane's long
-  // searches do not hold its other pixels.  Means >= 10 go to queue B (rejection sampler).  Both
+  // searches do not hold its other pixels.  Means >= kPoissonSplit go to queue B (rejection sampler).  Both
   // queues share the LDS arrays: A from the front, B from the back.
   constexpr int HEAD = 4;
   int k[NJ];
@@ -824,7 +824,7 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   for (int j = 0; j < NJ; ++j) {
     const int pix = lane + 64 * j;
     const bool in = pix < NPIX;
-    const bool big = need_rng && in && v[j] >= 10.0f;
+    const bool big = need_rng && in && v[j] >= kPoissonSplit;
     const uint64_t ma = __ballot(more[j]);
     const uint64_t mb = __ballot(big);
     if (more[j]) {

@@ -271,7 +271,7 @@ def _poisson_sample(lam, n, seed=77):
     return P.poisson_counts(np.full(n, lam, np.float32), seed, pix, 5, 9, n)
 
 
-@pytest.mark.parametrize("lam", [0.3, 2.5, 9.5, 10.0, 31.7, 250.0])
+@pytest.mark.parametrize("lam", [0.3, 2.5, 9.5, 10.0, 19.7, 20.0, 31.7, 250.0])
 def test_poisson_moments_and_pmf(lam):
     n = 400_000
     k = _poisson_sample(lam, n)
@@ -673,7 +673,7 @@ def test_inversion_never_runs_to_the_cap_where_the_fp32_cdf_saturates():
     # for these means the FP32 cumulative sum ends a few 1e-7 below the largest uniform; the search
     # stops where the sum stops growing, at a count consistent with the mean, not at the step cap
     u = np.float32(1 - 2.0 ** -24)
-    for lam in (0.01189812, 0.0200900, 0.0536567, 3.3, 9.7):
+    for lam in (0.01189812, 0.0200900, 0.0536567, 3.3, 9.7, 15.5, 19.9):
         lam = np.float32(lam)
         k = int(P.poisson_inversion_f32(lam, u))
         assert k < P.INVERSION_MAX_K
