@@ -421,49 +421,43 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       if constexpr (BL) {
         // rows NPX .. N/2-1 are zero; row 0 holds the real row 0 only (row N/2 is zero), so its
         // filter is the plain product by K^ row 0.  Four lanes per row (q = l & 3, row l >> 2):
-        // each transforms the samples 4t + q, a radix-4 step across the quad (DPP) completes the
-        // N-point transform; lane q holds spectral samples c + (N/4) m(q), m = (0, 2, 1, 3).
+        // each transforms the samples 4t + q; spectral sample c + (N/4) m is then the sum over the
+        // quad of W_4^(q m) W_N^(q c) X_q[c].  Only m = 0 and m = 3 (samples c and c - N/4) lie in
+        // the spot's band, so the quad forms just those two sums (DPP adds, the same value in every
+        // lane), filters them, and each lane takes back its share conj(W_N^(q c)) Z_0 +
+        // conj(W_4^(3q) W_N^(q c)) Z_3 for the inverse transform.
         constexpr int M4 = CONV_N / 4;
+        static_assert(M4 == NPX, "band-limited row filter: N = 4 NPX");
         const int r4 = l >> 2, q = l & 3;
         if (active) {
-          const int m = ((q & 1) << 1) | (q >> 1);
-          // K^ row r4 at the lane's spectral samples c + (N/4) m, zero outside the spot's band;
-          // loaded unconditionally (in bounds for every lane) before the forward transform
-          float khv[M4];
-#pragma unroll
-          for (int c = 0; c < M4; ++c) khv[c] = kh_item[r4 * CONV_N + c + M4 * m];
-#pragma unroll
-          for (int c = 0; c < M4; ++c) {
-            const int j = c + M4 * m;
-            khv[c] = (j < NPX || j > CONV_N - NPX) ? khv[c] : 0.0f;
-          }
           float2 xq[M4];
 #pragma unroll
           for (int t = 0; t < M4; ++t) xq[t] = make_float2(re[r4 * ST + 4 * t + q], im[r4 * ST + 4 * t + q]);
           RegFFT<M4, -1>::run(xq);
-          // radix-2 x radix-2 across the quad: every butterfly is out = partner + s * own, with the
-          // internal twiddle (-i forward, +i inverse) applied by lane 3 to its own value
-          const float s2 = (q & 2) ? -1.0f : 1.0f, s1 = (q & 1) ? -1.0f : 1.0f;
-          const bool l3 = q == 3;
+          // K^ row r4 at samples c and c + 3N/4, all read before the first is used
+          float k0[M4], k3[M4];
 #pragma unroll
           for (int c = 0; c < M4; ++c) {
-            const float2 w = qtw[q * M4 + c];  // W_N^(q c)
-            float2 v = cmul(xq[c], w);
-            // forward: pairs q ^ 2, internal twiddle, pairs q ^ 1; lane q then holds sample c + (N/4) m(q)
-            float2 o = quad_swap2(v);
-            v = make_float2(o.x + s2 * v.x, o.y + s2 * v.y);
-            v = l3 ? make_float2(v.y, -v.x) : v;
-            o = pair_swap(v);
-            v = make_float2(o.x + s1 * v.x, o.y + s1 * v.y);
-            // filter: the spectrum is zero beyond NPX - 1 samples from 0 (band limit of the spot)
-            v = cscale(v, khv[c]);
-            // inverse: pairs q ^ 1, internal twiddle, pairs q ^ 2
-            o = pair_swap(v);
-            v = make_float2(o.x + s1 * v.x, o.y + s1 * v.y);
-            v = l3 ? make_float2(-v.y, v.x) : v;
-            o = quad_swap2(v);
-            v = make_float2(o.x + s2 * v.x, o.y + s2 * v.y);
-            xq[c] = cmul(v, cconj(w));
+            k0[c] = kh_item[r4 * CONV_N + c];
+            k3[c] = c > 0 ? kh_item[r4 * CONV_N + 3 * M4 + c] : 0.0f;  // sample 3N/4 is outside the band
+          }
+#pragma unroll
+          for (int c = 0; c < M4; ++c) {
+            const float2 w = qtw[q * M4 + c];            // W_N^(q c)
+            const float2 w3 = qtw[CONV_N + q * M4 + c];  // W_4^(3q) W_N^(q c) = i^q W_N^(q c)
+            const float2 v = cmul(xq[c], w);
+            float2 y0 = make_float2(v.x + quad_swap2(v.x), v.y + quad_swap2(v.y));
+            y0 = make_float2(y0.x + pair_swap(y0.x), y0.y + pair_swap(y0.y));
+            y0 = cscale(y0, k0[c]);
+            float2 u = cmul(y0, cconj(w));
+            if (c > 0) {
+              const float2 v3 = cmul(xq[c], w3);
+              float2 y3 = make_float2(v3.x + quad_swap2(v3.x), v3.y + quad_swap2(v3.y));
+              y3 = make_float2(y3.x + pair_swap(y3.x), y3.y + pair_swap(y3.y));
+              y3 = cscale(y3, k3[c]);
+              u = cadd(u, cmul(y3, cconj(w3)));
+            }
+            xq[c] = u;
           }
           RegFFT<M4, 1>::run(xq);
 #pragma unroll
@@ -709,15 +703,20 @@ __global__ __launch_bounds__(SPB * CONV_N) __attribute__((amdgpu_waves_per_eu(WP
   using LY = FusedLayout<NPX, FFT_N, CONV_N, DET_N, SPLIT, DSPLIT, BL>;
   __shared__ __align__(16) float s_re[SPB * LY::PLANE];
   __shared__ __align__(16) float s_im[SPB * LY::PLANE];
-  // band-limited kernels: W_N^(q c) = exp(-2 pi i q c / N), q < 4, c < N/4 (first read after a barrier)
-  constexpr int QTW = BL ? CONV_N : 1;
+  // band-limited kernels: W_N^(q c) = exp(-2 pi i q c / N), q < 4, c < N/4, then the same times
+  // i^q (first read after a barrier)
+  constexpr int QTW = BL ? 2 * CONV_N : 1;
   __shared__ float2 s_qtw[QTW];
   if constexpr (BL) {
     constexpr TwiddleTable<CONV_N> tw{};
     if ((int)threadIdx.x < CONV_N) {
       const int q = threadIdx.x / (CONV_N / 4), c = threadIdx.x - q * (CONV_N / 4);
       const int j = (q * c) % CONV_N;
-      s_qtw[threadIdx.x] = make_float2(tw.c[j], -tw.s[j]);
+      const float2 wv = make_float2(tw.c[j], -tw.s[j]);
+      s_qtw[threadIdx.x] = wv;
+      // i^q (a + i b): (a, b), (-b, a), (-a, -b), (b, -a)
+      s_qtw[CONV_N + threadIdx.x] = q == 0 ? wv : (q == 1 ? make_float2(-wv.y, wv.x)
+                                                          : (q == 2 ? make_float2(-wv.x, -wv.y) : make_float2(wv.y, -wv.x)));
     }
   }
   const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev : a.frame0;
@@ -918,7 +917,8 @@ static hipError_t launch_variant(const WfsLaunch& a0, hipStream_t st) {
 // waves-per-EU target, persistent grid, noise in the fused kernel or after it).  Variants
 // from kFirstDetSplit on end the fused kernel at the detector.
 constexpr int kTunedVariants = 11;
-// Band-limited variants (11: persistent, WPE 4; 12: one-shot, WPE 1), for LGS shapes with FFT_N = CONV_N.
+// Band-limited variants (11: persistent, 5 waves per EU; 12: one-shot, 6 waves per EU), for LGS shapes with
+// FFT_N = CONV_N.
 constexpr int kBandLimitedVariants = 2;
 template <int NPX, int FFT_N, int CONV_N, bool LGS>
 constexpr bool band_limited_ok() {
@@ -966,7 +966,7 @@ static hipError_t launch_one(int variant, const WfsLaunch& a, hipStream_t st) {
       case 12:
         if constexpr (band_limited_ok<NPX, FFT_N, CONV_N, LGS>()) {
           if (variant == 11) return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 5, true, true, false, true, true>(a, st);
-          return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, true, false, true, true>(a, st);
+          return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 6, false, true, false, true, true>(a, st);
         }
         return hipErrorInvalidValue;
       default: return hipErrorInvalidValue;
