@@ -85,12 +85,12 @@ hipError_t launch_project_layers(const ProjectLaunch& a, hipStream_t st) {
 
 // One block per LGS: samples of the launch beam, FP64 sums reduced in a fixed order.
 __global__ __launch_bounds__(256) void uplink_tilt_kernel(const UplinkLaunch a) {
-  __shared__ double red[4][256];
+  __shared__ double red[3][256];
   const int k = blockIdx.x;
   const double* g = a.lgs[k];
   const double lx = g[0], ly = g[1], tx = g[2], ty = g[3], H = g[4];
   const double step = a.d / a.n_s, r2 = 0.25 * a.d * a.d;
-  double so = 0.0, sxo = 0.0, syo = 0.0, sxx = 0.0;
+  double sxo = 0.0, syo = 0.0, sxx = 0.0;
   for (int e = threadIdx.x; e < a.n_s * a.n_s; e += 256) {
     const int si = e / a.n_s, sj = e - si * a.n_s;
     const double sx = ((double)sj + 0.5 - 0.5 * a.n_s) * step;
@@ -105,25 +105,23 @@ __global__ __launch_bounds__(256) void uplink_tilt_kernel(const UplinkLaunch a) 
       const double inv_p = 1.0 / L.pitch_m;
       opd += layer_sample(L, L.x0 + (cx + sx) * inv_p, L.y0 + (cy + sy) * inv_p);
     }
-    so += 1.0;
     sxo += sx * opd;
     syo += sy * opd;
     sxx += sx * sx;  // the sample set is symmetric: sum sy^2 = sum sx^2, sum sx = sum sy = sum sx sy = 0
   }
-  red[0][threadIdx.x] = so;
-  red[1][threadIdx.x] = sxo;
-  red[2][threadIdx.x] = syo;
-  red[3][threadIdx.x] = sxx;
+  red[0][threadIdx.x] = sxo;
+  red[1][threadIdx.x] = syo;
+  red[2][threadIdx.x] = sxx;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w)
-      for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double den = red[3][0];
-    a.tilt[2 * k] = den > 0.0 ? red[1][0] / den : 0.0;
-    a.tilt[2 * k + 1] = den > 0.0 ? red[2][0] / den : 0.0;
+    const double den = red[2][0];
+    a.tilt[2 * k] = den > 0.0 ? red[0][0] / den : 0.0;
+    a.tilt[2 * k + 1] = den > 0.0 ? red[1][0] / den : 0.0;
   }
 }
 
