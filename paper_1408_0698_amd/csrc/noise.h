@@ -90,14 +90,13 @@ constexpr int kInversionMaxK = 100;
 // FP32 e^-20 and the search up to its cap stay well within range.
 constexpr float kPoissonSplit = 20.0f;
 
-// Sequential search: p_0 = exp(-lam), p_k = (p_{k-1} lam) (1/k), F_k = F_{k-1} + p_k; the
+// Sequential search from p0 = exp(-lam): p_k = (p_{k-1} lam) (1/k), F_k = F_{k-1} + p_k; the
 // smallest k with u <= F_k (at most kInversionMaxK).  The FP32 sum saturates a few 1e-7 below 1
 // for some lam, so the search also stops at the first k whose term leaves F_k unchanged (the
 // mass beyond it is below the sum's rounding) rather than running on to the cap.  The step
 // counter is the loop counter, the same in every lane still searching, so 1/k is a scalar load.
-__device__ __forceinline__ int poisson_inversion(float lam, float u) {
+__device__ __forceinline__ int poisson_inversion_from(float lam, float u, float p0) {
 #pragma clang fp contract(off)
-  const float p0 = expf(-lam);
   float p = p0;
   float F = p;
   int k = 0;
@@ -125,15 +124,22 @@ __device__ __forceinline__ int poisson_inversion(float lam, float u) {
   return k;
 }
 
+// The same with p0 = exp(-lam) computed here.
+__device__ __forceinline__ int poisson_inversion(float lam, float u) {
+  return poisson_inversion_from(lam, u, expf(-lam));
+}
+
 // The first STEPS steps of NJ independent inversions, advanced in lockstep with the arithmetic
 // of poisson_inversion: the searches of a lane overlap instead of running one after another.
 // Entries with use[j] false keep k[j] = 0.  more[j] is set for an entry still searching after
-// STEPS steps; poisson_inversion run on it from the start then gives its count (the same steps).
+// STEPS steps; poisson_inversion_from run on it from the start (with p0[j] = exp(-lam[j])) then
+// gives its count (the same steps).
 // The head leaves out the stop where the sum no longer grows: an entry that reaches such a step
 // has u above the sum and stays searching, so it goes to poisson_inversion, which applies it.
 template <int NJ, int STEPS>
 __device__ __forceinline__ void poisson_inversion_head(const float (&lam)[NJ], const float (&u)[NJ],
-                                                       const bool (&use)[NJ], int (&k)[NJ], bool (&more)[NJ]) {
+                                                       const bool (&use)[NJ], int (&k)[NJ], bool (&more)[NJ],
+                                                       float (&p0)[NJ]) {
 #pragma clang fp contract(off)
   static_assert(STEPS < kInversionMaxK, "head steps");
   float p[NJ], F[NJ];
@@ -141,6 +147,7 @@ __device__ __forceinline__ void poisson_inversion_head(const float (&lam)[NJ], c
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     p[j] = use[j] ? expf(-lam[j]) : 0.0f;
+    p0[j] = p[j];
     F[j] = p[j];
     k[j] = 0;
     act[j] = use[j] && u[j] > F[j];

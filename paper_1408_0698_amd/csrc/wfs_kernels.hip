@@ -106,6 +106,13 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
+// Centroid num / den (den > 0) from the FP64 sums: FP32 operands times the hardware reciprocal,
+// a relative error of a few 1e-7, far below a slope's tolerance, for a handful of instructions
+// instead of an FP64 division.
+__device__ __forceinline__ float centroid_ratio(double num, double den) {
+  return (float)num * __builtin_amdgcn_rcpf((float)den);
+}
+
 // Per-item output buffers and noise key: from the work list, or the launch-wide layout.
 struct ItemRef {
   int f, w, i;
@@ -688,8 +695,8 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       ty += red[2 * L + j];
     }
     const bool empty = !(t0 > 0.0);
-    slopes_fw[i] = empty ? 0.0f : (float)(tx / t0);
-    slopes_fw[a.n_valid + i] = empty ? 0.0f : (float)(ty / t0);
+    slopes_fw[i] = empty ? 0.0f : centroid_ratio(tx, t0);
+    slopes_fw[a.n_valid + i] = empty ? 0.0f : centroid_ratio(ty, t0);
     if (a.flags && !a.list) a.flags[item] = empty ? 1 : 0;
   }
 }
@@ -744,11 +751,11 @@ template <int DET_N>
 __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   constexpr int NPIX = DET_N * DET_N;
   constexpr float CD = 0.5f * (float)(DET_N - 1);
-  // per-wavefront pixel queues: long inversions (pixel, mean, uniform, read-noise deviate) from
-  // the front, means >= kPoissonSplit for the rejection sampler (pixel, mean, read-noise deviate) from the
-  // back, so that each runs once for up to 64 pixels
+  // per-wavefront pixel queues: long inversions (pixel, mean, uniform, read-noise deviate,
+  // exp(-mean)) from the front, means >= kPoissonSplit for the rejection sampler (pixel, mean,
+  // read-noise deviate) from the back, so that each runs once for up to 64 pixels
   __shared__ int q_pix[4][NPIX];
-  __shared__ float q_val[4][3][NPIX];
+  __shared__ float q_val[4][4][NPIX];
   const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev : a.frame0;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: item arithmetic on the scalar unit
@@ -806,7 +813,8 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   constexpr int HEAD = 4;
   int k[NJ];
   bool more[NJ];
-  poisson_inversion_head<NJ, HEAD>(v, u, small, k, more);
+  float p0[NJ];
+  poisson_inversion_head<NJ, HEAD>(v, u, small, k, more, p0);
   double s0 = 0.0, sx = 0.0, sy = 0.0;
   auto accumulate = [&](int pix, float img) {
     if (ref.images_it) ref.images_it[pix] = img;
@@ -832,6 +840,7 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
       q_val[wave][0][e] = v[j];
       q_val[wave][1][e] = u[j];
       q_val[wave][2][e] = z[j];
+      q_val[wave][3][e] = p0[j];
     } else if (big) {
       const int e = NPIX - 1 - (nq + __popcll(mb & below));
       q_pix[wave][e] = pix;
@@ -847,7 +856,7 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
   for (int e = lane; e < na; e += 64) {
-    const int kp = poisson_inversion(q_val[wave][0][e], q_val[wave][1][e]);
+    const int kp = poisson_inversion_from(q_val[wave][0][e], q_val[wave][1][e], q_val[wave][3][e]);
     accumulate(q_pix[wave][e], (float)kp + a.ron * q_val[wave][2][e]);
   }
   for (int t = lane; t < nq; t += 64) {
@@ -863,8 +872,8 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   sy = wave_sum(sy);
   if (lane == 0) {
     const bool empty = !(s0 > 0.0);
-    ref.slopes_fw[ref.i] = empty ? 0.0f : (float)(sx / s0);
-    ref.slopes_fw[a.n_valid + ref.i] = empty ? 0.0f : (float)(sy / s0);
+    ref.slopes_fw[ref.i] = empty ? 0.0f : centroid_ratio(sx, s0);
+    ref.slopes_fw[a.n_valid + ref.i] = empty ? 0.0f : centroid_ratio(sy, s0);
     if (a.flags && !a.list) a.flags[item] = empty ? 1 : 0;
   }
 }
