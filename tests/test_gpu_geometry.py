@@ -217,3 +217,39 @@ def test_lgs_frame_from_layers_parity(torch_dev):
     from test_gpu_wfs import assert_images_close, assert_slopes_close
     assert_images_close(im.cpu().numpy().astype(np.float64), want["images"])
     assert_slopes_close(sl.cpu().numpy().astype(np.float64), want["slopes"])
+
+
+def test_geometry_edge_cases(torch_dev):
+    """No targets is a no-op; bad arguments raise before any launch; a single-wavelength
+    colour-weighted PSF is the plain accumulation; a single 2-D PSF and a zero radius."""
+    from paper_1408_0698_amd import shwfs
+    torch = torch_dev
+    print("geometry edge cases", flush=True)
+    scr = _screens([(64, 64)], 5)
+    gpu, _ = _layers(torch, scr, [(0.1, 0.0, 32.0, 32.0)])
+    out = torch.full((1, 16, 16), 7.0, device="cuda")
+    shwfs.project_layers(gpu, 16, 0.1, [], out)
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all())
+    with pytest.raises(shwfs.ShwError):
+        shwfs.project_layers(gpu, 16, 0.1, [(0.0, 0.0, -1.0)], out)   # negative altitude
+    with pytest.raises(shwfs.ShwError):
+        shwfs.project_layers(gpu, 200, 0.1, [(0.0, 0.0, 0.0)], torch.empty((1, 200, 200), device="cuda"))
+    with pytest.raises(shwfs.ShwError):
+        shwfs.uplink_tilt(gpu, [(0.0, 0.0, 0.0, 0.0, 90000.0)], 0.4, 1, torch.empty((1, 2), dtype=torch.float64,
+                                                                                    device="cuda"))
+    cfg = G.PsfConfig(pupil_n=64, pupil_dx_m=39.0 / 64)
+    plan = shwfs.PsfPlan(cfg.pupil_n, cfg.pupil_dx_m, cfg.obstruction, cfg.fft_m, cfg.wavelength_m)
+    opd = torch.from_numpy((S.screen_opd_m(512, 0.1)[:64, :64] * 0.2).astype(np.float32)[None]).cuda()
+    a = torch.zeros((1600, 1600), device="cuda")
+    plan.accumulate(opd, a)
+    b = torch.zeros((1600, 1600), device="cuda")
+    shwfs.polychromatic_psf([plan], [1.0], opd, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    ee = plan.encircled_energy(a, [0.0])
+    torch.cuda.synchronize()
+    assert ee.shape == (1,)
+    assert abs(float(ee[0]) - float(a[800, 800]) / float(a.double().sum())) < 1e-9
+    with pytest.raises(shwfs.ShwError):
+        shwfs.psf_resample_accumulate(a, 1.0, 1.0, a)   # source and destination overlap
