@@ -184,10 +184,14 @@ int shw_wfs_plan_kernel_spectra(const shw_wfs_plan* plan, int32_t wfs, float* d_
  *               r*row_pitch + c]; row_pitch >= pupil_n, all strides >= 0.
  * n_frames    : >= 0 (0 is a no-op).
  * seed, frame0: noise key and the frame number of the first frame; the
- *               noise of pixel p of sub-aperture i of sensor w in frame
- *               frame0 + f is drawn from Philox4x32-10 with key seed and
- *               counter (trial, p, w*n_valid + i, frame0 + f), so a result
- *               does not depend on how frames are batched.
+ *               noise of sub-aperture i of sensor w in frame frame0 + f
+ *               is drawn from Philox4x32-10 with key seed: pixels b and
+ *               b + h of the det_n^2 pixels (h = ceil(det_n^2 / 2)) share
+ *               the block of counter (0, b, w*n_valid + i, frame0 + f)
+ *               (Poisson uniforms from words 0 and 1, both Box-Muller
+ *               deviates from words 2 and 3); means >= 20 use the
+ *               rejection sampler with counters (t >= 1, p, ...).  So a
+ *               result does not depend on how frames are batched.
  *               frame0 + n_frames must be <= 2^32.
  * d_slopes    : [n_frames][n_wfs][2][n_valid] FP32, detector pixels from
  *               the sub-aperture centre, X (columns) block then Y block.
