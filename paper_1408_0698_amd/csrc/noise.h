@@ -71,9 +71,11 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
   return c;
 }
 
-// ((x >> 9) + 1/2) * 2^-23: exact in FP32, never 0 or 1.
+// ((x >> 9) + 1/2) * 2^-23: exact in FP32, never 0 or 1.  Formed as 1 + (x >> 9) 2^-23 (the
+// high 23 bits as the mantissa of a number in [1, 2)) minus (1 - 2^-24): both operands and the
+// difference (2 (x >> 9) + 1) 2^-24 are exact.
 __device__ __forceinline__ float u01(uint32_t x) {
-  return ((float)(x >> 9) + 0.5f) * 1.1920928955078125e-07f;
+  return __uint_as_float((x >> 9) | 0x3F800000u) - 0.999999940395355224609375f;
 }
 
 // 1/k rounded to FP32 (index 0 unused): the inversion multiplies by it instead of dividing.
@@ -89,6 +91,20 @@ constexpr int kInversionMaxK = 100;
 // cost less than a rejection trial's logarithms up to means of about 20-30 (measured), and in
 // FP32 e^-20 and the search up to its cap stay well within range.
 constexpr float kPoissonSplit = 20.0f;
+
+// e^-lam for 0 <= lam < 87 (a normal result), without the out-of-range branches of expf: with
+// the Cody-Waite split of the exponent, -lam log2(e) = n + r, n = rint(h) for the rounded product
+// h, r = (h - n) + l where l (FMA) carries the product's rounding error and the low part of
+// log2(e); then e^-lam = 2^n 2^r with the hardware base-2 exponential of r (|r| <= 1/2 + 1e-6).
+__device__ __forceinline__ float exp_neg(float lam) {
+#pragma clang fp contract(off)  // h - n must be the exact difference of the rounded h and n
+  constexpr float kLog2E = 1.44269502162933349609375f;       // log2(e) rounded to FP32
+  constexpr float kLog2ELo = 1.925963033500011079e-8f;      // log2(e) - kLog2E
+  const float h = -lam * kLog2E;
+  const float l = fmaf(-lam, kLog2ELo, fmaf(-lam, kLog2E, -h));
+  const float n = rintf(h);
+  return ldexpf(__builtin_amdgcn_exp2f((h - n) + l), (int)n);
+}
 
 // Sequential search from p0 = exp(-lam): p_k = (p_{k-1} lam) (1/k), F_k = F_{k-1} + p_k; the
 // smallest k with u <= F_k (at most kInversionMaxK).  The FP32 sum saturates a few 1e-7 below 1
@@ -124,9 +140,9 @@ __device__ __forceinline__ int poisson_inversion_from(float lam, float u, float 
   return k;
 }
 
-// The same with p0 = exp(-lam) computed here.
+// The same with p0 = exp(-lam) computed here (0 < lam < kPoissonSplit).
 __device__ __forceinline__ int poisson_inversion(float lam, float u) {
-  return poisson_inversion_from(lam, u, expf(-lam));
+  return poisson_inversion_from(lam, u, exp_neg(lam));
 }
 
 // The first STEPS steps of NJ independent inversions, advanced in lockstep with the arithmetic
@@ -146,7 +162,7 @@ __device__ __forceinline__ void poisson_inversion_head(const float (&lam)[NJ], c
   bool act[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
-    p[j] = use[j] ? expf(-lam[j]) : 0.0f;
+    p[j] = use[j] ? exp_neg(lam[j]) : 0.0f;
     p0[j] = p[j];
     F[j] = p[j];
     k[j] = 0;

@@ -38,7 +38,8 @@
 //     FP64 sums, reduced over the item's lanes.  Detector-split variants
 //     stop after C, write the detector values to a workspace and run D in
 //     det_noise_kernel: one wavefront per item and few registers, so many
-//     more waves hide the latency of the Philox chains.
+//     more waves hide the latency of the Philox chains; its centroid sums
+//     are FP32 (a lane's few pixels, then a six-level tree over the lanes).
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -85,25 +86,25 @@ __device__ __forceinline__ uint32_t udiv_magic(uint32_t n, uint32_t m, uint32_t 
   return (__umulhi(n, m) + n) >> s;
 }
 
-// v + (v of the lane selected by the DPP control), FP64 as two 32-bit moves.
-template <int CTRL>
-__device__ __forceinline__ double dpp_add_f64(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
-  return v + __hiloint2double(hi, lo);
+// v + (v of the lane selected by the DPP control) in the rows enabled by ROWS; the other rows
+// add zero and keep v.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_add_f32(float v) {
+  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
 }
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                          __builtin_amdgcn_readlane(__double2loint(v), l));
-}
-// Sum over the 64 lanes of a wavefront (all lanes active), the same value in every lane: lane
-// pairs and quads (quad permutations), rows of 16 (rotations by 4 and 8), then the four rows.
-__device__ __forceinline__ double wave_sum(double v) {
-  v = dpp_add_f64<0xB1>(v);   // quad_perm 1, 0, 3, 2
-  v = dpp_add_f64<0x4E>(v);   // quad_perm 2, 3, 0, 1
-  v = dpp_add_f64<0x124>(v);  // row_ror 4
-  v = dpp_add_f64<0x128>(v);  // row_ror 8
-  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+// Sum over the 64 lanes of a wavefront (all lanes active), in every lane (read from lane 63): a six-level tree of pairs
+// and quads (quad permutations), rows of 16 (rotations by 4 and 8), then row 0 into row 1 and row
+// 2 into row 3 (broadcast of lane 15 to the next row) and rows 0-1 into row 3 (broadcast of lane
+// 31).  Each value takes part in six additions, so the rounding error is at most about
+// 6 * 2^-24 times the sum of the magnitudes.
+__device__ __forceinline__ float wave_sum_tree(float v) {
+  v = dpp_add_f32<0xB1, 0xF>(v);   // quad_perm 1, 0, 3, 2
+  v = dpp_add_f32<0x4E, 0xF>(v);   // quad_perm 2, 3, 0, 1
+  v = dpp_add_f32<0x124, 0xF>(v);  // row_ror 4
+  v = dpp_add_f32<0x128, 0xF>(v);  // row_ror 8
+  v = dpp_add_f32<0x142, 0xA>(v);  // row_bcast 15 into rows 1 and 3
+  v = dpp_add_f32<0x143, 0xC>(v);  // row_bcast 31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 // Centroid num / den (den > 0) from the FP64 sums: FP32 operands times the hardware reciprocal,
@@ -746,7 +747,9 @@ __global__ __launch_bounds__(SPB * CONV_N) __attribute__((amdgpu_waves_per_eu(WP
 
 // Stage D of the detector-split variants: one wavefront per item, each lane takes pixels
 // l, l + 64, ... of the item's detector values in det_ws.  The same per-pixel noise (keyed by
-// pixel, sub-aperture and frame), threshold and FP64 centroid sums as the fused stage.
+// pixel, sub-aperture and frame) and threshold as the fused stage, so the same images; the
+// centroid sums are FP32 (per lane, then a tree over the lanes) instead of FP64, which moves a
+// slope by a few 1e-5 detector pixels at most.
 template <int DET_N>
 __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   constexpr int NPIX = DET_N * DET_N;
@@ -815,15 +818,18 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   bool more[NJ];
   float p0[NJ];
   poisson_inversion_head<NJ, HEAD>(v, u, small, k, more, p0);
-  double s0 = 0.0, sx = 0.0, sy = 0.0;
+  // centroid sums: FP32 over the lane's few pixels, then the 64-lane tree (wave_sum_tree); with
+  // at most a dozen terms per lane the sums are exact to about 20 * 2^-24 of their magnitudes,
+  // a few 1e-5 detector pixels at most in a slope
+  float s0 = 0.0f, sx = 0.0f, sy = 0.0f;
   auto accumulate = [&](int pix, float img) {
     if (ref.images_it) ref.images_it[pix] = img;
     const int p = pix / DET_N;
     const int q = pix - p * DET_N;
-    const double t = (double)fmaxf(img - a.thr, 0.0f);
+    const float t = fmaxf(img - a.thr, 0.0f);
     s0 += t;
-    sx += (double)((float)q - CD) * t;
-    sy += (double)((float)p - CD) * t;
+    sx = fmaf((float)q - CD, t, sx);
+    sy = fmaf((float)p - CD, t, sy);
   };
   const uint64_t below = (1ull << lane) - 1ull;
   int na = 0, nq = 0;
@@ -865,15 +871,16 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
     const int kp = poisson_ptrs(q_val[wave][0][e], (uint32_t)pix, gsub, ref.frame, ref.key0, ref.key1);
     accumulate(pix, (float)kp + a.ron * q_val[wave][2][e]);
   }
-  // every lane of the wavefront is active here: sums within rows of 16 lanes by DPP, then the
-  // four row sums
-  s0 = wave_sum(s0);
-  sx = wave_sum(sx);
-  sy = wave_sum(sy);
+  // every lane of the wavefront is active here; the sums of non-negative terms are zero only
+  // when every term is
+  s0 = wave_sum_tree(s0);
+  sx = wave_sum_tree(sx);
+  sy = wave_sum_tree(sy);
   if (lane == 0) {
-    const bool empty = !(s0 > 0.0);
-    ref.slopes_fw[ref.i] = empty ? 0.0f : centroid_ratio(sx, s0);
-    ref.slopes_fw[a.n_valid + ref.i] = empty ? 0.0f : centroid_ratio(sy, s0);
+    const bool empty = !(s0 > 0.0f);
+    const float r = __builtin_amdgcn_rcpf(s0);
+    ref.slopes_fw[ref.i] = empty ? 0.0f : sx * r;
+    ref.slopes_fw[a.n_valid + ref.i] = empty ? 0.0f : sy * r;
     if (a.flags && !a.list) a.flags[item] = empty ? 1 : 0;
   }
 }

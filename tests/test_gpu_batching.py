@@ -1,4 +1,4 @@
-"""Batching form: launch variants agree bitwise, the autotuner picks one, and a captured
+"""Batching form: launch variants agree (bitwise within a family), the autotuner picks one, and a captured
 loop-step graph replayed frame after frame equals eager calls."""
 import numpy as np
 import pytest
@@ -28,6 +28,24 @@ def _plan(cfg, n_wfs):
 WHOLE_ROWS = (0, 1, 4, 5, 6, 7)
 SPLIT_ROWS = (2, 3, 8, 9, 10)
 BAND_LIMITED = (11, 12)   # the column spectrum from autocorrelations: another rounding family
+# Variants 6-12 take noise and centroid in the separate detector kernel, whose centroid sums are
+# FP32 per lane and a 64-lane tree (variants 0-5: FP64 sums in the fused kernel).  Their images
+# equal those of their row family bitwise; their slopes differ from the FP64 sums' by the FP32
+# rounding of the sums, at most about 20 * 2^-24 of (|sum x t| + |slope| sum t) / sum t, a few
+# 1e-5 detector pixels.
+DETECTOR_KERNEL = (6, 7, 8, 9, 10, 11, 12)
+SUM_TOL_PX = 1e-4
+
+
+def _assert_same(torch, got, ref, v, w, images=True):
+    """Variant v's output equals variant w's: images bitwise, slopes bitwise when both take the
+    centroid in the same kernel, else within SUM_TOL_PX."""
+    if images:
+        assert torch.equal(got[1], ref[1]), (v, w)
+    if (v in DETECTOR_KERNEL) == (w in DETECTOR_KERNEL):
+        assert torch.equal(got[0], ref[0]), (v, w)
+    else:
+        assert (got[0] - ref[0]).abs().max().item() < SUM_TOL_PX, (v, w)
 
 
 def _measure_variants(torch, plan, opd, variants, images=True, **kw):
@@ -50,7 +68,7 @@ def test_variants_agree(torch_dev):
     out = _measure_variants(torch_dev, plan, opd, range(13), seed=7, frame0=40)
     for fam in (WHOLE_ROWS, SPLIT_ROWS, BAND_LIMITED):
         for v in fam[1:]:
-            assert torch_dev.equal(out[v][0], out[fam[0]][0]) and torch_dev.equal(out[v][1], out[fam[0]][1]), v
+            _assert_same(torch_dev, out[v], out[fam[0]], v, fam[0])
     quiet = _plan(cfg.replace(flags=0), 3)
     q = _measure_variants(torch_dev, quiet, opd, (0, 2, 11))
     for v in (2, 11):
@@ -68,7 +86,7 @@ def test_persistent_variant_covers_many_groups(torch_dev):
     out = _measure_variants(torch_dev, plan, opd, range(13), images=False, seed=3, frame0=0)
     for fam in (WHOLE_ROWS, SPLIT_ROWS, BAND_LIMITED):
         for v in fam[1:]:
-            assert torch_dev.equal(out[v][0], out[fam[0]][0]), v
+            _assert_same(torch_dev, out[v], out[fam[0]], v, fam[0], images=False)
 
 
 def test_autotune_selects_a_variant(torch_dev, tmp_path, monkeypatch):
@@ -116,13 +134,13 @@ def test_graph_replay_advances_frames(torch_dev):
 
 
 def test_detector_split_work_list_equals_single_calls(torch_dev):
-    """A work list of three frames, run with each detector-split variant, equals per-frame calls of a
-    variant of the same row-transform family."""
+    """A work list of three frames, run with each detector-split variant, equals per-frame calls of the
+    first detector-split variant of the same row-transform family."""
     from paper_1408_0698_amd import shwfs
     cfg = G.CFG1.replace(pupil_n=130, n_subap=13)
     plan = _plan(cfg, 6)
     opd = torch_dev.from_numpy(S.lgs39m_opd(3, 6, pupil_n=130)).cuda()
-    for fam_ref, variants in ((0, (6, 7)), (2, (8, 9, 10)), (11, (11, 12))):
+    for fam_ref, variants in ((6, (6, 7)), (8, (8, 9, 10)), (11, (11, 12))):
         plan.set_variant(fam_ref)
         ref = []
         for f in range(3):

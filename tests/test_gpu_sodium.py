@@ -101,8 +101,10 @@ def test_plain_measure_on_sodium_plan_shares_the_wavefront(torch_dev):
 
 
 def test_variants_agree(torch_dev):
-    """Within a row-transform family the variants agree bitwise (split rows: 1, 2; band-limited: 3, 4);
-    across families the noise-free images agree to FP32 rounding."""
+    """Within a row-transform family the variants agree (split rows: 1, 2; band-limited: 3, 4): images
+    bitwise, slopes bitwise when the centroid is taken in the same kernel (variant 1 sums in FP64 in
+    the fused kernel, 2-4 in FP32 in the detector kernel: within 1e-4 px); across families the
+    noise-free images agree to FP32 rounding."""
     from paper_1408_0698_amd import shwfs
     cfg = small_lgs(13)
     launch = G.launch_positions(cfg, 6)
@@ -121,8 +123,11 @@ def test_variants_agree(torch_dev):
     torch_dev.cuda.synchronize()
     for fl in (cfg.flags, 0):
         for x, y in ((1, 2), (3, 4)):
-            assert torch_dev.equal(outs[(fl, x)][0], outs[(fl, y)][0]) and torch_dev.equal(outs[(fl, x)][1],
-                                                                                       outs[(fl, y)][1]), (fl, x, y)
+            assert torch_dev.equal(outs[(fl, x)][1], outs[(fl, y)][1]), (fl, x, y)
+            if x == 1:
+                assert (outs[(fl, x)][0] - outs[(fl, y)][0]).abs().max().item() < 1e-4, (fl, x, y)
+            else:
+                assert torch_dev.equal(outs[(fl, x)][0], outs[(fl, y)][0]), (fl, x, y)
     a = outs[(0, 0)][1].cpu().numpy()
     for v in (1, 3):
         b = outs[(0, v)][1].cpu().numpy()
