@@ -56,6 +56,11 @@ __device__ __forceinline__ float log_factorial(float k) {
   return k < 256.0f ? kLogFactorial.v[(int)k] : lgammaf(k + 1.0f);
 }
 
+// a ^ b ^ c as one three-input bitwise operation (truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
@@ -66,7 +71,14 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     // one 32 x 32 -> 64-bit product per multiplier (v_mad_u64_u32), split into hi and lo words
     const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+    if (r < 2) {
+      // the counters used here have wavefront-uniform words z and w (and x), which keep parts
+      // of the first rounds on the scalar unit: plain XORs leave them there
+      c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+    } else {
+      c = make_uint4(xor3((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1, xor3((uint32_t)(p0 >> 32), c.w, k1),
+                     (uint32_t)p0);
+    }
   }
   return c;
 }

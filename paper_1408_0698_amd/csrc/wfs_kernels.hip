@@ -776,12 +776,18 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   constexpr bool PAIRED = NJ % 2 == 0 && PH == 64 * (NJ / 2);
   float v[NJ], u[NJ], z[NJ];
   bool small[NJ];
+  // all loads first, then branch-free tests (short-circuit tests would put a branch, and so a
+  // wait for the load, between consecutive loads)
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     const int pix = lane + 64 * j;
     v[j] = pix < NPIX ? det[pix] : 0.0f;
-    if (a.ph_scale > 0.0f) v[j] = a.ph_scale * v[j];  // expected electrons
-    small[j] = need_rng && pix < NPIX && v[j] > 0.0f && v[j] < kPoissonSplit;
+  }
+  const float scale = a.ph_scale > 0.0f ? a.ph_scale : 1.0f;  // to expected electrons
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    v[j] = scale * v[j];
+    small[j] = need_rng & (lane + 64 * j < NPIX) & (v[j] > 0.0f) & (v[j] < kPoissonSplit);
   }
   if (need_rng) {
     if constexpr (PAIRED) {
