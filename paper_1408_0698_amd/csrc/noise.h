@@ -92,13 +92,14 @@ __device__ __forceinline__ float u01(uint32_t x) {
 
 // 1/k rounded to FP32 (index 0 unused): the inversion multiplies by it instead of dividing.
 struct RcpTable {
-  float v[128];
+  float v[128];  // at least kInversionMaxK + 3 entries (the search reads one pass ahead)
   constexpr RcpTable() : v() {
     for (int k = 1; k < 128; ++k) v[k] = (float)(1.0 / (double)k);
   }
 };
 __constant__ const RcpTable kRcp = RcpTable();
 constexpr int kInversionMaxK = 100;
+static_assert(kInversionMaxK + 3 <= 128, "reciprocal table size");
 // Means below the split take the inversion, the others PTRS.  On the GPU the inversion's steps
 // cost less than a rejection trial's logarithms up to means of about 20-30 (measured), and in
 // FP32 e^-20 and the search up to its cap stay well within range.
@@ -123,33 +124,44 @@ __device__ __forceinline__ float exp_neg(float lam) {
 // for some lam, so the search also stops at the first k whose term leaves F_k unchanged (the
 // mass beyond it is below the sum's rounding) rather than running on to the cap.  The step
 // counter is the loop counter, the same in every lane still searching, so 1/k is a scalar load.
+// Two steps per pass (kInversionMaxK is even): both sums are formed, then compared with u in
+// step order, which halves the loop's scalar bookkeeping and table loads.
 __device__ __forceinline__ int poisson_inversion_from(float lam, float u, float p0) {
 #pragma clang fp contract(off)
+  static_assert(kInversionMaxK % 2 == 0, "two steps per pass");
   float p = p0;
   float F = p;
-  int k = 0;
-#pragma unroll 1
-  for (int kk = 1; kk <= kInversionMaxK; ++kk) {
-    if (!(u > F)) break;
-    k = kk;
-    p = (p * lam) * kRcp.v[kk];
-    F = F + p;
-  }
+  if (!(u > F)) return 0;
+  // u > F_{kk-1} on entry to a pass, which forms F_kk (Fa) and F_{kk+1} (F); the pass loads the
+  // next pass's reciprocals (index at most kInversionMaxK + 2, inside the table) before its own
+  // arithmetic, so that the load's latency is not waited out at the top of the pass
+  float Fa;
+  int kk = 1;
+  float ra = kRcp.v[1], rb = kRcp.v[2];
+  do {
+    const float na = kRcp.v[kk + 2], nb = kRcp.v[kk + 3];
+    const float pa = (p * lam) * ra;
+    Fa = F + pa;
+    p = (pa * lam) * rb;
+    F = Fa + p;
+    ra = na;
+    rb = nb;
+    kk += 2;
+  } while (u > F && kk < kInversionMaxK);
+  if (!(u > F)) return kk - 2 + (u > Fa ? 1 : 0);  // F >= Fa: u <= Fa ends at step kk - 2
   // The sum grows until its terms fall below its rounding and then never again, so a search
   // that ran out of steps with u still above the sum saturated: its count is the first step
   // that left the sum unchanged (found by replaying the steps; this happens about once in 1e9).
-  if (k == kInversionMaxK && u > F) {
-    p = p0;
-    F = p0;
+  p = p0;
+  F = p0;
 #pragma unroll 1
-    for (int kk = 1; kk <= kInversionMaxK; ++kk) {
-      p = (p * lam) * kRcp.v[kk];
-      const float Fn = F + p;
-      if (!(Fn > F)) return kk;
-      F = Fn;
-    }
+  for (kk = 1; kk <= kInversionMaxK; ++kk) {
+    p = (p * lam) * kRcp.v[kk];
+    const float Fn = F + p;
+    if (!(Fn > F)) return kk;
+    F = Fn;
   }
-  return k;
+  return kInversionMaxK;
 }
 
 // The same with p0 = exp(-lam) computed here (0 < lam < kPoissonSplit).
