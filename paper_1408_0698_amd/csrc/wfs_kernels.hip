@@ -60,6 +60,35 @@ constexpr float rebin_weight(int CN, int DN, int p, int k) {
   return hi > lo ? (float)(hi - lo) : 0.0f;
 }
 
+// Band-limited column inverse transform and column rebin as one real linear map: for a column
+// whose spectrum R (Hermitian, length N) is zero outside k < NB and k > N - NB, the rebinned
+// values D[p] = sum_u W[p][u] J[u] of J[u] = sum_k R[k] e^(2 pi i u k / N) are
+// D[p] = R[0] M[p][0] + sum_{k=1}^{NB-1} 2 Re(R[k] M[p][k]), M[p][k] = sum_u W[p][u] e^(2 pi i u k / N).
+// a[p][k] = 2 Re M[p][k] and b[p][k] = -2 Im M[p][k] (k >= 1), a[p][0] = M[p][0]: FP64 sums rounded
+// to FP32 at compile time, so the map is fused multiply-adds with literal coefficients.
+template <int N, int DN, int NB>
+struct BandRebinMap {
+  float a[DN][NB];
+  float b[DN][NB];
+  constexpr BandRebinMap() : a(), b() {
+    for (int p = 0; p < DN; ++p)
+      for (int k = 0; k < NB; ++k) {
+        double re = 0.0, im = 0.0;
+        for (int u = 0; u < N; ++u) {
+          const double bn = (double)N / (double)DN;
+          const double lo = (double)u > bn * p ? (double)u : bn * p;
+          const double hi = (double)(u + 1) < bn * (p + 1) ? (double)(u + 1) : bn * (p + 1);
+          if (hi > lo) {
+            re += (hi - lo) * ct_cos_frac((long)u * k, N);
+            im += (hi - lo) * ct_sin_frac((long)u * k, N);
+          }
+        }
+        a[p][k] = (float)(k == 0 ? re : 2.0 * re);
+        b[p][k] = (float)(k == 0 ? 0.0 : -2.0 * im);
+      }
+  }
+};
+
 // Detector pixels per lane in the final stage: the smallest divisor QB of det_n such that
 // det_n^2 / QB pixels fit on the item's lanes and conv_n QB / det_n is an integer.
 constexpr int det_block(int conv_n, int det_n, int lanes) {
@@ -539,16 +568,37 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       }
     }
     __syncthreads();
-    {
+    if constexpr (BL) {
+      // B3 + column rebin as one linear map of the column's in-band spectrum rows (BandRebinMap);
+      // the detector rows are written after the barrier that frees the planes
+      constexpr BandRebinMap<CONV_N, DET_N, NPX> bm{};
+      float zr[NPX], zi[NPX];
+      zr[0] = re[l];
+      zi[0] = 0.0f;
+#pragma unroll
+      for (int k = 1; k < NPX; ++k) {
+        zr[k] = re[k * ST + l];
+        zi[k] = im[k * ST + l];
+      }
+#pragma unroll
+      for (int p = 0; p < DET_N; ++p) {
+        float acc = zr[0] * bm.a[p][0];
+#pragma unroll
+        for (int k = 1; k < NPX; ++k) {
+          acc = fmaf(zr[k], bm.a[p][k], acc);
+          acc = fmaf(zi[k], bm.b[p][k], acc);
+        }
+        col[p] = acc;
+      }
+    } else {
       // B3: real J from the half spectrum: y = IFFT_{N/2}(C), C[k] = (Z[k] + conj Z[N/2-k])
       //     + i W^-k (Z[k] - conj Z[N/2-k]); J[2m] = Re y[m], J[2m+1] = Im y[m]
       // computed in place pair by pair (k, N/2 - k): Z[k] and Z[N/2 - k] give C[k] and C[N/2 - k]
       float2 y[HN];
       const float z0 = re[l];
-      const float zh = BL ? 0.0f : (SPLIT ? im[l] : re[HN * ST + l]);
+      const float zh = SPLIT ? im[l] : re[HN * ST + l];
 #pragma unroll
-      for (int k = 1; k < HN; ++k)
-        y[k] = (BL && k >= NPX) ? make_float2(0.0f, 0.0f) : make_float2(re[k * ST + l], im[k * ST + l]);
+      for (int k = 1; k < HN; ++k) y[k] = make_float2(re[k * ST + l], im[k * ST + l]);
       auto cfold = [](float2 zk, float2 zm, int k) {
         const float2 zc = cconj(zm);
         const float2 e = cadd(zk, zc);
@@ -583,10 +633,14 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
 #pragma unroll
   for (int p = 0; p < DET_N; ++p) {
     float acc = 0.0f;
+    if constexpr (BL) {
+      acc = col[p];  // already rebinned along the column
+    } else {
 #pragma unroll
-    for (int k = 0; k < CONV_N; ++k) {
-      const float wgt = rebin_weight(CONV_N, DET_N, p, k);
-      if (wgt != 0.0f) acc += wgt * col[k];
+      for (int k = 0; k < CONV_N; ++k) {
+        const float wgt = rebin_weight(CONV_N, DET_N, p, k);
+        if (wgt != 0.0f) acc += wgt * col[k];
+      }
     }
     det_row(p)[l] = acc;
   }
