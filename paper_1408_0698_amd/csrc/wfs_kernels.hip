@@ -478,23 +478,25 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
             k0[c] = kh_item[r4 * CONV_N + c];
             k3[c] = c > 0 ? kh_item[r4 * CONV_N + 3 * M4 + c] : 0.0f;  // sample 3N/4 is outside the band
           }
+          // sample c + 3N/4 is S3 = sum_q i^q v_q (v_q = W_N^(q c) X_q[c]); the lane's share of its
+          // filtered value, conj(i^q) K3 S3, is K3 (d + i ps(d)) on even lanes and K3 (d - i ps(d))
+          // on odd ones, d = v_q - v_(q^2), ps the partner lane q^1: one DPP difference and one
+          // swap instead of a second product and quad sum
+          const float sgn = (q & 1) ? 1.0f : -1.0f;
 #pragma unroll
           for (int c = 0; c < M4; ++c) {
-            const float2 w = qtw[q * M4 + c];            // W_N^(q c)
-            const float2 w3 = qtw[CONV_N + q * M4 + c];  // W_4^(3q) W_N^(q c) = i^q W_N^(q c)
+            const float2 w = qtw[q * M4 + c];  // W_N^(q c)
             const float2 v = cmul(xq[c], w);
             float2 y0 = make_float2(v.x + quad_swap2(v.x), v.y + quad_swap2(v.y));
             y0 = make_float2(y0.x + pair_swap(y0.x), y0.y + pair_swap(y0.y));
-            y0 = cscale(y0, k0[c]);
-            float2 u = cmul(y0, cconj(w));
+            float2 t = cscale(y0, k0[c]);
             if (c > 0) {
-              const float2 v3 = cmul(xq[c], w3);
-              float2 y3 = make_float2(v3.x + quad_swap2(v3.x), v3.y + quad_swap2(v3.y));
-              y3 = make_float2(y3.x + pair_swap(y3.x), y3.y + pair_swap(y3.y));
-              y3 = cscale(y3, k3[c]);
-              u = cadd(u, cmul(y3, cconj(w3)));
+              const float2 d = make_float2(v.x - quad_swap2(v.x), v.y - quad_swap2(v.y));
+              const float2 pd = pair_swap(d);
+              const float2 g = make_float2(fmaf(sgn, pd.y, d.x), fmaf(-sgn, pd.x, d.y));
+              t = make_float2(fmaf(k3[c], g.x, t.x), fmaf(k3[c], g.y, t.y));
             }
-            xq[c] = u;
+            xq[c] = cmul(t, cconj(w));
           }
           RegFFT<M4, 1>::run(xq);
 #pragma unroll
@@ -765,20 +767,16 @@ __global__ __launch_bounds__(SPB * CONV_N) __attribute__((amdgpu_waves_per_eu(WP
   using LY = FusedLayout<NPX, FFT_N, CONV_N, DET_N, SPLIT, DSPLIT, BL>;
   __shared__ __align__(16) float s_re[SPB * LY::PLANE];
   __shared__ __align__(16) float s_im[SPB * LY::PLANE];
-  // band-limited kernels: W_N^(q c) = exp(-2 pi i q c / N), q < 4, c < N/4, then the same times
-  // i^q (first read after a barrier)
-  constexpr int QTW = BL ? 2 * CONV_N : 1;
+  // band-limited kernels: W_N^(q c) = exp(-2 pi i q c / N), q < 4, c < N/4 (first read after a
+  // barrier)
+  constexpr int QTW = BL ? CONV_N : 1;
   __shared__ float2 s_qtw[QTW];
   if constexpr (BL) {
     constexpr TwiddleTable<CONV_N> tw{};
     if ((int)threadIdx.x < CONV_N) {
       const int q = threadIdx.x / (CONV_N / 4), c = threadIdx.x - q * (CONV_N / 4);
       const int j = (q * c) % CONV_N;
-      const float2 wv = make_float2(tw.c[j], -tw.s[j]);
-      s_qtw[threadIdx.x] = wv;
-      // i^q (a + i b): (a, b), (-b, a), (-a, -b), (b, -a)
-      s_qtw[CONV_N + threadIdx.x] = q == 0 ? wv : (q == 1 ? make_float2(-wv.y, wv.x)
-                                                          : (q == 2 ? make_float2(-wv.x, -wv.y) : make_float2(wv.y, -wv.x)));
+      s_qtw[threadIdx.x] = make_float2(tw.c[j], -tw.s[j]);
     }
   }
   const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev : a.frame0;
