@@ -63,28 +63,36 @@ constexpr float rebin_weight(int CN, int DN, int p, int k) {
 // Band-limited column inverse transform and column rebin as one real linear map: for a column
 // whose spectrum R (Hermitian, length N) is zero outside k < NB and k > N - NB, the rebinned
 // values D[p] = sum_u W[p][u] J[u] of J[u] = sum_k R[k] e^(2 pi i u k / N) are
-// D[p] = R[0] M[p][0] + sum_{k=1}^{NB-1} 2 Re(R[k] M[p][k]), M[p][k] = sum_u W[p][u] e^(2 pi i u k / N).
-// a[p][k] = 2 Re M[p][k] and b[p][k] = -2 Im M[p][k] (k >= 1), a[p][0] = M[p][0]: FP64 sums rounded
-// to FP32 at compile time, so the map is fused multiply-adds with literal coefficients.
+// D[p] = Re sum_{k<NB} c_k R[k] M[p][k], M[p][k] = sum_u W[p][u] e^(2 pi i u k / N), c_0 = 1, else 2.
+// With two detector pixels per S = 2N/DN samples, pixel 2m + s is pixel s shifted by m S samples,
+// so M[2m + s][k] = M[s][k] e^(2 pi i m k / G), G = DN/2: D[2m + s] = Re sum_j B_s[j] e^(2 pi i m j / G)
+// with B_s[j] the sum of c_k R[k] M[s][k] over k = j mod G.  The real parts of the two G-point
+// inverse transforms come from one complex transform of Z = H_0 + i H_1, H_s[j] = (B_s[j] +
+// conj B_s[-j]) / 2 (Hermitian, so each transform alone would be real).  The table holds
+// f_k c_k M[s][k], f_k = 1/2 except for j = 0 and G/2, where H_s[j] = Re B_s[j]: FP64 sums rounded
+// to FP32 at compile time.
 template <int N, int DN, int NB>
-struct BandRebinMap {
-  float a[DN][NB];
-  float b[DN][NB];
-  constexpr BandRebinMap() : a(), b() {
-    for (int p = 0; p < DN; ++p)
+struct BandRebinPairs {
+  static constexpr int G = DN / 2;
+  float mr[2][NB];
+  float mi[2][NB];
+  constexpr BandRebinPairs() : mr(), mi() {
+    const double bn = (double)N / (double)DN;
+    for (int sp = 0; sp < 2; ++sp)
       for (int k = 0; k < NB; ++k) {
         double re = 0.0, im = 0.0;
         for (int u = 0; u < N; ++u) {
-          const double bn = (double)N / (double)DN;
-          const double lo = (double)u > bn * p ? (double)u : bn * p;
-          const double hi = (double)(u + 1) < bn * (p + 1) ? (double)(u + 1) : bn * (p + 1);
+          const double lo = (double)u > bn * sp ? (double)u : bn * sp;
+          const double hi = (double)(u + 1) < bn * (sp + 1) ? (double)(u + 1) : bn * (sp + 1);
           if (hi > lo) {
             re += (hi - lo) * ct_cos_frac((long)u * k, N);
             im += (hi - lo) * ct_sin_frac((long)u * k, N);
           }
         }
-        a[p][k] = (float)(k == 0 ? re : 2.0 * re);
-        b[p][k] = (float)(k == 0 ? 0.0 : -2.0 * im);
+        const int j = k % G;
+        const double f = (k == 0 ? 1.0 : 2.0) * ((j == 0 || 2 * j == G) ? 1.0 : 0.5);
+        mr[sp][k] = (float)(f * re);
+        mi[sp][k] = (float)(f * im);
       }
   }
 };
@@ -571,9 +579,12 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
     }
     __syncthreads();
     if constexpr (BL) {
-      // B3 + column rebin as one linear map of the column's in-band spectrum rows (BandRebinMap);
+      // B3 + column rebin as one linear map of the column's in-band spectrum rows (BandRebinPairs);
       // the detector rows are written after the barrier that frees the planes
-      constexpr BandRebinMap<CONV_N, DET_N, NPX> bm{};
+      static_assert(2 * CONV_N % DET_N == 0 && DET_N % 2 == 0, "two detector pixels per whole number of samples");
+      using BP = BandRebinPairs<CONV_N, DET_N, NPX>;
+      constexpr int G = BP::G;
+      constexpr BP bm{};
       float zr[NPX], zi[NPX];
       zr[0] = re[l];
       zi[0] = 0.0f;
@@ -582,15 +593,38 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
         zr[k] = re[k * ST + l];
         zi[k] = im[k * ST + l];
       }
+      float2 bs[2][G];
 #pragma unroll
-      for (int p = 0; p < DET_N; ++p) {
-        float acc = zr[0] * bm.a[p][0];
+      for (int sp = 0; sp < 2; ++sp) {
 #pragma unroll
-        for (int k = 1; k < NPX; ++k) {
-          acc = fmaf(zr[k], bm.a[p][k], acc);
-          acc = fmaf(zi[k], bm.b[p][k], acc);
+        for (int j = 0; j < G; ++j) bs[sp][j] = make_float2(0.0f, 0.0f);
+#pragma unroll
+        for (int k = 0; k < NPX; ++k) {
+          const int j = k % G;
+          const float ar = bm.mr[sp][k], ai = bm.mi[sp][k];
+          bs[sp][j].x = fmaf(zr[k], ar, bs[sp][j].x);
+          if (k > 0) bs[sp][j].x = fmaf(-zi[k], ai, bs[sp][j].x);
+          if (j != 0 && 2 * j != G) {  // only the real part is used at j = 0 and G/2
+            bs[sp][j].y = fmaf(zr[k], ai, bs[sp][j].y);
+            if (k > 0) bs[sp][j].y = fmaf(zi[k], ar, bs[sp][j].y);
+          }
         }
-        col[p] = acc;
+      }
+      float2 zz[G];
+      zz[0] = make_float2(bs[0][0].x, bs[1][0].x);
+      zz[G / 2] = make_float2(bs[0][G / 2].x, bs[1][G / 2].x);
+#pragma unroll
+      for (int j = 1; j < G / 2; ++j) {
+        const float2 h0 = make_float2(bs[0][j].x + bs[0][G - j].x, bs[0][j].y - bs[0][G - j].y);
+        const float2 h1 = make_float2(bs[1][j].x + bs[1][G - j].x, bs[1][j].y - bs[1][G - j].y);
+        zz[j] = make_float2(h0.x - h1.y, h0.y + h1.x);      // H_0 + i H_1
+        zz[G - j] = make_float2(h0.x + h1.y, h1.x - h0.y);  // conj H_0 + i conj H_1
+      }
+      RegFFT<G, 1>::run(zz);
+#pragma unroll
+      for (int m = 0; m < G; ++m) {
+        col[2 * m] = zz[m].x;
+        col[2 * m + 1] = zz[m].y;
       }
     } else {
       // B3: real J from the half spectrum: y = IFFT_{N/2}(C), C[k] = (Z[k] + conj Z[N/2-k])
