@@ -60,6 +60,14 @@ constexpr float rebin_weight(int CN, int DN, int p, int k) {
   return hi > lo ? (float)(hi - lo) : 0.0f;
 }
 
+// 1/sqrt(n) rounded to FP32 (Newton iterations in FP64 at compile time).
+template <int N>
+constexpr float kBandAmp() {
+  double r = 1.0 / (double)N;  // below the root, where the iteration rises monotonically to it
+  for (int i = 0; i < 100; ++i) r = r * (1.5 - 0.5 * (double)N * r * r);
+  return (float)r;
+}
+
 // Band-limited column inverse transform and column rebin as one real linear map: for a column
 // whose spectrum R (Hermitian, length N) is zero outside k < NB and k > N - NB, the rebinned
 // values D[p] = sum_u W[p][u] J[u] of J[u] = sum_k R[k] e^(2 pi i u k / N) are
@@ -294,16 +302,24 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
     }
     // every OPD sample of the row is inside the pupil grid: load them all first, so that the
     // loads are in flight together, and mask unlit pixels by amplitude (no branch per pixel)
+    // (the OPD is device memory: global loads, which wait on the vector memory counter only)
+    using GlobalF = __attribute__((address_space(1))) const float;
+    const GlobalF* gsrc = (const GlobalF*)src;
     float ov[NPX];
 #pragma unroll
-    for (int x = 0; x < NPX; ++x) ov[x] = src[x];
+    for (int x = 0; x < NPX; ++x) ov[x] = gsrc[x];
+    // pixel-centre x coordinates: ax0 + x is exact (half-integers far below 2^23)
+    const float ax0 = (float)x0 + 0.5f - a.half_n;
     float2 z[NPX];
 #pragma unroll
     for (int x = 0; x < NPX; ++x) {
-      const float ax = (float)(x0 + x) + 0.5f - a.half_n;
+      const float ax = ax0 + (float)x;
       const float r2 = ax * ax + ay2;
       const bool lit = (r2 <= a.r2_outer) && (r2 >= a.r2_inner);
-      const float amp = lit ? 1.0f : 0.0f;
+      // band-limited single-layer path: the autocorrelation's 1/N enters as the amplitude
+      // 1/sqrt(N) of the field (one factor per lane product instead of one per lag)
+      constexpr float kAmp = BL && !SUB ? kBandAmp<FFT_N>() : 1.0f;
+      const float amp = lit ? kAmp : 0.0f;
       // waves: OPD / lambda + centring ramp (FFT_N-1)(x+y)/(2 FFT_N) - x k2 / FFT_N = rb + x rx
       double wv = (double)ov[x] * a.inv_lambda + ((double)x * rx + rb);
       if constexpr (SUB) {
@@ -328,7 +344,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   if constexpr (BL) {
     // R[k] = sum_v I[v] w^(kv) = (1/N) sum_y G[y] conj(G[y + k]), k < NPX (zero for NPX <= k <= N/2)
     constexpr float INV_N = 1.0f / (float)FFT_N;
-    const float wgt = SUB ? (float)a.sub_coef[2 * sl + 1] * INV_N : INV_N;
+    const float wgt = SUB ? (float)a.sub_coef[2 * sl + 1] * INV_N : 1.0f;  // single layer: 1/N is in the field
     if (active) {
       float2 g[NPX];
 #pragma unroll
@@ -341,7 +357,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
         e0 = fmaf(g[y].x, g[y].x, e0);
         e0 = fmaf(g[y].y, g[y].y, e0);
       }
-      ac[0].x = fmaf(e0, wgt, ac[0].x);
+      ac[0].x = SUB ? fmaf(e0, wgt, ac[0].x) : e0;
 #pragma unroll
       for (int k = 1; k < NPX; ++k) {
         // G[y] conj(G[y + k])
@@ -355,8 +371,8 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
           ty = fmaf(g[y].y, g[y + k].x, ty);
           ty = fmaf(-g[y].x, g[y + k].y, ty);
         }
-        ac[k].x = fmaf(tx, wgt, ac[k].x);
-        ac[k].y = fmaf(ty, wgt, ac[k].y);
+        ac[k].x = SUB ? fmaf(tx, wgt, ac[k].x) : tx;
+        ac[k].y = SUB ? fmaf(ty, wgt, ac[k].y) : ty;
       }
     }
   } else {
