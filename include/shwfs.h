@@ -250,8 +250,11 @@ int shw_wfs_plan_destroy(shw_wfs_plan* plan);
  * persistent grid, row transforms whole or split over lane pairs, noise and
  * centroid in the fused kernel or in a second kernel over the detector
  * values kept in a plan-owned workspace).  Variants with the same row
- * transform give bitwise identical results; the two row-transform families
- * differ by FP32 rounding (about 1e-7 of an image).  Band-limited variants
+ * transform give bitwise identical images, and bitwise identical slopes when
+ * the centroid is taken in the same kernel (FP64 sums in the fused kernel,
+ * FP32 sums in the second kernel: slopes within 1e-4 pixel of each other);
+ * the row-transform families differ by FP32 rounding (about 1e-7 of an
+ * image).  Band-limited variants
  * (LGS with fft_n = conv_n = 4 * sub-aperture pixels: 11 and 12, sodium
  * plans 3 and 4) compute the column spectrum of the spot from
  * autocorrelations of the row transforms and filter only the rows inside

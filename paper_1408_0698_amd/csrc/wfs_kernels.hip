@@ -32,8 +32,10 @@
 //     each row-pass column over its NPX samples, only rows 0 .. NPX-1 of the
 //     half spectrum are filtered, and the inverse column transform reads
 //     only those rows: the column pass, the real column transform and half
-//     of the row filtering are not needed.
-//  C  rebin along the column in registers, then along the row via LDS.
+//     of the row filtering are not needed.  Their inverse column transform
+//     and column rebin are one compile-time linear map (BandRebinPairs).
+//  C  rebin along the column in registers (band-limited: done in B), then
+//     along the row via LDS.
 //  D  photometry, Poisson + read noise, threshold, centre of gravity with
 //     FP64 sums, reduced over the item's lanes.  Detector-split variants
 //     stop after C, write the detector values to a workspace and run D in
