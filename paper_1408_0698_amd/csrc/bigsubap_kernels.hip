@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void big_rows_kernel(const BigLaunch a, int
       if (r2 <= a.r2_outer && r2 >= a.r2_inner) {
         const double ramp = (double)((kN - 1) * (x + y)) / (2.0 * kN);
         double wv = (double)src[x] * a.inv_lambda + ramp;
-        wv -= floor(wv);
+        wv = __builtin_amdgcn_fract(wv);  // wv - floor(wv), one instruction
         // hardware sine and cosine take revolutions: exp(2 pi i wv) after the FP64 reduction
         const float fw = (float)wv;
         e = make_float2(__builtin_amdgcn_cosf(fw), __builtin_amdgcn_sinf(fw));

@@ -169,7 +169,7 @@ __global__ __launch_bounds__(64 * kWaves) void wfs_mfma_kernel(const WfsLaunch a
         const float r2 = ax * ax + ay * ay;
         if (r2 <= a.r2_outer && r2 >= a.r2_inner) {
           double wv = (double)src[(int64_t)prow * a.row_pitch + pcol] * a.inv_lambda;
-          wv -= floor(wv);
+          wv = __builtin_amdgcn_fract(wv);  // wv - floor(wv), one instruction
           float sn, cs;
           sincospif(2.0f * (float)wv, &sn, &cs);
           cr = cs;

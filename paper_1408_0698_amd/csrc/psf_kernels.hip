@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kLines * kP) void psf_rows_kernel(const PsfLaunch a
         const float r2 = bx * bx + by2;
         if (r2 <= a.r2_outer && r2 >= a.r2_inner) {
           double wv = (double)src[x] * a.inv_lambda + 0.5 * (double)(x + y);
-          wv -= floor(wv);
+          wv = __builtin_amdgcn_fract(wv);  // wv - floor(wv), one instruction
           // hardware sine and cosine take revolutions: exp(2 pi i wv) after the FP64 reduction
           const float fw = (float)wv;
           e = make_float2(__builtin_amdgcn_cosf(fw), __builtin_amdgcn_sinf(fw));

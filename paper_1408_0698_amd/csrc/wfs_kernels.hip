@@ -328,7 +328,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
         const double dx = (double)ax - lx;
         wv += qy + c_sub * dx * dx;
       }
-      wv -= floor(wv);
+      wv = __builtin_amdgcn_fract(wv);  // wv - floor(wv), one instruction
       // hardware sine/cosine take the argument in revolutions: exp(2 pi i wv) after the FP64 reduction
       const float fw = (float)wv;
       z[x] = make_float2(amp * __builtin_amdgcn_cosf(fw), amp * __builtin_amdgcn_sinf(fw));
