@@ -1092,7 +1092,7 @@ static hipError_t launch_one(int variant, const WfsLaunch& a, hipStream_t st) {
       case 12:
         if constexpr (band_limited_ok<NPX, FFT_N, CONV_N, LGS>()) {
           if (variant == 11) return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 5, true, true, false, true, true>(a, st);
-          return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 6, false, true, false, true, true>(a, st);
+          return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 7, false, true, false, true, true>(a, st);
         }
         return hipErrorInvalidValue;
       default: return hipErrorInvalidValue;
