@@ -1069,7 +1069,7 @@ static hipError_t launch_one(int variant, const WfsLaunch& a, hipStream_t st) {
       case 3:
       case 4:
         if constexpr (band_limited_ok<NPX, FFT_N, CONV_N, LGS>()) {
-          if (variant == 3) return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, false, true, true, true, true>(a, st);
+          if (variant == 3) return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 5, false, true, true, true, true>(a, st);
           return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 5, true, true, true, true, true>(a, st);
         }
         return hipErrorInvalidValue;
