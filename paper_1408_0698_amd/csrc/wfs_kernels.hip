@@ -603,13 +603,17 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
       using BP = BandRebinPairs<CONV_N, DET_N, NPX>;
       constexpr int G = BP::G;
       constexpr BP bm{};
+      // the lane index through an opaque move: the compiler recomputes these LDS addresses here
+      // instead of keeping the ones of the autocorrelation stores live across the row filter
+      int lb = l;
+      asm volatile("" : "+v"(lb));
       float zr[NPX], zi[NPX];
-      zr[0] = re[l];
+      zr[0] = re[lb];
       zi[0] = 0.0f;
 #pragma unroll
       for (int k = 1; k < NPX; ++k) {
-        zr[k] = re[k * ST + l];
-        zi[k] = im[k * ST + l];
+        zr[k] = re[k * ST + lb];
+        zi[k] = im[k * ST + lb];
       }
       float2 bs[2][G];
 #pragma unroll
@@ -723,7 +727,13 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
     sy += (double)((float)p - CD) * t;
   };
   float* det_area = im + DETA;
-  if constexpr (DSPLIT) det_area = a.det_ws + (it - a.item0) * NPIX;
+  if constexpr (DSPLIT) {
+    // it - item0 for the active lanes (the only ones that write), recomputed from the block's
+    // group and the item slot rather than kept live from the start of the kernel
+    int sd = s;
+    asm volatile("" : "+v"(sd));
+    det_area = a.det_ws + (group * SPB + sd) * NPIX;
+  }
   if (active && l < DET_N * G) {
     const int p = l / G;
     const int q0 = QB * (l - p * G);
