@@ -33,7 +33,7 @@ TRAFFIC = os.path.join(ROOT, "profiles", "wfs_measure_lgs39m_traffic.json")
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("wfs_kernels.hip", "regfft.h", "noise.h", "internal.h"):
+    for f in ("wfs_kernels.hip", "regfft.h", "noise.h", "internal.h", "band_rebin.h"):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
