@@ -246,8 +246,12 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   if (SUB && sl > 0) __syncthreads();  // the previous sub-layer's column pass has read the plane
   // ---------------------------------------------------------------- A: row pass
   if (active && l < FFT_N) {
-    const int y = l / R;
-    const int k2 = l - y * R;
+    // sub-layer kernels: the lane index passes through an opaque move in every sub-layer, so that
+    // the FP64 ramp terms of the row (rb + x rx) are recomputed there, not kept live across the loop
+    int lr = l;
+    if constexpr (SUB) asm volatile("" : "+v"(lr));
+    const int y = lr / R;
+    const int k2 = lr - y * R;
     const int prow = sa * NPX + y;
     const float* src = opd_f + (int64_t)w * wfs_stride + (int64_t)prow * row_pitch + (int64_t)sb * NPX;
     // sub-layer kernels: the column offset passes through an opaque move in every sub-layer, so
@@ -1008,7 +1012,7 @@ static hipError_t launch_one(int variant, const WfsLaunch& a, hipStream_t st) {
       case 4:
         if constexpr (band_limited_ok<NPX, FFT_N, CONV_N, LGS>()) {
           if (variant == 3) return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 5, false, true, true, true, true>(a, st);
-          return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 5, true, true, true, true, true>(a, st);
+          return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 6, true, true, true, true, true>(a, st);
         }
         return hipErrorInvalidValue;
       default: return hipErrorInvalidValue;
