@@ -883,7 +883,10 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
     sx = fmaf((float)q - CD, t, sx);
     sy = fmaf((float)p - CD, t, sy);
   };
-  const uint64_t below = (1ull << lane) - 1ull;
+  // set bits of a wavefront mask in the lanes below this one (the hardware's masked bit count)
+  auto below = [](uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  };
   int na = 0, nq = 0;
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
@@ -893,14 +896,14 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
     const uint64_t ma = __ballot(more[j]);
     const uint64_t mb = __ballot(big);
     if (more[j]) {
-      const int e = na + __popcll(ma & below);
+      const int e = na + below(ma);
       q_pix[wave][e] = pix;
       q_val[wave][0][e] = v[j];
       q_val[wave][1][e] = u[j];
       q_val[wave][2][e] = z[j];
       q_val[wave][3][e] = p0[j];
     } else if (big) {
-      const int e = NPIX - 1 - (nq + __popcll(mb & below));
+      const int e = NPIX - 1 - (nq + below(mb));
       q_pix[wave][e] = pix;
       q_val[wave][0][e] = v[j];
       q_val[wave][2][e] = z[j];
