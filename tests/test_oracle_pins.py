@@ -225,6 +225,115 @@ def test_elongation_geometry():
     assert abs(abs(psi[j]) - math.pi) < 0.01
 
 
+# ---------------------------------------------------------------- O4 plate scale, O5 widths in arcsec
+# The angular size of an FFT pixel is measured here from what a wavefront tilt does to the spot,
+# through the oracle's field formation and transform only; no plate-scale formula is used.  A plane
+# wave arriving at angle theta adds OPD = x sin(theta) across the pupil.  The spot of an n-sample
+# field zero-padded to N >= 2n is a trigonometric polynomial of degree < n in the pixel index, so a
+# tilt moves it by an exact, generally fractional, shift s, and its DFT along that axis at frequency
+# k takes the factor exp(-2 pi i k s / N).
+
+def _tilt_shift_px(cfg, theta_rad, axis, sel=(0, 1000, 2500, 4000)):
+    """Spot shift in FFT pixels caused by an OPD tilt of theta along x (axis 1) or y (axis 0)."""
+    vi, _ = G.subap_table(cfg)
+    vi = vi[list(sel)]
+    rng = np.random.default_rng(41)
+    base = rng.normal(0.0, 0.2 * cfg.wavelength_m, (cfg.pupil_n, cfg.pupil_n))
+    coord = (np.arange(cfg.pupil_n) + 0.5 - cfg.pupil_n / 2.0) * cfg.pupil_dx_m
+    tilt = np.sin(theta_rad) * (coord[None, :] if axis == 1 else coord[:, None])
+    N = cfg.fft_n
+    n = cfg.pupil_n // cfg.n_subap
+    I0 = O.spot_intensity(cfg, O.subap_fields(cfg, base, vi))
+    I1 = O.spot_intensity(cfg, O.subap_fields(cfg, base + tilt, vi))
+    F0 = np.fft.fft(I0, axis=1 + axis)
+    F1 = np.fft.fft(I1, axis=1 + axis)
+    k1 = (slice(None), slice(None), 1) if axis == 1 else (slice(None), 1, slice(None))
+    s = -np.angle(np.sum(F1[k1] * np.conj(F0[k1]))) * N / (2 * np.pi)
+    # the shift is exact at every in-band frequency, not only at k = 1
+    k = np.arange(N)
+    kk = np.where(k < N / 2, k, k - N)
+    ph = np.exp(-2j * np.pi * kk * s / N)
+    band = np.abs(kk) < n
+    shape = (1, 1, N) if axis == 1 else (1, N, 1)
+    want = F0 * ph.reshape(shape)
+    sl = (slice(None), slice(None), band) if axis == 1 else (slice(None), band, slice(None))
+    assert np.abs(F1[sl] - want[sl]).max() < 1e-9 * np.abs(F0).max()
+    return s
+
+
+@pytest.mark.parametrize("cfg_name", ["CFG0", "CFG1", "CFG1_R2"])
+@pytest.mark.parametrize("axis", [1, 0])
+def test_fft_pixel_angle_from_the_tilt_response(cfg_name, axis):
+    cfg = getattr(C, cfg_name).replace(lgs=0)
+    theta = 0.37 * G.ARCSEC
+    sel = (0, 30, 55, 79) if cfg.n_subap == 10 else (0, 1000, 2500, 4000)
+    s = _tilt_shift_px(cfg, theta, axis, sel)
+    assert s > 0  # a positive tilt moves the spot to larger pixel indices (reading O3)
+    assert abs(s * G.fft_pixel_rad(cfg) - theta) < 1e-9 * theta
+    assert abs(G.det_pixel_rad(cfg) / G.fft_pixel_rad(cfg) - cfg.conv_n / cfg.det_n) < 1e-15
+
+
+def _fwhm_arcsec_from_spectrum(khat_axis_1, N, px_rad):
+    """FWHM of a Gaussian kernel from its DFT at frequency 1 along one axis.
+
+    The DFT of the periodised samples of exp(-t^2 / 2 sigma^2) at integer frequency k is exactly the
+    continuous transform there, exp(-2 pi^2 sigma^2 k^2 / N^2), up to the aliasing of the sampling
+    (negligible for sigma >= 1 px); a Gaussian falls to half its peak at sigma sqrt(2 ln 2).
+    """
+    sigma_px = N * math.sqrt(-math.log(khat_axis_1) / 2.0) / math.pi
+    return 2.0 * sigma_px * math.sqrt(2.0 * math.log(2.0)) * px_rad / G.ARCSEC
+
+
+@pytest.mark.parametrize("frac", [1.0 / 3.0, 0.1, 0.55])
+def test_elongated_kernel_widths_in_arcsec(frac):
+    """The kernel of a sub-aperture at distance d from its launcher has FWHM sqrt((3'' d/D)^2 + 0.5''^2)
+    along the launcher direction and 0.5'' across it (reading O5), in angles measured by the tilt."""
+    cfg = C.CFG1
+    theta = 0.37 * G.ARCSEC
+    px = theta / _tilt_shift_px(cfg.replace(lgs=0), theta, 1)
+    vi, _ = G.subap_table(cfg)
+    i = 1234
+    n = cfg.pupil_n // cfg.n_subap
+    a, b = divmod(int(vi[i]), cfg.n_subap)
+    xc = ((b + 0.5) * n - cfg.pupil_n / 2.0) * cfg.pupil_dx_m
+    yc = ((a + 0.5) * n - cfg.pupil_n / 2.0) * cfg.pupil_dx_m
+    D = cfg.pupil_n * cfg.pupil_dx_m
+    d = frac * D
+    K = O.kernel_spectra(cfg, (xc - d, yc), vi[[i]])[0]   # launcher on the -x side: long axis along x
+    par = _fwhm_arcsec_from_spectrum(K[0, 1], cfg.conv_n, px)
+    perp = _fwhm_arcsec_from_spectrum(K[1, 0], cfg.conv_n, px)
+    assert abs(par - math.hypot(3.0 * frac, 0.5)) < 1e-6
+    assert abs(perp - 0.5) < 1e-6
+
+
+def test_geometric_elongation_law_in_arcsec():
+    """elong_max <= 0: the elongation is the sodium layer's depth seen from a distance d, d * dh / H^2."""
+    cfg = C.CFG1.replace(elong_max_arcsec=0.0)
+    theta = 0.37 * G.ARCSEC
+    px = theta / _tilt_shift_px(cfg.replace(lgs=0), theta, 0)
+    vi, _ = G.subap_table(cfg)
+    i = 777
+    n = cfg.pupil_n // cfg.n_subap
+    a, b = divmod(int(vi[i]), cfg.n_subap)
+    xc = ((b + 0.5) * n - cfg.pupil_n / 2.0) * cfg.pupil_dx_m
+    yc = ((a + 0.5) * n - cfg.pupil_n / 2.0) * cfg.pupil_dx_m
+    d = 3.0
+    K = O.kernel_spectra(cfg, (xc, yc - d), vi[[i]])[0]   # launcher on the -y side: long axis along y
+    el = d * 10e3 / 90e3 ** 2 / G.ARCSEC
+    assert abs(_fwhm_arcsec_from_spectrum(K[1, 0], cfg.conv_n, px) - math.hypot(el, 0.5)) < 1e-6
+    assert abs(_fwhm_arcsec_from_spectrum(K[0, 1], cfg.conv_n, px) - 0.5) < 1e-6
+
+
+def test_round_laser_spot_kernel_in_arcsec():
+    """The sub-layer form's kernel is the round 0.5'' laser spot, in angles measured by the tilt."""
+    cfg = C.CFG1
+    theta = 0.37 * G.ARCSEC
+    px = theta / _tilt_shift_px(cfg.replace(lgs=0), theta, 1)
+    K = O.round_kernel_spectrum(cfg)
+    for v in (K[0, 1], K[1, 0]):
+        assert abs(_fwhm_arcsec_from_spectrum(v, cfg.conv_n, px) - 0.5) < 1e-6
+
+
 # ---------------------------------------------------------------- O7 rebin
 
 @pytest.mark.parametrize("N,d", [(40, 16), (16, 8), (512, 16), (40, 40)])
@@ -302,10 +411,13 @@ def test_poisson_inversion_small_uniform_gives_zero():
 
 def test_inversion_matches_fp64_search_away_from_ties():
     rng = np.random.default_rng(3)
-    lam = rng.uniform(0.1, 9.9, 20000).astype(np.float32)
+    # the whole range the inversion serves: 0 < lambda < POISSON_SPLIT (= 20)
+    lam = rng.uniform(0.1, P.POISSON_SPLIT, 20000).astype(np.float32)
+    lam = np.minimum(lam, np.nextafter(np.float32(P.POISSON_SPLIT), np.float32(0)))
     u = P.uniform_f32(rng.integers(0, 2 ** 32, 20000, dtype=np.uint64).astype(np.uint32))
     k32 = P.poisson_inversion_f32(lam, u)
-    for l, uu, k in zip(lam[:3000], u[:3000], k32[:3000]):
+    assert (lam[:4000] >= 10.0).sum() > 1500
+    for l, uu, k in zip(lam[:4000], u[:4000], k32[:4000]):
         F, p, kk = math.exp(-float(l)), math.exp(-float(l)), 0
         while float(uu) > F:
             kk += 1
