@@ -21,13 +21,19 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # nominal FFT flops of one 40x40 complex 2-D transform: 5 N^2 log2(N^2); three per sub-aperture
-FLOP_PER_SUBAP = 3 * 5 * 40 * 40 * math.log2(40 * 40)
+# (the convention's count; the band-limited kernels execute fewer operations, see COUNTERS)
+FLOP_PER_SUBAP_NOMINAL = 3 * 5 * 40 * 40 * math.log2(40 * 40)
 PEAK_FP32_TFLOPS = 157.3
+# VALU issue capacity: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles, 2.4 GHz
+PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # launch variants of the 40-point shapes whose measurement is two kernels (fused stages up to the
 # detector, then noise and centroid); the roofline time covers both
 DETECTOR_SPLIT_VARIANTS = (6, 7, 8, 9, 10, 11, 12)
 CSRC = os.path.join(ROOT, "paper_1408_0698_amd", "csrc")
-TRAFFIC = os.path.join(ROOT, "profiles", "wfs_measure_lgs39m_traffic.json")
+# executed FLOPs (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_{F32,F64}), VALU instructions and HBM bytes
+# (FETCH_SIZE, WRITE_SIZE) per frame of the default launch variant, from rocprofv3 runs of this bench
+COUNTERS = os.path.join(ROOT, "profiles", "wfs_measure_lgs39m_counters.json")
+LATENCY_LAUNCHES = 200
 
 
 def kernel_source_hash():
@@ -39,18 +45,17 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(frames_per_launch):
-    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary, or None if the
-    kernel sources changed since the counters were taken."""
+def measured_counters(variant):
+    """Per-frame counter totals of the committed summary, or None if the kernel sources or the
+    launch variant differ from those the counters were taken with."""
     try:
-        with open(TRAFFIC) as fh:
+        with open(COUNTERS) as fh:
             t = json.load(fh)
     except OSError:
         return None
-    if t.get("kernel_source_hash") != kernel_source_hash():
+    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("launch_variant") != variant:
         return None
-    per_frame = (t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]) / t["frames_per_launch"]
-    return per_frame * frames_per_launch
+    return t
 
 
 def cpu_baseline(cfg, launch, opd, min_seconds=10.0):
@@ -546,8 +551,9 @@ def main():
     frames = args.steps * B
     value = frames / wall
     avg_launch_ms = e0.elapsed_time(e1) / args.steps
-    # per-launch latency percentiles, from a separate run with events around every launch
-    n_lat = min(args.steps, 100)
+    # per-launch latency percentiles, from a separate run of LATENCY_LAUNCHES launches with events
+    # around every launch
+    n_lat = LATENCY_LAUNCHES
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_lat)]
     for k in range(n_lat):
         ev[k][0].record(stream)
@@ -556,7 +562,32 @@ def main():
     torch.cuda.synchronize()
     lat = np.array([a.elapsed_time(b) for a, b in ev])      # ms per launch (B frames)
     subaps = 6 * plan.n_valid * B
-    achieved = FLOP_PER_SUBAP * subaps / (avg_launch_ms * 1e-3) / 1e12
+    launch_s = avg_launch_ms * 1e-3
+    nominal = FLOP_PER_SUBAP_NOMINAL * subaps / launch_s / 1e12
+    kernels = ("wfs_fused_kernel<10,40,40,16,lgs>"
+               + (" + det_noise_kernel<16>" if variant in DETECTOR_SPLIT_VARIANTS else ""))
+    ctr = measured_counters(variant)
+    if ctr is not None:
+        # executed FP32 FLOPs of both kernels (FMA = 2) per frame, from the committed counters
+        fp32 = ctr["fp32_flop_per_frame"] * B / launch_s / 1e12
+        roof = {"bound": "alu", "achieved": fp32, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": fp32 / PEAK_FP32_TFLOPS,
+                "traffic": ctr["hbm_bytes_per_frame"] * B,
+                "flops": "executed FP32 (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F32, FMA = 2) per frame, "
+                         "counters in profiles/wfs_measure_lgs39m.md",
+                "fp64_tflops": ctr["fp64_flop_per_frame"] * B / launch_s / 1e12,
+                "valu_issue_frac": ctr["valu_lane_ops_per_frame"] * B / launch_s / PEAK_VALU_LANE_OPS,
+                "nominal_tflops": nominal,
+                "nominal_note": "3 x 5 N^2 log2 N^2 per sub-aperture (three full 40x40 transforms); the "
+                                "band-limited kernels execute fewer operations",
+                "kernel": f"sh_wfs_measure launch variant {variant}: {kernels}",
+                "avg_launch_ms": avg_launch_ms}
+    else:
+        # kernels changed since the counters were taken: no executed count, nominal reported alone
+        roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": None,
+                "traffic": None, "nominal_tflops": nominal,
+                "kernel": f"sh_wfs_measure launch variant {variant}: {kernels}",
+                "avg_launch_ms": avg_launch_ms}
     out = {
         "metric": "SH-WFS frames/s (6 LGS, 80x80 subaps)",
         "value": value,
@@ -576,11 +607,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "per": f"launch of {B} frame(s), HIP events on the launch stream, {n_lat} launches "
                               f"after the timed region"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(B),
-                     "kernel": f"sh_wfs_measure launch variant {variant}: wfs_fused_kernel<10,40,40,16,lgs>"
-                               + (" + det_noise_kernel<16>" if variant in DETECTOR_SPLIT_VARIANTS else ""),
-                     "avg_launch_ms": avg_launch_ms},
+        "roofline": roof,
         "launch_variant": variant,
         "autotune_ms_per_variant": tuned["ms_per_launch"] if tuned else None,
     }
