@@ -348,6 +348,25 @@ int psf_encircled_energy(shw_psf_plan* plan, const float* d_psf, int32_t n_psf, 
                          const double* r_px, double* d_ee, void* hip_stream);
 
 /*
+ * psf_encircled_energy_noalloc - psf_encircled_energy for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, validation, result and
+ * bits as psf_encircled_energy, but the workspace is a static device array of
+ * 4 MiB (524,288 doubles) that the library holds on each GPU it runs on until
+ * the process ends, instead of the plan's workspace.  The call allocates and
+ * frees nothing and does not synchronise.  Limit: n_psf * 200 * (n_r + 1) <=
+ * 524,288 (e.g. 39 PSFs at 64 radii, 124 PSFs at 20 radii); larger requests
+ * return SHW_E_INVALID before any device work.  The first call on a device
+ * looks up the array's address there (that device must be current, as for
+ * every call on the plan).  All calls on one GPU share its array: calls that
+ * overlap on one GPU (two streams, or two threads) race and give undefined
+ * results; calls ordered on one stream do not.  Nothing carries over between
+ * calls: each call writes every workspace entry it reads.
+ */
+int psf_encircled_energy_noalloc(const shw_psf_plan* plan, const float* d_psf, int32_t n_psf, int64_t psf_stride,
+                                 int32_t n_r, const double* r_px, double* d_ee, void* hip_stream);
+
+/*
  * psf_resample_accumulate - put a PSF computed at wavelength lambda_i on the
  * angular grid of a reference wavelength lambda_ref (both M x M, on-axis at
  * pixel (M/2, M/2)) and add it with a weight (Sec. 3 PSF block: PSFs at

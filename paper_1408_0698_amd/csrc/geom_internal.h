@@ -68,6 +68,13 @@ struct EeLaunch {
 };
 hipError_t launch_encircled_energy(const EeLaunch& a, hipStream_t st);
 
+// Allocation-free form: the workspace is a file-scope device array of kEeScratchDoubles doubles
+// (4 MiB), one per GPU.  ee_scratch_device() returns its address on `device`, which must be the
+// current device; the first call per device looks the address up (hipGetSymbolAddress) and keeps it.
+constexpr size_t kEeScratchDoubles = (size_t)1 << 19;
+constexpr int kMaxDevices = 64;
+hipError_t ee_scratch_device(int device, double** out);
+
 // dst[v][u] += w * bilinear(src at (M/2 + (v - M/2) s, M/2 + (u - M/2) s)), zero outside src.
 hipError_t launch_psf_resample(const float* src, int32_t m, double s, float w, float* dst, hipStream_t st);
 

@@ -3,9 +3,16 @@
 // the object's colour; Strehl ratio and encircled energy in a chosen radius).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "geom_internal.h"
 
 namespace shw {
+
+// Workspace of the allocation-free encircled-energy entry point: one copy of this array per GPU,
+// held until the process ends.  In host code the name stands for a host-side shadow, not a device
+// address; kernels receive the address from ee_scratch_device() below.
+static __device__ __align__(256) double scratch[kEeScratchDoubles];
 
 // Largest integer w with w^2 <= q (q >= 0).
 __device__ __forceinline__ int isqrt_floor(double q) {
@@ -84,6 +91,22 @@ hipError_t launch_encircled_energy(const EeLaunch& a, hipStream_t st) {
   hipLaunchKernelGGL(ee_rows_kernel, dim3(kEeGroups, (unsigned)a.n_psf), dim3(256), 0, st, a);
   hipLaunchKernelGGL(ee_final_kernel, dim3((unsigned)a.n_psf), dim3(64), 0, st, a);
   return hipGetLastError();
+}
+
+hipError_t ee_scratch_device(int device, double** out) {
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    // the caller has made `device` current; each GPU holds its own copy at its own address
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = static_cast<double*>(p);
+  }
+  *out = addr[device];
+  return hipSuccess;
 }
 
 // dst[v][u] += w * src sampled bilinearly at (c + (v - c) s, c + (u - c) s), c = M/2; samples

@@ -1348,8 +1348,12 @@ extern "C" int shw_uplink_tilt(int32_t n_layers, const float* const* d_screen, c
   return ok();
 }
 
-extern "C" int psf_encircled_energy(shw_psf_plan* plan, const float* d_psf, int32_t n_psf, int64_t psf_stride,
-                                    int32_t n_r, const double* r_px, double* d_ee, void* stream) {
+// Validation and launch arguments shared by the two encircled-energy entry points.  Returns
+// SHW_OK with `a` filled (a.ws left for the caller), or an error; n_psf == 0 is SHW_OK with
+// a.n_psf == 0 and nothing to launch.
+static int ee_setup(const shw_psf_plan* plan, const float* d_psf, int32_t n_psf, int64_t psf_stride, int32_t n_r,
+                    const double* r_px, double* d_ee, EeLaunch& a) {
+  a = EeLaunch{};
   if (!plan) return fail(SHW_E_INVALID, "plan is NULL");
   const int M = plan->fft_m;
   if (M > 4096) return fail(SHW_E_UNSUPPORTED, "encircled energy supports fft_m <= 4096");
@@ -1358,7 +1362,6 @@ extern "C" int psf_encircled_energy(shw_psf_plan* plan, const float* d_psf, int3
   if (!d_psf || !r_px || !d_ee) return fail(SHW_E_INVALID, "NULL argument");
   if (n_psf > 1 && psf_stride < (int64_t)M * M) return fail(SHW_E_INVALID, "psf_stride < fft_m^2");
   if (n_r < 1 || n_r > kMaxRadii) return fail(SHW_E_INVALID, "n_r %d outside [1, %d]", n_r, kMaxRadii);
-  EeLaunch a{};
   for (int k = 0; k < n_r; ++k) {
     if (!(is_fin(r_px[k]) && r_px[k] >= 0)) return fail(SHW_E_INVALID, "radius %d must be finite and >= 0", k);
     a.r2[k] = r_px[k] * r_px[k];
@@ -1366,6 +1369,20 @@ extern "C" int psf_encircled_energy(shw_psf_plan* plan, const float* d_psf, int3
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != plan->device) return fail(SHW_E_INVALID, "the current device is not the plan's device");
+  a.psf = d_psf;
+  a.psf_stride = psf_stride;
+  a.m = M;
+  a.n_psf = n_psf;
+  a.n_r = n_r;
+  a.ee = d_ee;
+  return ok();
+}
+
+extern "C" int psf_encircled_energy(shw_psf_plan* plan, const float* d_psf, int32_t n_psf, int64_t psf_stride,
+                                    int32_t n_r, const double* r_px, double* d_ee, void* stream) {
+  EeLaunch a;
+  const int rc = ee_setup(plan, d_psf, n_psf, psf_stride, n_r, r_px, d_ee, a);
+  if (rc != SHW_OK || n_psf == 0) return rc;
   const size_t need = (size_t)n_psf * kEeGroups * (n_r + 1) * sizeof(double);
   if (need > plan->ee_bytes) {
     hipError_t he = hipDeviceSynchronize();
@@ -1377,15 +1394,28 @@ extern "C" int psf_encircled_energy(shw_psf_plan* plan, const float* d_psf, int3
     if (he != hipSuccess) return fail(SHW_E_NOMEM, "encircled-energy workspace of %zu bytes", need);
     plan->ee_bytes = need;
   }
-  a.psf = d_psf;
-  a.psf_stride = psf_stride;
-  a.m = M;
-  a.n_psf = n_psf;
-  a.n_r = n_r;
   a.ws = plan->d_ee_ws;
-  a.ee = d_ee;
   hipError_t he = launch_encircled_energy(a, (hipStream_t)stream);
   if (he != hipSuccess) return hip_fail(he, "encircled energy");
+  return ok();
+}
+
+extern "C" int psf_encircled_energy_noalloc(const shw_psf_plan* plan, const float* d_psf, int32_t n_psf,
+                                            int64_t psf_stride, int32_t n_r, const double* r_px, double* d_ee,
+                                            void* stream) {
+  EeLaunch a;
+  const int rc = ee_setup(plan, d_psf, n_psf, psf_stride, n_r, r_px, d_ee, a);
+  if (rc != SHW_OK || n_psf == 0) return rc;
+  const size_t need = (size_t)n_psf * kEeGroups * (n_r + 1);
+  if (need > kEeScratchDoubles)
+    return fail(SHW_E_INVALID, "n_psf * 200 * (n_r + 1) = %zu doubles exceeds the %zu of the static workspace",
+                need, kEeScratchDoubles);
+  // every workspace entry the final pass reads is written by the first pass of the same call, so
+  // nothing is cleared; what an earlier call left there is never read
+  hipError_t he = ee_scratch_device(plan->device, &a.ws);
+  if (he != hipSuccess) return hip_fail(he, "address of the static encircled-energy workspace");
+  he = launch_encircled_energy(a, (hipStream_t)stream);
+  if (he != hipSuccess) return hip_fail(he, "encircled energy (static workspace)");
   return ok();
 }
 

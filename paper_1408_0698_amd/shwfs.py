@@ -104,6 +104,8 @@ _sig = {
                                   C.POINTER(C.c_int64), C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                                   C.c_double, C.c_int32, _P, _P]),
     "psf_encircled_energy": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_int32, C.POINTER(C.c_double), _P, _P]),
+    "psf_encircled_energy_noalloc": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_int32, C.POINTER(C.c_double), _P,
+                                                 _P]),
     "psf_resample_accumulate": (C.c_int, [C.c_int32, _P, C.c_double, C.c_float, _P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
@@ -323,18 +325,26 @@ class PsfPlan:
         return acc
 
 
-    def encircled_energy(self, psf, radii_px, out=None, stream=None):
-        """psf: float32 device [M][M] or [S][M][M]; radii in pixels -> float64 device [S][n_r] (or [n_r])."""
+    def encircled_energy(self, psf, radii_px, out=None, stream=None, noalloc=False):
+        """psf: float32 device [M][M] or [S][M][M]; radii in pixels -> float64 device [S][n_r] (or [n_r]).
+        noalloc: call psf_encircled_energy_noalloc (static device workspace, no allocation; out must
+        then be given)."""
         import torch
         single = psf.dim() == 2
         p3 = psf.unsqueeze(0) if single else psf
         if p3.dim() != 3 or p3.shape[1:] != (self.fft_m, self.fft_m) or p3.stride(2) != 1 or p3.stride(1) != self.fft_m:
             raise ValueError("psf must be [S][M][M] with contiguous rows of the plan's size")
         r = (C.c_double * len(radii_px))(*[float(v) for v in radii_px])
+        if noalloc and out is None:
+            raise ValueError("noalloc needs an output tensor")
         if out is None:
             out = torch.empty((p3.shape[0], len(radii_px)), dtype=torch.float64, device=psf.device)
-        _check(_lib.psf_encircled_energy(self._h, _ptr(p3), p3.shape[0], p3.stride(0), len(radii_px), r, _ptr(out),
-                                         _stream_ptr(stream)), "psf_encircled_energy")
+        if (out.dtype != torch.float64 or not out.is_contiguous() or out.dim() != 2
+                or tuple(out.shape) != (p3.shape[0], len(radii_px))):
+            raise ValueError("out must be a contiguous float64 [S][n_r] tensor")
+        fn = _lib.psf_encircled_energy_noalloc if noalloc else _lib.psf_encircled_energy
+        _check(fn(self._h, _ptr(p3), p3.shape[0], p3.stride(0), len(radii_px), r, _ptr(out), _stream_ptr(stream)),
+               "psf_encircled_energy_noalloc" if noalloc else "psf_encircled_energy")
         return out[0] if single else out
 
 
