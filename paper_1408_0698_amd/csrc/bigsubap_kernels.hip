@@ -5,12 +5,18 @@
 // lane group: 400 x 400-pixel sub-apertures padded to 512 for the low-order
 // NGS sensors.  Three passes per batch of work items:
 //   rows  : field of one row (FP64 phase reduction, FP32 sincos, centring
-//           ramp folded in) -> 512-point transform -> T[item][y][u]
-//   cols  : 512-point transform of column u over the npx non-zero rows ->
-//           |F|^2 / N^2 -> rebin along the column -> Jr[item][p][u]
+//           ramp folded in) -> 512-point transform; 8 rows per block are
+//           transposed through LDS and stored column-major, T[item][u][y],
+//           so that each column's npx values are contiguous
+//   cols  : 512-point transform of column u over its npx non-zero rows (one
+//           contiguous read) -> |F|^2 / N^2 -> rebin along the column ->
+//           Jr[item][u][p], the det_n values of a column contiguous
 //   detect: rebin along the row, photometry, noise, threshold, FP64 centroid
-// The 512-point transform is a Stockham autosort radix-8 FFT (three passes
-// with strides 1, 8, 64) on 64 lanes, ping-ponging between two LDS buffers.
+// Every 512-point transform runs inside one wavefront: with n = j + 64 i
+// and k = k1 + 8 k2, lane j first transforms its 8 samples over i, then
+// multiplies by W_512^(j k1); the 64-point transforms over j that remain
+// (one per k1) split again as 8 x 8, through two LDS transposes within the
+// wavefront.  Lane L ends with X[L + 64 b], b = 0..7.
 #include <hip/hip_runtime.h>
 
 #include "big_internal.h"
@@ -22,68 +28,54 @@ namespace shw {
 namespace {
 
 constexpr int kN = 512;
-constexpr int kLanes = 64;           // lanes per transform
-constexpr int kLines = 8;            // transforms per block
-constexpr int kBlock = kLines * kLanes;
+constexpr int kRowWaves = 8;         // rows per block of the row pass (one wavefront each), a power of two
+constexpr int kColWaves = 4;         // columns per block of the column pass
+// LDS strides of the in-wave transposes, in complex values.  First transpose: [k1][j] with row
+// stride 72; second: [h][k2a][g] with g contiguous, k2a stride 8 and h stride 66.  With these, the
+// 16 lanes served together by a 64-bit LDS access touch 16 different bank pairs in every read
+// and write of the transform.
+constexpr int kS1 = 72;
+constexpr int kS4 = 66;
+constexpr int kWaveArea = 8 * kS1;   // complex values per wavefront (>= 8 * kS4)
+static_assert(8 * kS4 <= kWaveArea, "second transpose fits the wavefront's area");
+constexpr int kTileStride = kRowWaves + 1;  // row pass: [u][row] tile, odd stride
 
-struct Line {
-  float* are;
-  float* aim;
-  float* bre;
-  float* bim;
-};
+// W_512^m, m < 512, rounded to FP32 from FP64 values at compile time
+__constant__ const TwiddleTable<kN> kTw{};
 
-// One 512-point forward transform.  On entry lane j holds v[i] = x[j + 64 i];
-// on return the result is in the b planes in natural order.  All kBlock
-// lanes of the block must call this (it contains block barriers).
-__device__ __forceinline__ void fft512(Line ln, const float2* __restrict__ tw, int j, float2* v) {
-  // pass 0 (Ns = 1): no twiddle
-  RegFFT<8, -1>::run(v);
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    ln.bre[j * 8 + i] = v[i].x;
-    ln.bim[j * 8 + i] = v[i].y;
-  }
-  __syncthreads();
-  // pass 1 (Ns = 8): b -> a
-  {
-    const int k = j & 7;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = make_float2(ln.bre[j + 64 * i], ln.bim[j + 64 * i]);
-#pragma unroll
-    for (int i = 1; i < 8; ++i) v[i] = cmul(v[i], tw[(i * k * 8) & (kN - 1)]);
-    RegFFT<8, -1>::run(v);
-    const int d = (j >> 3) * 64 + k;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      ln.are[d + 8 * i] = v[i].x;
-      ln.aim[d + 8 * i] = v[i].y;
-    }
-  }
-  __syncthreads();
-  // pass 2 (Ns = 64): a -> b
-  {
-    const int k = j;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = make_float2(ln.are[j + 64 * i], ln.aim[j + 64 * i]);
-#pragma unroll
-    for (int i = 1; i < 8; ++i) v[i] = cmul(v[i], tw[(i * k) & (kN - 1)]);
-    RegFFT<8, -1>::run(v);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      ln.bre[k + 64 * i] = v[i].x;
-      ln.bim[k + 64 * i] = v[i].y;
-    }
-  }
-  __syncthreads();
+__device__ __forceinline__ void fill_twiddles(float2* tw, int tid, int nthreads) {
+  for (int m = tid; m < kN; m += nthreads) tw[m] = make_float2(kTw.c[m], -kTw.s[m]);
 }
 
-__device__ __forceinline__ void fill_twiddles(float2* tw) {
-  for (int m = threadIdx.x; m < kN; m += kBlock) {
-    float s, c;
-    sincospif(-2.0f * (float)m / (float)kN, &s, &c);
-    tw[m] = make_float2(c, s);
-  }
+// One forward 512-point transform in one wavefront.  On entry lane j holds v[i] = x[j + 64 i];
+// on return lane j holds v[b] = X[j + 64 b].  area: the wavefront's kWaveArea complex values;
+// tw: W_512^m, m < 512.  Every lane of the block must call it (block barriers).
+__device__ __forceinline__ void fft512_wave(float2 (&v)[8], float2* area, const float2* tw, int j) {
+  // over i: 8-point transforms, then the twiddle W_512^(j k1)
+  RegFFT<8, -1>::run(v);
+#pragma unroll
+  for (int k1 = 1; k1 < 8; ++k1) v[k1] = cmul(v[k1], tw[j * k1]);
+#pragma unroll
+  for (int k1 = 0; k1 < 8; ++k1) area[k1 * kS1 + j] = v[k1];
+  __syncthreads();
+  // lane (g, h) = (j >> 3, j & 7): samples y[h + 8 m] of the 64-point transform of k1 = g
+  const int g = j >> 3, h = j & 7;
+  float2 w[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) w[m] = area[g * kS1 + h + 8 * m];
+  RegFFT<8, -1>::run(w);
+#pragma unroll
+  for (int a = 1; a < 8; ++a) w[a] = cmul(w[a], tw[8 * h * a]);  // W_64^(h a)
+  __syncthreads();  // every lane has read the first transpose
+#pragma unroll
+  for (int a = 0; a < 8; ++a) area[h * kS4 + a * 8 + g] = w[a];
+  __syncthreads();
+  // lane (a, g') = (j >> 3, j & 7): the 8-point transform over h of k1 = g', k2a = a gives
+  // X[g' + 8 a + 64 b] = X[j + 64 b]
+  const int a2 = j >> 3, g2 = j & 7;
+#pragma unroll
+  for (int hh = 0; hh < 8; ++hh) v[hh] = area[hh * kS4 + a2 * 8 + g2];
+  RegFFT<8, -1>::run(v);
 }
 
 __device__ __forceinline__ void item_coords(const BigLaunch& a, int64_t item, int& f, int& w, int& i) {
@@ -96,14 +88,20 @@ __device__ __forceinline__ void item_coords(const BigLaunch& a, int64_t item, in
 
 }  // namespace
 
-// Line r of the launch = row y of item item0 + r / npx.
-__global__ __launch_bounds__(kBlock) void big_rows_kernel(const BigLaunch a, int64_t item0, int64_t nlines,
-                                                          float2* __restrict__ T) {
-  __shared__ float s_pl[kLines * 4 * kN];
+// Row r of the launch = row y = r % npx of item item0 + r / npx; wavefront t of block b takes
+// row 16 b + t.  T[(il * 512 + u) * npx + y] = X_y[u].
+__global__ __launch_bounds__(kRowWaves * 64) void big_rows_kernel(const BigLaunch a, int64_t item0, int64_t nlines,
+                                                                  float2* __restrict__ T) {
+  // the wavefronts' transform areas, later reused as the [u][row] tile of the block
+  constexpr int kAreas = kRowWaves * kWaveArea;
+  constexpr int kTile = kN * kTileStride;
+  __shared__ float2 s_buf[kAreas > kTile ? kAreas : kTile];
   __shared__ float2 s_tw[kN];
-  fill_twiddles(s_tw);
-  const int line = threadIdx.x / kLanes, j = threadIdx.x % kLanes;
-  const int64_t r = (int64_t)blockIdx.x * kLines + line;
+  const int tid = threadIdx.x;
+  fill_twiddles(s_tw, tid, kRowWaves * 64);
+  // the wavefront index is uniform: through readfirstlane the row's item arithmetic is scalar
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), j = tid & 63;
+  const int64_t r = (int64_t)blockIdx.x * kRowWaves + wv;
   const bool active = r < nlines;
   const int64_t rr = active ? r : 0;
   const int64_t il = rr / a.npx;
@@ -111,140 +109,197 @@ __global__ __launch_bounds__(kBlock) void big_rows_kernel(const BigLaunch a, int
   int f, w, i;
   item_coords(a, item0 + il, f, w, i);
   const int sidx = a.valid_idx[i];
-  const int sa = sidx / a.n_subap, sb = sidx - (sidx / a.n_subap) * a.n_subap;
+  const int sa = sidx / a.n_subap, sb = sidx - sa * a.n_subap;
   const int prow = sa * a.npx + y;
   const float* src = a.list ? a.list[f].opd + (int64_t)w * a.list[f].wfs_stride + (int64_t)prow * a.list[f].row_pitch
                             : a.opd + (int64_t)f * a.frame_stride + (int64_t)w * a.wfs_stride +
                                   (int64_t)prow * a.row_pitch;
   src += (int64_t)sb * a.npx;
+  // every sample of the row is loaded before any is used, unlit ones masked by amplitude
+  float ov[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int x = j + 64 * q;
+    ov[q] = (active && x < a.npx) ? src[x] : 0.0f;
+  }
   const float ay = (float)prow + 0.5f - a.half_n;
+  const float ay2 = ay * ay;
   float2 v[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int x = j + 64 * q;
-    float2 e = make_float2(0.0f, 0.0f);
-    if (active && x < a.npx) {
-      const float ax = (float)(sb * a.npx + x) + 0.5f - a.half_n;
-      const float r2 = ax * ax + ay * ay;
-      if (r2 <= a.r2_outer && r2 >= a.r2_inner) {
-        const double ramp = (double)((kN - 1) * (x + y)) / (2.0 * kN);
-        double wv = (double)src[x] * a.inv_lambda + ramp;
-        wv = __builtin_amdgcn_fract(wv);  // wv - floor(wv), one instruction
-        // hardware sine and cosine take revolutions: exp(2 pi i wv) after the FP64 reduction
-        const float fw = (float)wv;
-        e = make_float2(__builtin_amdgcn_cosf(fw), __builtin_amdgcn_sinf(fw));
-      }
-    }
-    v[q] = e;
+    const float ax = (float)(sb * a.npx + x) + 0.5f - a.half_n;
+    const float r2 = ax * ax + ay2;
+    const bool lit = active && x < a.npx && r2 <= a.r2_outer && r2 >= a.r2_inner;
+    // waves: OPD / lambda + centring ramp (N - 1)(x + y) / (2 N), exact in FP64
+    double wvs = (double)ov[q] * a.inv_lambda + (double)((kN - 1) * (x + y)) * (1.0 / (2.0 * kN));
+    wvs = __builtin_amdgcn_fract(wvs);  // wvs - floor(wvs), one instruction
+    // hardware sine and cosine take revolutions: exp(2 pi i wvs) after the FP64 reduction
+    const float fw = (float)wvs;
+    const float amp = lit ? 1.0f : 0.0f;
+    v[q] = make_float2(amp * __builtin_amdgcn_cosf(fw), amp * __builtin_amdgcn_sinf(fw));
   }
   __syncthreads();  // twiddles ready
-  float* base = s_pl + line * 4 * kN;
-  Line ln{base, base + kN, base + 2 * kN, base + 3 * kN};
-  fft512(ln, s_tw, j, v);
-  if (active) {
-    float2* dst = T + rr * kN;
+  fft512_wave(v, s_buf + wv * kWaveArea, s_tw, j);
+  __syncthreads();  // every wavefront has read its area: the tile overwrites them
 #pragma unroll
-    for (int q = 0; q < 8; ++q) dst[j + 64 * q] = make_float2(ln.bre[j + 64 * q], ln.bim[j + 64 * q]);
+  for (int b = 0; b < 8; ++b) s_buf[(j + 64 * b) * kTileStride + wv] = v[b];
+  __syncthreads();
+  // write-out: kRowWaves consecutive threads store the block's rows of one column u, contiguous in
+  // T when the rows belong to one item.  Thread tid always takes row t = tid % kRowWaves (the
+  // block's thread count is a multiple of kRowWaves) and columns u = tid / kRowWaves + 64 k.
+  const int t = tid & (kRowWaves - 1);
+  const int64_t r0 = (int64_t)blockIdx.x * kRowWaves;
+  const int64_t row = r0 + t;
+  if (row < nlines) {
+    // item and row of row r0 + t from those of r0 (uniform): at most kRowWaves steps when npx is small
+    const int64_t il0 = r0 / a.npx;
+    int64_t ilt = il0;
+    int yt = (int)(r0 - il0 * a.npx) + t;
+    while (yt >= a.npx) {
+      yt -= a.npx;
+      ++ilt;
+    }
+    float2* dst = T + ilt * kN * a.npx + yt;
+    const int u0 = tid / kRowWaves;
+#pragma unroll
+    for (int k = 0; k < kN / 64; ++k) {
+      const int u = u0 + 64 * k;
+      dst[(int64_t)u * a.npx] = s_buf[u * kTileStride + t];
+    }
   }
 }
 
-// Line c of the launch = column u = c % 512 of item item0 + c / 512.  Lanes are
-// interleaved (line = t % 8) so that a wave reads 8 adjacent columns per row.
-__global__ __launch_bounds__(kBlock) void big_cols_kernel(const BigLaunch a, int64_t nitems,
-                                                          const float2* __restrict__ T, float* __restrict__ Jr) {
-  __shared__ float s_pl[kLines * 4 * kN];
-  __shared__ float2 s_tw[kN];
-  fill_twiddles(s_tw);
-  const int line = threadIdx.x % kLines, j = threadIdx.x / kLines;
-  const int64_t c = (int64_t)blockIdx.x * kLines + line;
-  const bool active = c < nitems * kN;
-  const int64_t cc = active ? c : 0;
-  const int64_t il = cc / kN;
-  const int u = (int)(cc - il * kN);
-  const float2* src = T + il * a.npx * kN + u;
-  float2 v[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int y = j + 64 * q;
-    v[q] = (active && y < a.npx) ? src[(int64_t)y * kN] : make_float2(0.0f, 0.0f);
-  }
-  __syncthreads();
-  float* base = s_pl + line * 4 * kN;
-  Line ln{base, base + kN, base + 2 * kN, base + 3 * kN};
-  fft512(ln, s_tw, j, v);
-  // intensity into the a plane, then rebin along the column: b = 512 / det_n rows per pixel
-  const float inv_n2 = 1.0f / ((float)kN * (float)kN);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int vv = j + 64 * q;
-    const float re = ln.bre[vv], im = ln.bim[vv];
-    ln.are[vv] = (re * re + im * im) * inv_n2;
-  }
-  __syncthreads();
-  if (active && j < a.det_n) {
-    const int b = kN / a.det_n;
-    float s = 0.0f;
-    for (int k = 0; k < b; ++k) s += ln.are[j * b + k];
-    Jr[(il * a.det_n + j) * kN + u] = s;
-  }
-}
-
-// One block per work item: detector pixel = row-rebinned sum, photometry, noise, centroid.
-__global__ __launch_bounds__(256) void big_detect_kernel(const BigLaunch a, int64_t item0,
-                                                         const float* __restrict__ Jr) {
-  __shared__ double red[3][256];
-  const int64_t il = blockIdx.x;
+// Detector of item item0 + il: rebin along the row (b = 512 / det_n columns per pixel), photometry,
+// noise, threshold, FP64 centroid.  All 256 threads of the calling block take part (barriers);
+// red: 3 * 256 doubles of LDS.
+__device__ __forceinline__ void detect_item(const BigLaunch& a, int64_t item0, int64_t il, const float* Jr, int tid,
+                                            double (*red)[256]) {
   const int64_t item = item0 + il;
   int f, w, i;
   item_coords(a, item, f, w, i);
-  const int npix = a.det_n * a.det_n;
-  const int b = kN / a.det_n;
-  const float cd = 0.5f * (float)(a.det_n - 1);
+  const int dn = a.det_n;
+  const int npix = dn * dn;
+  const int b = kN / dn;
+  const float cd = 0.5f * (float)(dn - 1);
   const uint32_t gsub = (uint32_t)(w * a.n_valid + i);
   uint32_t frame = a.frame0 + (uint32_t)f, key0 = a.key0, key1 = a.key1;
   float* slopes_fw = a.slopes + ((int64_t)f * a.n_wfs + w) * 2 * a.n_valid;
-  float* images_it = a.images ? a.images + item * (int64_t)(a.det_n * a.det_n) : nullptr;
+  float* images_it = a.images ? a.images + item * (int64_t)npix : nullptr;
   if (a.list) {
     const FrameWork& fw = a.list[f];
     frame = (uint32_t)fw.frame;
     key0 = (uint32_t)(fw.seed & 0xFFFFFFFFu);
     key1 = (uint32_t)(fw.seed >> 32);
     slopes_fw = fw.slopes + (int64_t)w * 2 * a.n_valid;
-    images_it = fw.images ? fw.images + ((int64_t)w * a.n_valid + i) * (a.det_n * a.det_n) : nullptr;
+    images_it = fw.images ? fw.images + ((int64_t)w * a.n_valid + i) * npix : nullptr;
   }
+  const float* jr = Jr + il * kN * dn;
   double s0 = 0.0, sx = 0.0, sy = 0.0;
-  for (int pix = threadIdx.x; pix < npix; pix += 256) {
-    const int p = pix / a.det_n, q = pix - p * a.det_n;
-    const float* row = Jr + (il * a.det_n + p) * kN + q * b;
+  // thread t takes pixel (p, q) = (t % det_n, t / det_n): consecutive threads read consecutive p
+  for (int t = tid; t < npix; t += 256) {
+    const int q = t / dn, p = t - q * dn;
+    const int pix = p * dn + q;
+    const float* col = jr + (int64_t)q * b * dn + p;
+    // b = 512 / det_n is a power of two: for b >= 8, eight loads in flight per step (partial sums
+    // in a fixed order), not one load per dependent addition
     float det = 0.0f;
-    for (int k = 0; k < b; ++k) det += row[k];
+    if (b >= 8) {
+      float ps[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+      for (int k0 = 0; k0 < b; k0 += 8) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) ps[r] += col[(k0 + r) * dn];
+      }
+      det = ((ps[0] + ps[1]) + (ps[2] + ps[3])) + ((ps[4] + ps[5]) + (ps[6] + ps[7]));
+    } else {
+      for (int k = 0; k < b; ++k) det += col[k * dn];
+    }
     float img = det;
     if (a.ph_scale > 0.0f) {
       const float lam = a.ph_scale * det;
       img = a.noise ? noisy_pixel(lam, a.ron, (uint32_t)pix, (uint32_t)npix, gsub, frame, key0, key1) : lam;
     }
     if (images_it) images_it[pix] = img;
-    const double t = (double)fmaxf(img - a.thr, 0.0f);
-    s0 += t;
-    sx += (double)((float)q - cd) * t;
-    sy += (double)((float)p - cd) * t;
+    const double tt = (double)fmaxf(img - a.thr, 0.0f);
+    s0 += tt;
+    sx += (double)((float)q - cd) * tt;
+    sy += (double)((float)p - cd) * tt;
   }
-  red[0][threadIdx.x] = s0;
-  red[1][threadIdx.x] = sx;
-  red[2][threadIdx.x] = sy;
+  red[0][tid] = s0;
+  red[1][tid] = sx;
+  red[2][tid] = sy;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st)
-      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
+    if (tid < st)
+      for (int c = 0; c < 3; ++c) red[c][tid] += red[c][tid + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     const double t0 = red[0][0];
     const bool empty = !(t0 > 0.0);
     slopes_fw[i] = empty ? 0.0f : (float)(red[1][0] / t0);
     slopes_fw[a.n_valid + i] = empty ? 0.0f : (float)(red[2][0] / t0);
     if (a.flags && !a.list) a.flags[item] = empty ? 1 : 0;
   }
+}
+
+// Column c of the launch = column u = c % 512 of item c / 512, one wavefront each:
+// Jr[(il * 512 + u) * det_n + p] = sum over the b = 512 / det_n rows v of pixel p of |X_u[v]|^2 / N^2.
+__global__ __launch_bounds__(kColWaves * 64) void big_cols_kernel(const BigLaunch a, int64_t nitems,
+                                                                  const float2* __restrict__ T, float* __restrict__ Jr) {
+  __shared__ __align__(16) float2 s_area[kColWaves * kWaveArea];  // 16-byte reads in the rebin
+  __shared__ float2 s_tw[kN];
+  const int tid = threadIdx.x;
+  fill_twiddles(s_tw, tid, kColWaves * 64);
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), j = tid & 63;
+  const int64_t c = (int64_t)blockIdx.x * kColWaves + wv;
+  const bool active = c < nitems * kN;
+  const int64_t cc = active ? c : 0;
+  const int64_t il = cc / kN;
+  const int u = (int)(cc - il * kN);
+  const float2* src = T + (il * kN + u) * a.npx;
+  float2 v[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int y = j + 64 * q;
+    v[q] = (active && y < a.npx) ? src[y] : make_float2(0.0f, 0.0f);
+  }
+  __syncthreads();  // twiddles ready
+  float2* area = s_area + wv * kWaveArea;
+  fft512_wave(v, area, s_tw, j);
+  // intensity of row v = j + 64 b into the wavefront's area (as floats), then the column rebin
+  const float inv_n2 = 1.0f / ((float)kN * (float)kN);
+  float* ia = reinterpret_cast<float*>(area);
+  __syncthreads();  // every lane has read the second transpose
+#pragma unroll
+  for (int b = 0; b < 8; ++b) ia[j + 64 * b] = (v[b].x * v[b].x + v[b].y * v[b].y) * inv_n2;
+  __syncthreads();
+  if (active) {
+    const int bsz = kN / a.det_n;  // rows per detector pixel, a power of two
+    if (bsz >= 8) {
+      // lane j sums rows 8j .. 8j+7 (two 16-byte reads), then groups of bsz / 8 lanes add up by
+      // butterflies; the group's first lane holds pixel p = 8 j / bsz
+      const float4 q0 = reinterpret_cast<const float4*>(ia)[2 * j];
+      const float4 q1 = reinterpret_cast<const float4*>(ia)[2 * j + 1];
+      float sum = ((q0.x + q0.y) + (q0.z + q0.w)) + ((q1.x + q1.y) + (q1.z + q1.w));
+      const int gl = bsz >> 3;  // lanes per pixel, <= 64
+      for (int off = 1; off < gl; off <<= 1) sum += __shfl_xor(sum, off, 64);
+      if ((j & (gl - 1)) == 0) Jr[(il * kN + u) * a.det_n + j / gl] = sum;
+    } else {
+      for (int p = j; p < a.det_n; p += 64) {
+        float sum = 0.0f;
+        for (int k = 0; k < bsz; ++k) sum += ia[p * bsz + k];
+        Jr[(il * kN + u) * a.det_n + p] = sum;
+      }
+    }
+  }
+}
+
+// One block per work item: the detector stage.
+__global__ __launch_bounds__(256) void big_detect_kernel(const BigLaunch a, int64_t item0,
+                                                         const float* __restrict__ Jr) {
+  __shared__ double red[3][256];
+  detect_item(a, item0, blockIdx.x, Jr, threadIdx.x, red);
 }
 
 bool big_shape_supported(int npx, int fft_n, int conv_n, int det_n, int lgs) {
@@ -255,13 +310,13 @@ bool big_shape_supported(int npx, int fft_n, int conv_n, int det_n, int lgs) {
 hipError_t launch_big(const BigLaunch& a, int64_t item0, int64_t nitems, float2* T, float* Jr, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
   const int64_t rows = nitems * a.npx;
-  hipLaunchKernelGGL(big_rows_kernel, dim3((unsigned)((rows + kLines - 1) / kLines)), dim3(kBlock), 0, st, a, item0,
-                     rows, T);
+  hipLaunchKernelGGL(big_rows_kernel, dim3((unsigned)((rows + kRowWaves - 1) / kRowWaves)), dim3(kRowWaves * 64), 0,
+                     st, a, item0, rows, T);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t cols = nitems * kN;
-  hipLaunchKernelGGL(big_cols_kernel, dim3((unsigned)((cols + kLines - 1) / kLines)), dim3(kBlock), 0, st, a, nitems,
-                     (const float2*)T, Jr);
+  hipLaunchKernelGGL(big_cols_kernel, dim3((unsigned)((cols + kColWaves - 1) / kColWaves)), dim3(kColWaves * 64), 0,
+                     st, a, nitems, (const float2*)T, Jr);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(big_detect_kernel, dim3((unsigned)nitems), dim3(256), 0, st, a, item0, (const float*)Jr);
