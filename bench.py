@@ -373,9 +373,7 @@ def extras(stream, which=EXTRAS):
     out = {}
     for name in which:
         if name == "served":
-            out["served"] = served()
-            out["served_load_sweep"] = [served(rate_hz=r, duration_s=1.0, warm=False)
-                                        for r in (4000.0, 8000.0, 16000.0)]
+            out["served"], out["served_load_sweep"], out["served_knee_req_per_s"] = served()
         else:
             out.update(fns[name](stream))
         torch.cuda.synchronize()
@@ -452,26 +450,50 @@ def closed_loop(stream):
     return out
 
 
-def served(rate_hz=2000.0, duration_s=3.0, warm=True):
-    """Served mix: Poisson arrivals at rate_hz, 70% 8 m frames and 30% 39 m frames (6 LGS + 3 NGS)
-    over 12 instances (8 small, 4 large), continuous batching under a 4 GB instance-and-staging
-    budget (plans are counted on top); p50/p99 arrival -> slopes-ready latency."""
-    from paper_1408_0698_amd.serve import GpuExecutor, Server, latency_report, make_mix
-    ex = GpuExecutor()
-    budget = ex.shared_bytes() + (4 << 30)
-    if warm:
-        warm_inst, warm_reqs = make_mix(rate_hz=rate_hz, duration_s=0.3, seed=1)
-        w = Server(ex, warm_inst, budget)
-        w.warm()
-        w.run(warm_reqs, timeout=120)
-    instances, reqs = make_mix(rate_hz=rate_hz, duration_s=duration_s, seed=2000)
+def _binding_budget(ex):
+    """HBM budget of the served runs: the shared plans, 3 of the 4 large instances and all 8 small
+    ones resident, 3 large and 16 small staging slots.  A request for the large instance that is
+    not resident waits for HBM and evicts an idle one."""
+    return (ex.shared_bytes() + 3 * ex.instance_bytes("39m") + 8 * ex.instance_bytes("8m")
+            + 3 * ex.slot_bytes("39m") + 16 * ex.slot_bytes("8m"))
+
+
+def _served_run(ex, budget, rate_hz, duration_s, warm_s, seed):
+    from paper_1408_0698_amd.serve import Server, latency_report, make_mix
+    instances, reqs = make_mix(rate_hz=rate_hz, duration_s=warm_s + duration_s, seed=seed)
     srv = Server(ex, instances, budget)
     srv.warm()
-    out = srv.run(reqs, timeout=300)
-    rep = latency_report(out)
-    rep.update({"offered_req_per_s": rate_hz, "duration_s": duration_s, "requests": len(reqs),
-                "launches": srv.launches, "max_hbm_used_bytes": srv.max_used, "budget_bytes": budget})
+    ev0 = dict(ex.stats)
+    out = srv.run(reqs, timeout=600)
+    rep = latency_report([r for r in out if r.arrival >= warm_s])
+    print(f"served: {rate_hz:.0f} req/s for {warm_s + duration_s:.2f} s: {rep.get('completed')} completed, "
+          f"p99 {rep.get('p99_ms', float('nan')):.3f} ms, {srv.evictions} evictions", file=sys.stderr, flush=True)
+    rep.update({"offered_req_per_s": rate_hz, "duration_s": duration_s, "warmup_s": warm_s,
+                "requests": sum(r.arrival >= warm_s for r in reqs), "launches": srv.launches,
+                "max_inflight_batches": srv.max_inflight, "evictions": srv.evictions,
+                "restores": ex.stats["restored"] - ev0["restored"], "max_hbm_used_bytes": srv.max_used,
+                "budget_bytes": budget})
     return rep
+
+
+def served(duration_s=30.0, warm_s=2.0):
+    """Served mix: Poisson arrivals at 2000 req/s, 70% 8 m frames and 30% 39 m frames (6 LGS + 3 NGS)
+    over 12 instances (8 small, 4 large), continuous batching under a binding HBM budget; 30 s
+    measured after 2 s of warm-up, p50/p99 arrival -> slopes-ready latency; then a load sweep (1 s
+    per rate after 0.25 s of warm-up) up to saturation."""
+    from paper_1408_0698_amd.serve import GpuExecutor
+    ex = GpuExecutor()
+    budget = _binding_budget(ex)
+    main = _served_run(ex, budget, 2000.0, duration_s, warm_s, seed=2000)
+    sweep, knee = [], None
+    for rate in (2000.0, 4000.0, 8000.0, 16000.0, 24000.0, 32000.0, 48000.0, 64000.0):
+        rep = _served_run(ex, budget, rate, 1.0, 0.25, seed=int(rate) + 1)
+        sweep.append(rep)
+        if rep["frames_per_s"] >= 0.95 * rate:
+            knee = rate
+        else:
+            break              # saturated: completed rate below the offered rate
+    return main, sweep, knee
 
 
 def main():

@@ -237,7 +237,13 @@ typedef struct shw_work {
  * sh_wfs_measure_batch - n work items of possibly different plans in as few
  * launches as the plan geometries allow (one per distinct kernel shape).
  * Each item's result is identical to sh_wfs_measure on that item alone.
- * Items must not share output buffers.  Asynchronous on hip_stream.
+ * Items must not share output buffers.  Asynchronous on hip_stream: each
+ * plan's work list is staged in a pinned host ring of 4 slots and uploaded
+ * asynchronously, so the call returns without waiting for earlier work on
+ * the stream (it waits only when a slot's upload from 4 calls earlier has
+ * not run yet).  A plan's batches must all go to one stream.  The first call
+ * with more than 256 frames of a plan (or more than any earlier call) grows
+ * the plan's list: that call synchronises hip_stream and allocates.
  */
 int sh_wfs_measure_batch(const shw_work* items, int32_t n, void* hip_stream);
 

@@ -55,6 +55,8 @@ bool is_fin(double v) { return std::isfinite(v); }
 
 }  // namespace
 
+constexpr int kListRing = 4;  // host staging slots of the work lists
+
 struct shw_wfs_plan {
   shw_wfs_config cfg;
   int32_t n_wfs = 0;
@@ -71,6 +73,12 @@ struct shw_wfs_plan {
   uint2* d_mfma_tab = nullptr;   // constant matrices of the MFMA variant
   FrameWork* d_list = nullptr;   // work list of sh_wfs_measure_batch
   int32_t list_cap = 0;
+  // pinned host staging of the work lists: kListRing slots of list_cap entries, each reusable once
+  // the event recorded after its upload has completed
+  FrameWork* h_ring = nullptr;
+  hipEvent_t ring_ev[kListRing] = {};
+  bool ring_pending[kListRing] = {};
+  int32_t ring_next = 0;
   // large sub-apertures (FFT 512): row/column workspace for chunk_items work items
   bool big = false;
   int64_t chunk_items = 0;
@@ -300,6 +308,11 @@ extern "C" int shw_wfs_plan_destroy(shw_wfs_plan* p) {
   if (p->d_valid) (void)hipFree(p->d_valid);
   if (p->d_khat) (void)hipFree(p->d_khat);
   if (p->d_T) (void)hipFree(p->d_T);
+  for (int k = 0; k < kListRing; ++k) {
+    if (p->ring_pending[k]) (void)hipEventSynchronize(p->ring_ev[k]);  // uploads out of the host ring done
+    if (p->ring_ev[k]) (void)hipEventDestroy(p->ring_ev[k]);
+  }
+  if (p->h_ring) (void)hipHostFree(p->h_ring);
   if (p->d_list) (void)hipFree(p->d_list);
   if (p->d_mfma_tab) (void)hipFree(p->d_mfma_tab);
   if (p->d_Jr) (void)hipFree(p->d_Jr);
@@ -628,17 +641,40 @@ extern "C" int sh_wfs_measure_batch(const shw_work* items, int32_t n, void* stre
     }
     const int32_t nf = (int32_t)list.size();
     if (nf > p->list_cap) {
+      // grow the device list and the host ring: wait for what still uses them first
+      hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+      for (int k = 0; e == hipSuccess && k < kListRing; ++k)
+        if (p->ring_pending[k]) e = hipEventSynchronize(p->ring_ev[k]);
+      if (e != hipSuccess) return hip_fail(e, "work list: wait before growing");
+      for (int k = 0; k < kListRing; ++k) p->ring_pending[k] = false;
       if (p->d_list) (void)hipFree(p->d_list);
+      if (p->h_ring) (void)hipHostFree(p->h_ring);
       p->d_list = nullptr;
+      p->h_ring = nullptr;
       p->list_cap = 0;
       const int32_t cap = nf < 256 ? 256 : nf;
-      hipError_t e = hipMalloc(&p->d_list, sizeof(FrameWork) * cap);
+      e = hipMalloc(&p->d_list, sizeof(FrameWork) * cap);
+      if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_ring, sizeof(FrameWork) * (size_t)cap * kListRing);
+      for (int k = 0; e == hipSuccess && k < kListRing; ++k)
+        if (!p->ring_ev[k]) e = hipEventCreateWithFlags(&p->ring_ev[k], hipEventDisableTiming);
       if (e != hipSuccess) return hip_fail(e, "work list");
       p->list_cap = cap;
     }
-    hipError_t e = hipMemcpyAsync(p->d_list, list.data(), sizeof(FrameWork) * nf, hipMemcpyHostToDevice,
-                                  (hipStream_t)stream);
+    // stage the list in a pinned ring slot, so that the upload is asynchronous and the caller's
+    // thread does not wait for earlier work on the stream; the slot is reused once its previous
+    // upload has completed
+    const int slot = p->ring_next;
+    p->ring_next = (slot + 1) % kListRing;
+    if (p->ring_pending[slot]) {
+      hipError_t e = hipEventSynchronize(p->ring_ev[slot]);
+      if (e != hipSuccess) return hip_fail(e, "work list: wait for a staging slot");
+    }
+    FrameWork* h = p->h_ring + (size_t)slot * p->list_cap;
+    std::memcpy(h, list.data(), sizeof(FrameWork) * nf);
+    hipError_t e = hipMemcpyAsync(p->d_list, h, sizeof(FrameWork) * nf, hipMemcpyHostToDevice, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipEventRecord(p->ring_ev[slot], (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "work list upload");
+    p->ring_pending[slot] = true;
     WfsLaunch a = base_launch(p);
     a.list = p->d_list;
     a.total = (int64_t)nf * p->n_wfs * p->n_valid;

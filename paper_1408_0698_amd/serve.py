@@ -41,6 +41,7 @@ class Request:
     done: Optional[float] = None
     status: str = "waiting"        # waiting | running | done | failed | rejected | cancelled
     error: Optional[str] = None
+    held: bool = False             # had to wait for HBM (instance residency or a staging slot)
 
     @property
     def latency(self):
@@ -95,25 +96,37 @@ class Server:
         self.results: Dict[int, object] = {}
         self.max_used = self.adm.used
         self.launches = 0
+        self.evictions = 0             # idle resident instances evicted to admit another
+        self.max_inflight = 0          # most batches on the device at once
         self.t0 = time.perf_counter()
 
     def now(self) -> float:
         return time.perf_counter() - self.t0
 
     # ------------------------------------------------------------ admission
-    def _make_resident(self, inst: Instance) -> bool:
-        need = self.ex.instance_bytes(inst.cls)
+    def _make_room(self, need: int, keep: Instance) -> bool:
+        """Evict idle resident instances other than `keep` until `need` bytes fit.  True if they fit."""
         if not self.adm.fits(need):
-            # evict idle resident instances, least recently used first
-            idle = sorted((i for i in self.instances.values() if i.resident and i.inflight == 0 and i is not inst),
-                          key=lambda i: i.last_used)
+            # victims: idle instances whose eviction alone makes room first (least recently used
+            # first among them), then the others least recently used first, so that small
+            # instances are not evicted one by one for a large request
+            deficit = self.adm.used + need - self.adm.budget
+            idle = sorted((i for i in self.instances.values() if i.resident and i.inflight == 0 and i is not keep),
+                          key=lambda i: (self.ex.instance_bytes(i.cls) < deficit, i.last_used))
+            if sum(self.ex.instance_bytes(i.cls) for i in idle) < deficit:
+                return False       # evicting every idle instance would not make room: evict none
             for victim in idle:
                 self.ex.destroy_instance(victim)
                 victim.resident = False
+                self.evictions += 1
                 self.adm.give(self.ex.instance_bytes(victim.cls))
                 if self.adm.fits(need):
                     break
-        if not self.adm.fits(need):
+        return self.adm.fits(need)
+
+    def _make_resident(self, inst: Instance) -> bool:
+        need = self.ex.instance_bytes(inst.cls)
+        if not self._make_room(need, inst):
             return False
         self.ex.create_instance(inst)
         self.adm.take(need)
@@ -163,7 +176,8 @@ class Server:
                 continue
             ok = inst.resident or self._make_resident(inst)
             slot = self.ex.slot_bytes(inst.cls)
-            if ok and self.adm.fits(slot):
+            # a resident instance whose staging slot does not fit may evict idle others for it
+            if ok and self._make_room(slot, inst):
                 self.adm.take(slot)
                 inst.inflight += 1
                 inst.last_used = self.now()
@@ -172,6 +186,7 @@ class Server:
                 batch.append(r)
             else:
                 blocked.add(r.instance)
+                r.held = True
                 keep.append(r)
         keep.extend(self.queue)
         self.queue = keep
@@ -216,6 +231,7 @@ class Server:
                 h = self.ex.launch(batch)
                 self.launches += 1
                 self.inflight.append((h, batch))
+                self.max_inflight = max(self.max_inflight, len(self.inflight))
             except Exception as e:
                 self._retire(batch, failed=f"{type(e).__name__}: {e}")
             busy = True
@@ -246,10 +262,13 @@ def latency_report(reqs: List[Request]) -> dict:
     if len(done) == 0:
         return {"completed": 0}
     span = max(r.done for r in done) - min(r.arrival for r in done)
+    wait = np.array([r.admitted - r.arrival for r in done]) * 1e3
     return {"completed": len(done), "failed": sum(r.status == "failed" for r in reqs),
             "rejected": sum(r.status == "rejected" for r in reqs),
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "mean_ms": float(lat.mean()), "frames_per_s": len(done) / span if span > 0 else float("nan")}
+            "mean_ms": float(lat.mean()), "frames_per_s": len(done) / span if span > 0 else float("nan"),
+            "queue_wait_p50_ms": float(np.percentile(wait, 50)), "queue_wait_p99_ms": float(np.percentile(wait, 99)),
+            "held_for_hbm": sum(r.held for r in done)}
 
 
 # ---------------------------------------------------------------- GPU executor
@@ -257,13 +276,18 @@ def latency_report(reqs: List[Request]) -> dict:
 class GpuExecutor:
     """Device state and launches through libshwfs; torch provides memory and streams only."""
 
-    def __init__(self, keep_results: bool = False):
+    def __init__(self, keep_results: bool = False, keep_images: bool = False):
         import torch
 
         from gen import configs as G
         from . import shwfs
         self.torch, self.G, self.s = torch, G, shwfs
-        self.keep = keep_results
+        self.keep = keep_results or keep_images
+        self.keep_images = keep_images
+        # instance state lives in pinned host memory once created; making an instance resident again
+        # after an eviction is an asynchronous copy, not a regeneration
+        self.host = {}
+        self.stats = {"created": 0, "restored": 0, "evicted": 0}
         self.streams = {"8m": torch.cuda.Stream(), "39m": torch.cuda.Stream()}
         self.plan8 = shwfs.WfsPlan(G.CFG0)
         self.plan_lgs = shwfs.WfsPlan(G.CFG1, 6, G.launch_positions(G.CFG1, 6))
@@ -296,24 +320,40 @@ class GpuExecutor:
 
         from gen import screens as S
         torch = self.torch
-        if inst.cls == "8m":
-            scr = S.screen_opd_m(512, 0.1, seed=inst.seed).astype(np.float32)
-            self.state[inst.iid] = {"screen": torch.from_numpy(scr).cuda()}
+        st = self.streams[inst.cls]
+        if inst.iid in self.host:
+            # resident again after an eviction: copy the saved state on the class stream (ordered
+            # before the work that uses it)
+            with torch.cuda.stream(st):
+                self.state[inst.iid] = {k: ([h.to("cuda", non_blocking=True) for h in v] if isinstance(v, list)
+                                            else v.to("cuda", non_blocking=True))
+                                        for k, v in self.host[inst.iid].items()}
+            self.stats["restored"] += 1
             return
-        scr = S.screen_opd_m(2048, 4.875e-2, seed=inst.seed).astype(np.float32)
-        st = self.streams["39m"]
-        surfs = []
+        if inst.cls == "8m":
+            scr = torch.from_numpy(S.screen_opd_m(512, 0.1, seed=inst.seed).astype(np.float32)).pin_memory()
+            host = {"screen": scr}
+        else:
+            scr = torch.from_numpy(S.screen_opd_m(2048, 4.875e-2, seed=inst.seed).astype(np.float32)).pin_memory()
+            surfs = []
+            with torch.cuda.stream(st):
+                for d, p in enumerate(self.dm_plans):
+                    c = torch.from_numpy(S.dm_coefficients(p.n_act, inst.seed * 10 + d).astype(np.float32)).cuda()
+                    sf = torch.empty((p.size, p.size), device="cuda")
+                    p.surface(c, sf, stream=st)
+                    surfs.append(sf)
+            st.synchronize()
+            host = {"screen": scr, "surfaces": [sf.cpu().pin_memory() for sf in surfs]}
+        self.host[inst.iid] = host
         with torch.cuda.stream(st):
-            for d, p in enumerate(self.dm_plans):
-                c = torch.from_numpy(S.dm_coefficients(p.n_act, inst.seed * 10 + d).astype(np.float32)).cuda()
-                sf = torch.empty((p.size, p.size), device="cuda")
-                p.surface(c, sf, stream=st)
-                surfs.append(sf)
-        st.synchronize()
-        self.state[inst.iid] = {"screen": torch.from_numpy(scr).cuda(), "surfaces": surfs}
+            self.state[inst.iid] = {k: ([h.to("cuda", non_blocking=True) for h in v] if isinstance(v, list)
+                                        else v.to("cuda", non_blocking=True)) for k, v in host.items()}
+        self.stats["created"] += 1
 
     def destroy_instance(self, inst: Instance):
-        self.state.pop(inst.iid, None)
+        # only idle instances are evicted: no queued work reads this state any more
+        if self.state.pop(inst.iid, None) is not None:
+            self.stats["evicted"] += 1
 
     def _origins_39m(self, frame: int):
         t = frame % (2048 - 800 - 400 + 1)
@@ -345,17 +385,23 @@ class GpuExecutor:
                 if cls == "8m":
                     opd = torch.empty((len(reqs), 1, 80, 80), device="cuda")
                     sl = torch.empty((len(reqs), 1, 2, self.n_valid["8m"]), device="cuda")
+                    im = (torch.empty((len(reqs), 1, self.n_valid["8m"], 8, 8), device="cuda")
+                          if self.keep_images else None)
                     for iid, ks in groups.items():
                         org = [((reqs[k].frame % (432 * 432)) // 432, reqs[k].frame % 432) for k in ks]
                         s.residual_opd(self.state[iid]["screen"], [], 80, org, [[] for _ in ks],
                                        opd[ks[0]:ks[-1] + 1].view(-1, 80, 80), stream=st)
-                    s.measure_batch([(self.plan8, opd[k], sl[k], None, self._seed(r), r.frame)
+                    s.measure_batch([(self.plan8, opd[k], sl[k], None if im is None else im[k], self._seed(r), r.frame)
                                      for k, r in enumerate(reqs)], stream=st)
-                    handle["slots"][cls] = (reqs, opd, sl, None)
+                    handle["slots"][cls] = (reqs, opd, sl, None, im, None)
                 else:
                     opd = torch.empty((len(reqs), 9, 800, 800), device="cuda")
                     sl_l = torch.empty((len(reqs), 6, 2, self.n_valid["lgs"]), device="cuda")
                     sl_n = torch.empty((len(reqs), 3, 2, self.n_valid["ngs"]), device="cuda")
+                    im_l = im_n = None
+                    if self.keep_images:
+                        im_l = torch.empty((len(reqs), 6, self.n_valid["lgs"], 16, 16), device="cuda")
+                        im_n = torch.empty((len(reqs), 3, self.n_valid["ngs"], 16, 16), device="cuda")
                     for iid, ks in groups.items():
                         stt = self.state[iid]
                         scr_o, dm_o = [], []
@@ -365,11 +411,11 @@ class GpuExecutor:
                             dm_o += b_
                         s.residual_opd(stt["screen"], stt["surfaces"], 800, scr_o, dm_o,
                                        opd[ks[0]:ks[-1] + 1].view(-1, 800, 800), stream=st)
-                    s.measure_batch([(self.plan_lgs, opd[k, :6], sl_l[k], None, self._seed(r), r.frame)
-                                     for k, r in enumerate(reqs)], stream=st)
-                    s.measure_batch([(self.plan_ngs, opd[k, 6:], sl_n[k], None, self._seed(r), r.frame)
-                                     for k, r in enumerate(reqs)], stream=st)
-                    handle["slots"][cls] = (reqs, opd, sl_l, sl_n)
+                    s.measure_batch([(self.plan_lgs, opd[k, :6], sl_l[k], None if im_l is None else im_l[k],
+                                      self._seed(r), r.frame) for k, r in enumerate(reqs)], stream=st)
+                    s.measure_batch([(self.plan_ngs, opd[k, 6:], sl_n[k], None if im_n is None else im_n[k],
+                                      self._seed(r), r.frame) for k, r in enumerate(reqs)], stream=st)
+                    handle["slots"][cls] = (reqs, opd, sl_l, sl_n, im_l, im_n)
                 ev = torch.cuda.Event()
                 ev.record(st)
                 handle["events"].append(ev)
@@ -391,11 +437,16 @@ class GpuExecutor:
         if not self.keep:
             return None
         out = {}
-        for cls, (reqs, _opd, a, b) in h["slots"].items():
+        for cls, (reqs, _opd, a, b, ia, ib) in h["slots"].items():
             a_h = a.cpu().numpy()
             b_h = b.cpu().numpy() if b is not None else None
+            ia_h = ia.cpu().numpy() if ia is not None else None
+            ib_h = ib.cpu().numpy() if ib is not None else None
             for k, r in enumerate(reqs):
-                out[r.rid] = (a_h[k].copy(), None if b_h is None else b_h[k].copy())
+                res = (a_h[k].copy(), None if b_h is None else b_h[k].copy())
+                if self.keep_images:
+                    res += (ia_h[k].copy(), None if ib_h is None else ib_h[k].copy())
+                out[r.rid] = res
         return out
 
 

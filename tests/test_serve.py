@@ -151,3 +151,36 @@ def test_results_do_not_depend_on_the_mix():
         rr = Request(r.rid, r.instance, r.frame, 0.0)
         alone.run([rr])
         assert np.array_equal(alone.results[r.rid], srv.results[r.rid])
+
+
+def test_binding_budget_evicts_holds_and_reports():
+    """A budget for one resident instance at a time: requests alternating between two instances
+    force evictions, are held for HBM, still finish in per-instance order, and the report counts
+    the holds and queue waits."""
+    ex = FakeExecutor(duration=0.001, inst_bytes=1000, slot=100)
+    inst = [Instance(0, "39m", 1), Instance(1, "39m", 2)]
+    srv = Server(ex, inst, budget_bytes=1000 + 2 * 100)    # one instance, two slots
+    reqs = [Request(k, k % 2, k // 2, 0.0005 * k) for k in range(20)]
+    out = srv.run(reqs, timeout=30)
+    assert all(r.status == "done" for r in out)
+    assert srv.evictions >= 5 and len(ex.destroyed) == srv.evictions
+    assert srv.max_used <= srv.adm.budget
+    rep = latency_report(out)
+    assert rep["held_for_hbm"] > 0 and rep["queue_wait_p99_ms"] > 0.0
+    for i in range(2):
+        mine = [r for r in sorted(out, key=lambda r: r.admitted) if r.instance == i]
+        assert [r.frame for r in mine] == sorted(r.frame for r in mine)
+
+
+def test_slot_that_does_not_fit_evicts_idle_instances():
+    """Every instance resident and idle, and the budget too small for one more staging slot: the
+    request evicts an idle instance for its slot instead of waiting for ever."""
+    ex = FakeExecutor(duration=0.001, inst_bytes=1000, slot=500)
+    inst = [Instance(i, "39m", i) for i in range(4)]
+    srv = Server(ex, inst, budget_bytes=4 * 1000 + 300)   # all four fit, a slot does not
+    for i in inst:                                         # make all four resident
+        assert srv._make_resident(srv.instances[i.iid])
+    assert srv.adm.used == 4000
+    out = srv.run([Request(0, 2, 0, 0.0), Request(1, 0, 0, 0.0), Request(2, 3, 0, 0.0)], timeout=10)
+    assert all(r.status == "done" for r in out)
+    assert srv.evictions >= 1 and srv.max_used <= srv.adm.budget
