@@ -45,17 +45,18 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_counters(variant):
-    """Per-frame counter totals of the committed summary, or None if the kernel sources or the
-    launch variant differ from those the counters were taken with."""
+def measured_counters(variant, noise_head):
+    """Per-frame counter totals of the committed summary for this launch variant and noise-kernel
+    head, or None if the kernel sources changed since the counters were taken or that
+    configuration was not profiled."""
     try:
         with open(COUNTERS) as fh:
             t = json.load(fh)
     except OSError:
         return None
-    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("launch_variant") != variant:
+    if t.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return t
+    return t.get("configs", {}).get(f"{variant}/{noise_head}")
 
 
 def cpu_baseline(cfg, launch, opd, min_seconds=10.0):
@@ -107,23 +108,34 @@ def ex_ngs8m(stream):
     from gen import screens as S
     from paper_1408_0698_amd import shwfs
     out = {}
-    # 8 m NGS (80 sub-apertures): launch-bound, replayed as a graph
+    # 8 m NGS (80 sub-apertures): launch-bound.  Graphs: one loop step per graph (measure with the
+    # device frame counter, counter += 1), and K = 32 steps per graph (offsets 0..31, one counter += 32)
     plan0 = shwfs.WfsPlan(G.CFG0)
-    opd0 = torch.from_numpy(S.ngs8m_opd(1)[:, None].copy()).cuda()
-    sl0 = torch.zeros((1, 1, 2, plan0.n_valid), device="cuda")
+    K = 32
+    opd0 = torch.from_numpy(S.ngs8m_opd(K)[:, None].copy()).cuda()
+    sl0 = torch.zeros((K, 1, 2, plan0.n_valid), device="cuda")
     ctr = torch.zeros(1, dtype=torch.int64, device="cuda")
     gstream = torch.cuda.Stream()      # graph capture needs a stream other than the NULL stream
     with torch.cuda.stream(gstream):
         with shwfs.Graph.capture(gstream) as cap:
-            plan0.measure_devframe(opd0, sl0, ctr, stream=gstream)
+            plan0.measure_devframe(opd0[:1], sl0[:1], ctr, stream=gstream)
             shwfs.counter_add(ctr, 1, stream=gstream)
-        g = cap.graph
+        g1 = cap.graph
+        with shwfs.Graph.capture(gstream) as cap:
+            for k in range(K):
+                plan0.measure_devframe(opd0[k:k + 1], sl0[k:k + 1], ctr, stream=gstream, frame_offset=k)
+            shwfs.counter_add(ctr, K, stream=gstream)
+        gk = cap.graph
         for _ in range(20):
-            g.launch(gstream)
-        ms_graph = _time(lambda k: g.launch(gstream), 500, gstream)
-        ms_eager = _time(lambda k: plan0.measure(opd0, sl0, frame0=k, stream=gstream), 500, gstream)
+            g1.launch(gstream)
+            gk.launch(gstream)
+        ms_graph = _time(lambda k: g1.launch(gstream), 500, gstream)
+        ms_graph_k = _time(lambda k: gk.launch(gstream), 100, gstream) / K
+        ms_eager = _time(lambda k: plan0.measure(opd0[k % K:k % K + 1], sl0[k % K:k % K + 1], frame0=k, stream=gstream),
+                         500, gstream)
     torch.cuda.synchronize()
     out["ngs8m_graph_frames_per_s"] = 1e3 / ms_graph
+    out["ngs8m_graph32_frames_per_s"] = 1e3 / ms_graph_k
     out["ngs8m_eager_frames_per_s"] = 1e3 / ms_eager
     # 8 m NGS, 4096 frames per launch (batch of loop steps)
     opd0b = torch.from_numpy(S.ngs8m_opd(4096)[:, None].copy()).cuda()
@@ -508,6 +520,8 @@ def main():
     ap.add_argument("--extras", default=",".join(EXTRAS_DEFAULT),
                     help="comma-separated secondary workloads to run after the headline")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--noise-head", type=int, default=0, choices=(0, 2, 4, 6),
+                    help="with --no-autotune: the noise kernel's inversion head (default: the plan's, 4)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before timing, run 5 plain device copies of this many MB (profiler counter scale)")
     args = ap.parse_args()
@@ -544,6 +558,8 @@ def main():
         del src, dst
 
     variant = plan.variant
+    if args.noise_head:
+        plan.set_noise_head(args.noise_head)
     tuned = None
     if not args.no_autotune:
         import tempfile
@@ -588,7 +604,7 @@ def main():
     nominal = FLOP_PER_SUBAP_NOMINAL * subaps / launch_s / 1e12
     kernels = ("wfs_fused_kernel<10,40,40,16,lgs>"
                + (" + det_noise_kernel<16>" if variant in DETECTOR_SPLIT_VARIANTS else ""))
-    ctr = measured_counters(variant)
+    ctr = measured_counters(variant, plan.noise_head)
     if ctr is not None:
         # executed FP32 FLOPs of both kernels (FMA = 2) per frame, from the committed counters
         fp32 = ctr["fp32_flop_per_frame"] * B / launch_s / 1e12
@@ -602,7 +618,7 @@ def main():
                 "nominal_tflops": nominal,
                 "nominal_note": "3 x 5 N^2 log2 N^2 per sub-aperture (three full 40x40 transforms); the "
                                 "band-limited kernels execute fewer operations",
-                "kernel": f"sh_wfs_measure launch variant {variant}: {kernels}",
+                "kernel": f"sh_wfs_measure launch variant {variant}, noise head {plan.noise_head}: {kernels}",
                 "avg_launch_ms": avg_launch_ms}
     else:
         # kernels changed since the counters were taken: no executed count, nominal reported alone
@@ -632,6 +648,8 @@ def main():
         "roofline": roof,
         "launch_variant": variant,
         "autotune_ms_per_variant": tuned["ms_per_launch"] if tuned else None,
+        "autotune": ({"variant": tuned["variant"], "noise_head": tuned["noise_head"], "params": tuned["params"],
+                      "ms_per_noise_head": tuned["ms_per_noise_head"]} if tuned else None),
     }
     if not args.no_extras:
         out["extras"] = extras(stream, [w for w in args.extras.split(",") if w])

@@ -280,6 +280,33 @@ int shw_wfs_plan_autotune(shw_wfs_plan* plan, const float* d_opd_m, int64_t row_
                           int32_t* best, float* ms);
 
 /*
+ * shw_wfs_plan_variant_params - the parameters that variant `variant` fixes,
+ * as 6 values in params: convolution form (0 whole-row transforms, 1 split
+ * rows over lane pairs, 2 band-limited), waves-per-EU register target,
+ * persistent grid (0/1), noise and centroid in a second kernel (0/1), work
+ * items per block, sodium sub-layers (0/1).  SHW_E_UNSUPPORTED for plans
+ * without launch variants (FFT 512, MFMA precision forms).
+ */
+int shw_wfs_plan_variant_params(const shw_wfs_plan* plan, int32_t variant, int32_t* params);
+
+/*
+ * Inversion head of the noise kernel (variants with noise in a second
+ * kernel): the number of steps (2, 4 or 6; default 4) of the Poisson
+ * sequential search that every lane runs in lockstep for its pixels before
+ * the pixels still searching are queued and finished one per lane.  It
+ * changes which pixels are queued, not their counts; the FP32 centroid sums
+ * move by rounding (below 1e-4 detector px).
+ * shw_wfs_plan_autotune_noise_head times the three values on the given
+ * inputs for the current variant and keeps the fastest (ms: 3 entries,
+ * nullable); it synchronises the stream.
+ */
+int shw_wfs_plan_set_noise_head(shw_wfs_plan* plan, int32_t head);
+int shw_wfs_plan_get_noise_head(const shw_wfs_plan* plan, int32_t* head);
+int shw_wfs_plan_autotune_noise_head(shw_wfs_plan* plan, const float* d_opd_m, int64_t row_pitch,
+                                     int64_t wfs_stride, int64_t frame_stride, int32_t n_frames, float* d_slopes,
+                                     int32_t reps, void* hip_stream, int32_t* best, float* ms);
+
+/*
  * sh_wfs_measure with the frame number of the first frame read on the
  * device from *d_frame0 when the kernel runs (so a captured graph can be
  * replayed frame after frame; see shw_counter_add).  *d_frame0 + n_frames
@@ -288,6 +315,18 @@ int shw_wfs_plan_autotune(shw_wfs_plan* plan, const float* d_opd_m, int64_t row_
 int sh_wfs_measure_devframe(shw_wfs_plan* plan, const float* d_opd_m, int64_t row_pitch, int64_t wfs_stride,
                             int64_t frame_stride, int32_t n_frames, uint64_t seed, const uint64_t* d_frame0,
                             float* d_slopes, float* d_images, uint8_t* d_flags, void* hip_stream);
+
+/*
+ * sh_wfs_measure_devframe with the first frame number *d_frame0 +
+ * frame_offset (read on the device): several loop steps captured into one
+ * graph take offsets 0, 1, ..., K-1 and one shw_counter_add(K) after them,
+ * so that one replay measures K consecutive frames.  The sum must stay
+ * below 2^32 (not checked).
+ */
+int sh_wfs_measure_devframe_at(shw_wfs_plan* plan, const float* d_opd_m, int64_t row_pitch, int64_t wfs_stride,
+                               int64_t frame_stride, int32_t n_frames, uint64_t seed, const uint64_t* d_frame0,
+                               uint32_t frame_offset, float* d_slopes, float* d_images, uint8_t* d_flags,
+                               void* hip_stream);
 
 /* *d_counter += inc on the device (a one-lane kernel, capturable). */
 int shw_counter_add(uint64_t* d_counter, uint64_t inc, void* hip_stream);

@@ -1,9 +1,13 @@
-"""Autotuner cache: the fastest launch variant per (GPU architecture, geometry, batch).
+"""Autotuner cache: the fastest launch configuration per (GPU architecture, geometry, batch).
 
-The library times its own variants (shw_wfs_plan_autotune); this module
-only remembers the answer in a JSON file so that later processes start with
-the tuned variant.  Cache path: $SHW_AUTOTUNE_CACHE, else
-~/.cache/shwfs/autotune.json.
+The search is coordinate-wise: the library times every launch variant
+(shw_wfs_plan_autotune; a variant fixes the convolution form, the
+waves-per-EU register target, one-shot or persistent grid, and where noise
+and centroid run), then, for a variant with a separate noise kernel, the
+noise kernel's inversion head of 2, 4 or 6 lockstep steps
+(shw_wfs_plan_autotune_noise_head).  This module remembers the answer and
+the parameters it stands for in a JSON file, so that later processes start
+tuned.  Cache path: $SHW_AUTOTUNE_CACHE, else ~/.cache/shwfs/autotune.json.
 """
 from __future__ import annotations
 
@@ -32,15 +36,22 @@ def _load(path):
 
 
 def tuned_variant(plan: "shwfs.WfsPlan", opd, slopes, arch: str, reps: int = 20, stream=None, retune=False):
-    """Select the plan's launch variant from the cache, or time all variants and record the winner."""
+    """Configure the plan from the cache, or search and record the winner and its parameters."""
     path = cache_path()
     k = key(arch, plan.cfg, plan.n_wfs, opd.shape[0])
     table = _load(path)
-    if not retune and k in table and 0 <= table[k]["variant"] < plan.n_variants:
-        plan.set_variant(table[k]["variant"])
-        return table[k]
+    rec = table.get(k)
+    if not retune and rec and 0 <= rec.get("variant", -1) < plan.n_variants and rec.get("noise_head") in (2, 4, 6):
+        plan.set_variant(rec["variant"])
+        plan.set_noise_head(rec["noise_head"])
+        return rec
     best, ms = plan.autotune(opd, slopes, reps=reps, stream=stream)
-    rec = {"variant": best, "ms_per_launch": ms}
+    params = plan.variant_params(best)
+    head, ms_head = plan.noise_head, None
+    if params["noise_kernel"]:
+        head, ms_head = plan.autotune_noise_head(opd, slopes, reps=reps, stream=stream)
+    rec = {"variant": best, "noise_head": head, "params": params, "ms_per_launch": ms,
+           "ms_per_noise_head": ms_head}
     table[k] = rec
     os.makedirs(os.path.dirname(path), exist_ok=True)
     tmp = path + ".tmp"

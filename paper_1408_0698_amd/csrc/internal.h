@@ -36,12 +36,13 @@ struct WfsLaunch {
   float ron, thr;
   int32_t noise;
   uint32_t key0, key1, frame0;
-  const uint64_t* frame0_dev;  // nullable: frame number of the first frame, read on the device
+  const uint64_t* frame0_dev;  // nullable: frame number of the first frame (+ frame0), read on the device
   const FrameWork* list;       // nullable: frame f takes buffers, strides and key from list[f]
   // sodium sub-layers (kernels built with sub-layers only): sub-layer j adds c_j |r - L_w|^2 / 2
   // waves to the phase (r the pixel centre, L_w the launcher, both in pupil pixels from the axis)
   // and weighs its spot by weight_j
-  int32_t n_sub, pad1;
+  int32_t n_sub;
+  int32_t noise_head;          // lockstep inversion steps of det_noise_kernel (2, 4 or 6)
   int64_t sub_stride;          // OPD elements between the sub-layer wavefronts of a sensor (0: shared)
   const double* sub_coef;      // [n_sub][2] = (c_j waves / pixel^2, weight_j)
   const double* launch_px;     // [n_wfs][2] launcher (x, y) in pupil pixels from the axis
@@ -78,6 +79,10 @@ int wfs_variant_count(const WfsShape& s);
 
 // Variant a new plan starts with (the autotuner may pick another).
 int wfs_default_variant(const WfsShape& s);
+// Parameters of variant v: {convolution form (0 whole rows, 1 split rows, 2 band-limited),
+// waves-per-EU target, persistent grid, noise in det_noise_kernel, items per block, sub-layers};
+// false if v is not a variant of the shape.
+bool wfs_variant_params(const WfsShape& s, int v, int32_t* out);
 
 // True if the variant ends the fused kernel at the detector (needs a.det_ws).
 bool wfs_variant_needs_det_ws(const WfsShape& s, int variant);

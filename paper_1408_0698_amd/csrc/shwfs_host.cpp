@@ -69,6 +69,7 @@ struct shw_wfs_plan {
   size_t bytes = 0;
   std::vector<int32_t> valid;
   int32_t variant = 0;
+  int32_t noise_head = 4;        // lockstep inversion steps of det_noise_kernel: 2, 4 or 6
   int32_t prec = 0;              // SHW_PREC_*: 0 = FP32 register FFTs, else MFMA DFT GEMMs
   uint2* d_mfma_tab = nullptr;   // constant matrices of the MFMA variant
   FrameWork* d_list = nullptr;   // work list of sh_wfs_measure_batch
@@ -536,6 +537,7 @@ static WfsLaunch base_launch(const shw_wfs_plan* p) {
   a.launch_px = p->d_sub ? p->d_sub + 2 * p->n_sub : nullptr;
   a.det_ws = p->d_det_ws;
   a.det_ws_items = p->det_ws_items;
+  a.noise_head = p->noise_head;
   return a;
 }
 
@@ -1030,6 +1032,15 @@ extern "C" int sh_wfs_measure_devframe(shw_wfs_plan* p, const float* d_opd_m, in
                       d_images, d_flags, stream);
 }
 
+extern "C" int sh_wfs_measure_devframe_at(shw_wfs_plan* p, const float* d_opd_m, int64_t row_pitch,
+                                          int64_t wfs_stride, int64_t frame_stride, int32_t n_frames, uint64_t seed,
+                                          const uint64_t* d_frame0, uint32_t frame_offset, float* d_slopes,
+                                          float* d_images, uint8_t* d_flags, void* stream) {
+  if (!d_frame0) return fail(SHW_E_INVALID, "d_frame0 is NULL");
+  return measure_impl(p, d_opd_m, row_pitch, wfs_stride, frame_stride, n_frames, seed, frame_offset, d_frame0,
+                      d_slopes, d_images, d_flags, stream);
+}
+
 // ---------------------------------------------------------------- variants, autotuning
 
 extern "C" int shw_wfs_plan_variant_count(const shw_wfs_plan* p, int32_t* n) {
@@ -1049,6 +1060,26 @@ extern "C" int shw_wfs_plan_set_variant(shw_wfs_plan* p, int32_t v) {
   const int n = p->big ? 1 : wfs_variant_count(p->shape);
   if (v < 0 || v >= n) return fail(SHW_E_INVALID, "variant %d outside [0, %d)", v, n);
   p->variant = v;
+  return ok();
+}
+
+extern "C" int shw_wfs_plan_variant_params(const shw_wfs_plan* p, int32_t v, int32_t* params) {
+  if (!p || !params) return fail(SHW_E_INVALID, "NULL argument");
+  if (p->big || p->prec != SHW_PREC_FP32) return fail(SHW_E_UNSUPPORTED, "no launch variants for this plan");
+  if (!wfs_variant_params(p->shape, v, params)) return fail(SHW_E_INVALID, "variant %d out of range", v);
+  return ok();
+}
+
+extern "C" int shw_wfs_plan_set_noise_head(shw_wfs_plan* p, int32_t head) {
+  if (!p) return fail(SHW_E_INVALID, "plan is NULL");
+  if (head != 2 && head != 4 && head != 6) return fail(SHW_E_INVALID, "noise head %d not in {2, 4, 6}", head);
+  p->noise_head = head;
+  return ok();
+}
+
+extern "C" int shw_wfs_plan_get_noise_head(const shw_wfs_plan* p, int32_t* head) {
+  if (!p || !head) return fail(SHW_E_INVALID, "NULL argument");
+  *head = p->noise_head;
   return ok();
 }
 
@@ -1102,6 +1133,60 @@ extern "C" int shw_wfs_plan_autotune(shw_wfs_plan* p, const float* d_opd_m, int6
   }
   p->variant = best_v;
   *best = best_v;
+  return ok();
+}
+
+extern "C" int shw_wfs_plan_autotune_noise_head(shw_wfs_plan* p, const float* d_opd_m, int64_t row_pitch,
+                                                int64_t wfs_stride, int64_t frame_stride, int32_t n_frames,
+                                                float* d_slopes, int32_t reps, void* stream, int32_t* best,
+                                                float* ms) {
+  if (!p || !best) return fail(SHW_E_INVALID, "NULL argument");
+  if (n_frames < 1 || reps < 1 || reps > 100000) return fail(SHW_E_INVALID, "n_frames >= 1 and reps in [1, 1e5]");
+  static const int32_t kHeads[3] = {2, 4, 6};
+  const int32_t keep = p->noise_head;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(e, "autotune events");
+  }
+  float best_ms = 0.0f;
+  int32_t best_h = keep;
+  int rc = SHW_OK;
+  for (int h = 0; h < 3 && rc == SHW_OK && e == hipSuccess; ++h) {
+    p->noise_head = kHeads[h];
+    for (int k = 0; k < 2 + reps && rc == SHW_OK; ++k) {
+      if (k == 2) e = hipEventRecord(e0, (hipStream_t)stream);
+      if (e != hipSuccess) break;
+      rc = sh_wfs_measure(p, d_opd_m, row_pitch, wfs_stride, frame_stride, n_frames, 0, 0, d_slopes, nullptr,
+                          nullptr, stream);
+    }
+    if (rc != SHW_OK || e != hipSuccess) break;
+    e = hipEventRecord(e1, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e != hipSuccess) break;
+    t /= (float)reps;
+    if (ms) ms[h] = t;
+    if (h == 0 || t < best_ms) {
+      best_ms = t;
+      best_h = kHeads[h];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != SHW_OK) {
+    p->noise_head = keep;
+    return rc;
+  }
+  if (e != hipSuccess) {
+    p->noise_head = keep;
+    return hip_fail(e, "autotune timing");
+  }
+  p->noise_head = best_h;
+  *best = best_h;
   return ok();
 }
 

@@ -753,7 +753,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
 }
 
 // One-shot grid (one group per block) or persistent grid (blocks stride over the groups).
-// The frame number of the first frame comes from a.frame0_dev when set (graph replay).
+// The frame number of the first frame comes from a.frame0_dev (plus a.frame0) when set (graph replay).
 template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, int WPE, bool PERSIST, bool SPLIT, bool SUB,
           bool DSPLIT, bool BL>
 __global__ __launch_bounds__(SPB * CONV_N) __attribute__((amdgpu_waves_per_eu(WPE))) void wfs_fused_kernel(
@@ -773,7 +773,8 @@ __global__ __launch_bounds__(SPB * CONV_N) __attribute__((amdgpu_waves_per_eu(WP
       s_qtw[threadIdx.x] = make_float2(tw.c[j], -tw.s[j]);
     }
   }
-  const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev : a.frame0;
+  // device frame counter (graph replay): *frame0_dev plus the launch's offset a.frame0
+  const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev + a.frame0 : a.frame0;
   if constexpr (PERSIST) {
     const int64_t ngroups = (a.total - a.item0 + SPB - 1) / SPB;
     for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
@@ -796,7 +797,7 @@ __global__ __launch_bounds__(SPB * CONV_N) __attribute__((amdgpu_waves_per_eu(WP
 // pixel, sub-aperture and frame) and threshold as the fused stage, so the same images; the
 // centroid sums are FP32 (per lane, then a tree over the lanes) instead of FP64, which moves a
 // slope by a few 1e-5 detector pixels at most.
-template <int DET_N>
+template <int DET_N, int HEAD>
 __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   constexpr int NPIX = DET_N * DET_N;
   constexpr float CD = 0.5f * (float)(DET_N - 1);
@@ -805,7 +806,8 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   // read-noise deviate) from the back, so that each runs once for up to 64 pixels
   __shared__ int q_pix[4][NPIX];
   __shared__ float q_val[4][4][NPIX];
-  const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev : a.frame0;
+  // device frame counter (graph replay): *frame0_dev plus the launch's offset a.frame0
+  const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev + a.frame0 : a.frame0;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: item arithmetic on the scalar unit
   const int64_t item = a.item0 + (int64_t)blockIdx.x * 4 + wave;
@@ -861,11 +863,11 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) u[j] = z[j] = 0.0f;
   }
-  // Inversions: a few lockstep steps for the lane's pixels (most means are small and end there);
+  // Inversions: HEAD lockstep steps for the lane's pixels (most means are small and end there);
   // the ones still searching go to queue A and restart one per lane, so that the lane's long
   // searches do not hold its other pixels.  Means >= kPoissonSplit go to queue B (rejection sampler).  Both
-  // queues share the LDS arrays: A from the front, B from the back.
-  constexpr int HEAD = 4;
+  // queues share the LDS arrays: A from the front, B from the back.  HEAD changes which pixels reach
+  // queue A, not their counts (the same steps either way).
   int k[NJ];
   bool more[NJ];
   float p0[NJ];
@@ -976,7 +978,11 @@ static hipError_t launch_variant(const WfsLaunch& a0, hipStream_t st) {
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(SPB * CONV_N), 0, st, a);
     if constexpr (DSPLIT) {
       const int64_t nb = (a.total - a.item0 + 3) / 4;
-      hipLaunchKernelGGL(det_noise_kernel<DET_N>, dim3((unsigned)nb), dim3(256), 0, st, a);
+      switch (a.noise_head) {
+        case 2: hipLaunchKernelGGL((det_noise_kernel<DET_N, 2>), dim3((unsigned)nb), dim3(256), 0, st, a); break;
+        case 6: hipLaunchKernelGGL((det_noise_kernel<DET_N, 6>), dim3((unsigned)nb), dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL((det_noise_kernel<DET_N, 4>), dim3((unsigned)nb), dim3(256), 0, st, a); break;
+      }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1077,6 +1083,29 @@ int wfs_variant_count(const WfsShape& s) {
   if (s.sub) return kSubVariants + (bl ? kBandLimitedVariants : 0);
   if (!(s.conv_n == 40 && s.det_n == 16)) return 1;
   return kTunedVariants + (bl ? kBandLimitedVariants : 0);
+}
+
+bool wfs_variant_params(const WfsShape& s, int v, int32_t* out) {
+  if (v < 0 || v >= wfs_variant_count(s)) return false;
+  // {convolution form (0 whole rows, 1 split rows, 2 band-limited), waves-per-EU target, persistent
+  // grid, noise in a second kernel, items per block, sodium sub-layers}
+  struct Row {
+    int8_t form, wpe, persist, dsplit;
+  };
+  static constexpr Row kTuned[] = {{0, 1, 0, 0}, {0, 4, 0, 0}, {1, 1, 0, 0}, {1, 4, 0, 0}, {0, 1, 1, 0},
+                                   {0, 4, 1, 0}, {0, 1, 0, 1}, {0, 4, 1, 1}, {1, 1, 0, 1}, {1, 4, 1, 1},
+                                   {1, 1, 1, 1}, {2, 5, 1, 1}, {2, 7, 0, 1}};
+  static constexpr Row kSub[] = {{0, 1, 0, 0}, {1, 1, 0, 0}, {1, 4, 1, 1}, {2, 5, 0, 1}, {2, 6, 1, 1}};
+  Row r{0, 1, 0, 0};
+  if (s.sub) r = kSub[v];
+  else if (s.conv_n == 40 && s.det_n == 16) r = kTuned[v];
+  out[0] = r.form;
+  out[1] = r.wpe;
+  out[2] = r.persist;
+  out[3] = r.dsplit;
+  out[4] = items_per_block(s.conv_n);
+  out[5] = s.sub ? 1 : 0;
+  return true;
 }
 
 int wfs_default_variant(const WfsShape& s) {

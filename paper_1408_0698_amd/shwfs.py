@@ -68,8 +68,15 @@ _sig = {
     "shw_wfs_plan_get_variant": (C.c_int, [_P, C.POINTER(C.c_int32)]),
     "shw_wfs_plan_autotune": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int64, C.c_int32, _P, C.c_int32, _P,
                                         C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+    "shw_wfs_plan_variant_params": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32)]),
+    "shw_wfs_plan_set_noise_head": (C.c_int, [_P, C.c_int32]),
+    "shw_wfs_plan_get_noise_head": (C.c_int, [_P, C.POINTER(C.c_int32)]),
+    "shw_wfs_plan_autotune_noise_head": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int64, C.c_int32, _P, C.c_int32,
+                                                   _P, C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
     "sh_wfs_measure_devframe": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_uint64, _P,
                                           _P, _P, _P, _P]),
+    "sh_wfs_measure_devframe_at": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_uint64, _P,
+                                             C.c_uint32, _P, _P, _P, _P]),
     "shw_counter_add": (C.c_int, [_P, C.c_uint64, _P]),
     "shw_graph_begin": (C.c_int, [_P]),
     "shw_graph_end": (C.c_int, [_P, C.POINTER(_P)]),
@@ -238,6 +245,37 @@ class WfsPlan:
     def set_variant(self, v):
         _check(_lib.shw_wfs_plan_set_variant(self._h, v), "shw_wfs_plan_set_variant")
 
+    VARIANT_PARAM_NAMES = ("convolution", "waves_per_eu", "persistent", "noise_kernel", "items_per_block",
+                           "sublayers")
+    CONVOLUTION_FORMS = ("whole_rows", "split_rows", "band_limited")
+
+    def variant_params(self, v):
+        """The parameters launch variant v fixes, as a dict."""
+        out = (C.c_int32 * 6)()
+        _check(_lib.shw_wfs_plan_variant_params(self._h, v, out), "shw_wfs_plan_variant_params")
+        d = dict(zip(self.VARIANT_PARAM_NAMES, list(out)))
+        d["convolution"] = self.CONVOLUTION_FORMS[d["convolution"]]
+        return d
+
+    @property
+    def noise_head(self):
+        h = C.c_int32(0)
+        _check(_lib.shw_wfs_plan_get_noise_head(self._h, C.byref(h)), "shw_wfs_plan_get_noise_head")
+        return h.value
+
+    def set_noise_head(self, head):
+        _check(_lib.shw_wfs_plan_set_noise_head(self._h, head), "shw_wfs_plan_set_noise_head")
+
+    def autotune_noise_head(self, opd, slopes, reps=20, stream=None):
+        """Time the noise kernel's inversion head (2, 4, 6 steps) for the current variant; keep the
+        fastest.  Returns (best, [ms per launch for 2, 4, 6])."""
+        ms = (C.c_float * 3)()
+        best = C.c_int32(-1)
+        _check(_lib.shw_wfs_plan_autotune_noise_head(self._h, _ptr(opd), opd.stride(2), opd.stride(1), opd.stride(0),
+                                                     opd.shape[0], _ptr(slopes), reps, _stream_ptr(stream),
+                                                     C.byref(best), ms), "shw_wfs_plan_autotune_noise_head")
+        return best.value, list(ms)
+
     def autotune(self, opd, slopes, reps=20, stream=None):
         """Time every launch variant on these inputs; select the fastest.  Returns (best, [ms per launch])."""
         n = self.n_variants
@@ -248,13 +286,20 @@ class WfsPlan:
                "shw_wfs_plan_autotune")
         return best.value, list(ms)
 
-    def measure_devframe(self, opd, slopes, d_frame0, images=None, flags=None, seed=0, stream=None):
-        """As measure, with the first frame number read on the device from the uint64 tensor d_frame0."""
+    def measure_devframe(self, opd, slopes, d_frame0, images=None, flags=None, seed=0, stream=None, frame_offset=0):
+        """As measure, with the first frame number read on the device from the uint64 tensor d_frame0
+        (plus frame_offset)."""
         if opd.dim() != 4 or opd.stride(3) != 1:
             raise ValueError("opd must be [frames][wfs][rows][cols] with contiguous rows")
-        _check(_lib.sh_wfs_measure_devframe(self._h, _ptr(opd), opd.stride(2), opd.stride(1), opd.stride(0),
-                                            opd.shape[0], seed, _ptr(d_frame0), _ptr(slopes), _ptr(images),
-                                            _ptr(flags), _stream_ptr(stream)), "sh_wfs_measure_devframe")
+        if frame_offset == 0:
+            _check(_lib.sh_wfs_measure_devframe(self._h, _ptr(opd), opd.stride(2), opd.stride(1), opd.stride(0),
+                                                opd.shape[0], seed, _ptr(d_frame0), _ptr(slopes), _ptr(images),
+                                                _ptr(flags), _stream_ptr(stream)), "sh_wfs_measure_devframe")
+        else:
+            _check(_lib.sh_wfs_measure_devframe_at(self._h, _ptr(opd), opd.stride(2), opd.stride(1), opd.stride(0),
+                                                   opd.shape[0], seed, _ptr(d_frame0), frame_offset, _ptr(slopes),
+                                                   _ptr(images), _ptr(flags), _stream_ptr(stream)),
+                   "sh_wfs_measure_devframe_at")
         return slopes
 
     def measure(self, opd, slopes, images=None, flags=None, seed=0, frame0=0, stream=None):

@@ -208,6 +208,8 @@ def test_geometry_and_psf_extras_argument_checks():
     assert s._lib.shw_uplink_tilt(*args, 0, lgs, 0.4, 32, None, None) == s.OK
     assert s._lib.psf_encircled_energy(None, fake, 1, 0, 1, (C.c_double * 1)(3.0), fake, None) == s.E_INVALID
     assert s._lib.psf_encircled_energy_noalloc(None, fake, 1, 0, 1, (C.c_double * 1)(3.0), fake, None) == s.E_INVALID
+    assert s._lib.shw_wfs_plan_set_noise_head(None, 4) == s.E_INVALID
+    assert s._lib.shw_wfs_plan_variant_params(None, 0, (C.c_int32 * 6)()) == s.E_INVALID
     assert s._lib.psf_resample_accumulate(1, fake, 1.0, C.c_float(1.0), C.c_void_p(0x9000), None) == s.E_INVALID
     assert s._lib.psf_resample_accumulate(64, fake, 0.0, C.c_float(1.0), C.c_void_p(0x90000), None) == s.E_INVALID
     assert s._lib.psf_resample_accumulate(64, fake, 1.0, C.c_float(1.0), C.c_void_p(0x1100), None) == s.E_INVALID

@@ -99,7 +99,36 @@ def test_autotune_selects_a_variant(torch_dev, tmp_path, monkeypatch):
     assert 0 <= rec["variant"] < plan.n_variants and len(rec["ms_per_launch"]) == plan.n_variants
     assert min(rec["ms_per_launch"]) == rec["ms_per_launch"][rec["variant"]]
     rec2 = autotune.tuned_variant(plan, opd, sl, "gfx950")
-    assert rec2["variant"] == rec["variant"]
+    assert rec2["variant"] == rec["variant"] and rec2["noise_head"] == rec["noise_head"]
+    # the record names the parameters of the chosen variant, and the head search ran for a
+    # variant with a separate noise kernel
+    assert rec["params"] == plan.variant_params(rec["variant"])
+    assert rec["noise_head"] in (2, 4, 6) and plan.noise_head == rec["noise_head"]
+    if rec["params"]["noise_kernel"]:
+        assert len(rec["ms_per_noise_head"]) == 3
+    forms = [plan.variant_params(v)["convolution"] for v in range(plan.n_variants)]
+    assert forms[11] == forms[12] == "band_limited" and forms[0] == "whole_rows" and forms[2] == "split_rows"
+
+
+def test_noise_head_changes_no_count(torch_dev):
+    """The noise kernel's inversion head (2, 4, 6 lockstep steps) changes which pixels are queued,
+    not their counts: images bitwise equal, slopes within 1e-4 px (FP32 centroid sums)."""
+    cfg = G.CFG1.replace(pupil_n=400, n_subap=40)
+    plan = _plan(cfg, 6)
+    opd = torch_dev.from_numpy(S.lgs39m_opd(1, 6, pupil_n=400)).cuda()
+    out = {}
+    for head in (2, 4, 6):
+        plan.set_noise_head(head)
+        sl = torch_dev.zeros((1, 6, 2, plan.n_valid), device="cuda")
+        im = torch_dev.zeros((1, 6, plan.n_valid, 16, 16), device="cuda")
+        plan.measure(opd, sl, im, seed=77, frame0=5)
+        torch_dev.cuda.synchronize()
+        out[head] = (sl.cpu().numpy(), im.cpu().numpy())
+    for head in (2, 6):
+        assert np.array_equal(out[head][1], out[4][1])
+        assert np.abs(out[head][0] - out[4][0]).max() <= 1e-4
+    with pytest.raises(Exception):
+        plan.set_noise_head(3)
 
 
 def test_graph_replay_advances_frames(torch_dev):
@@ -131,6 +160,43 @@ def test_graph_replay_advances_frames(torch_dev):
         torch.cuda.synchronize()
         assert torch.equal(got[0], ref_sl) and torch.equal(got[1], ref_im), f"replay {k}"
     assert int(counter.item()) == 1004
+
+
+def test_multi_step_graph_replays_consecutive_frames(torch_dev):
+    """Capture K = 8 loop steps (measure with the device frame counter at offsets 0..7, then one
+    counter += 8) in one graph; three replays with eager work and synchronisations between them
+    equal the eager calls for frames base + 8 r + k."""
+    from paper_1408_0698_amd import shwfs
+    torch = torch_dev
+    K = 8
+    cfg = G.CFG0.replace(photons_per_subap=100.0, ron_e=2.0, threshold_e=1.0, flags=1)
+    plan = _plan(cfg, 1)
+    opd = torch.from_numpy(S.ngs8m_opd(K)[:, None].copy()).cuda()
+    counter = torch.tensor([2000], dtype=torch.int64, device="cuda")
+    sl = torch.zeros((K, 1, 2, plan.n_valid), device="cuda")
+    im = torch.zeros((K, 1, plan.n_valid, 8, 8), device="cuda")
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    print("graph of", K, "steps", flush=True)
+    with torch.cuda.stream(stream):
+        with shwfs.Graph.capture(stream) as cap:
+            for k in range(K):
+                plan.measure_devframe(opd[k:k + 1], sl[k:k + 1], counter, images=im[k:k + 1], seed=11, stream=stream,
+                                      frame_offset=k)
+            shwfs.counter_add(counter, K, stream=stream)
+    g = cap.graph
+    for r in range(3):
+        with torch.cuda.stream(stream):
+            g.launch(stream)
+        stream.synchronize()
+        got_sl, got_im = sl.clone(), im.clone()
+        for k in range(K):
+            ref_sl = torch.zeros_like(sl[k:k + 1])
+            ref_im = torch.zeros_like(im[k:k + 1])
+            plan.measure(opd[k:k + 1], ref_sl, ref_im, seed=11, frame0=2000 + K * r + k)
+            torch.cuda.synchronize()
+            assert torch.equal(got_sl[k:k + 1], ref_sl) and torch.equal(got_im[k:k + 1], ref_im), f"replay {r} step {k}"
+    assert int(counter.item()) == 2000 + 3 * K
 
 
 def test_detector_split_work_list_equals_single_calls(torch_dev):
