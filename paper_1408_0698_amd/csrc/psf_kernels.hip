@@ -26,9 +26,10 @@
 // at ((f * M/8 + u/8) * pupil_n + y) * 8 + u % 8, so that rows write whole
 // 64-byte runs and the 8 columns of a column block are one contiguous region.
 // Column pass: 4 columns per block, the two halves of a column block launched
-// 8 blocks apart (the same XCD), frames accumulated in registers, one
-// read-modify-write of the accumulator per call; the on-axis sample of each
-// frame is the Strehl ratio.
+// 8 blocks apart (the same XCD), frames accumulated in LDS (each lane owns its
+// 20 outputs, so no barrier), one read-modify-write of the accumulator per
+// call; the on-axis sample of each frame is the Strehl ratio.  A 4-waves-per-
+// SIMD register target (128 VGPRs, a few spilled) lets 3 blocks share a CU.
 #include <hip/hip_runtime.h>
 
 #include "psf_internal.h"
@@ -158,10 +159,12 @@ __global__ __launch_bounds__(kLines * kP) void psf_rows_kernel(const PsfLaunch a
 
 // Column pass.  The two halves of a column block (4 columns each) go to blocks 8 apart in launch
 // order, which the dispatcher places on the same XCD, so each 64-byte run is fetched into one L2.
-__global__ __launch_bounds__(kLines * kP) void psf_cols_kernel(const PsfLaunch a, int64_t f0, int nf,
+__global__ __launch_bounds__(kLines * kP) __attribute__((amdgpu_waves_per_eu(4))) void psf_cols_kernel(const PsfLaunch a, int64_t f0, int nf,
                                                                const float2* __restrict__ T, float* __restrict__ acc,
                                                                float* __restrict__ strehl) {
   __shared__ float s_pl[kLines * kQ * kST];
+  // per-line sums over the frames: lane (q, h) owns entries q + 40 (c + 20 h), c < 20 (no barrier)
+  __shared__ float s_sum[kLines][kM];
   const int tid = threadIdx.x;
   const int line = tid / kP, j = tid - line * kP;
   const int q = j >> 1, h = j & 1;
@@ -171,9 +174,9 @@ __global__ __launch_bounds__(kLines * kP) void psf_cols_kernel(const PsfLaunch a
   const int star = group / (kM / kCB);
   const int u = (group - star * (kM / kCB)) * kCB + half * kLines + line;  // column of this star
   float* pl = s_pl + line * kQ * kST;
-  float sum[kNZ];
+  float* sum = s_sum[line];
 #pragma unroll
-  for (int c = 0; c < kNZ; ++c) sum[c] = 0.0f;
+  for (int c = 0; c < kNZ; ++c) sum[q + kQ * (c + kNZ * h)] = 0.0f;
   for (int fl = 0; fl < nf; ++fl) {
     const int64_t sf = (int64_t)star * nf + fl;
     float2 v[kNZ];
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(kLines * kP) void psf_cols_kernel(const PsfLaunch a
 #pragma unroll
     for (int c = 0; c < kNZ; ++c) {
       const float p = (x[c].x * x[c].x + x[c].y * x[c].y) * a.inv_norm;
-      sum[c] += p;
+      sum[q + kQ * (c + kNZ * h)] += p;
       // on-axis sample: v = u = M/2, i.e. k1 = 0, k2 = 20 (c = 0, h = 1) of column M/2
       if (strehl && u == kM / 2 && q == 0 && h == 1 && c == 0) strehl[(int64_t)star * a.n_frames + f0 + fl] = p;
     }
@@ -195,7 +198,7 @@ __global__ __launch_bounds__(kLines * kP) void psf_cols_kernel(const PsfLaunch a
 #pragma unroll
   for (int c = 0; c < kNZ; ++c) {
     const int vv = q + kQ * (c + kNZ * h);
-    acc[star * a.acc_stride + (int64_t)vv * kM + u] += sum[c];
+    acc[star * a.acc_stride + (int64_t)vv * kM + u] += sum[vv];
   }
 }
 
