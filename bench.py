@@ -169,8 +169,8 @@ def ex_precision(stream):
             for k in range(3):
                 pl.measure(opd1[k % 2:k % 2 + 1], sl, seed=1, frame0=k, stream=stream)
             ms = _time(lambda k: pl.measure(opd1[k % 2:k % 2 + 1], sl, seed=1, frame0=k, stream=stream), 20, stream)
-        # 384 16x16x16 products per sub-aperture, each one (bf16) or three (split) MFMA instructions
-        flops = 6 * pl.n_valid * 384 * mult * 2 * 16 * 16 * 16
+        # 102 16x16x16 products per sub-aperture, each one (bf16) or three (split) MFMA instructions
+        flops = 6 * pl.n_valid * 102 * mult * 2 * 16 * 16 * 16
         mm[name] = {"frames_per_s": 1e3 / ms, "ms_per_frame": ms, "mfma_tflops": flops / (ms * 1e-3) / 1e12,
                     "mfma_frac_of_2500": flops / (ms * 1e-3) / 2.5e15}
         pl.close()

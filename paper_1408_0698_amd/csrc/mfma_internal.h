@@ -14,17 +14,24 @@ constexpr int kPrecFp16x3 = 3;
 
 // Constant matrices, in 16x16 tiles, in B-operand lane order: entry (tile, lane) holds the
 // four values M[16 b + 4 (lane / 16) + r][16 c + lane % 16], r = 0..3, as hi halves (8 bytes)
-// then lo halves (8 bytes).  Tile offsets:
-constexpr int kTabWr = 0;       // W^T real, 16 x 48 (3 tiles); W[u][x] = exp(-2 pi i (u - 39/2) x / 40)
-constexpr int kTabWi = 3;       // W^T imaginary
-constexpr int kTabWiNeg = 6;    // -W^T imaginary
-constexpr int kTabC = 9;        // cos(2 pi k v / 40), 48 x 48 (9 tiles)
-constexpr int kTabS = 18;       // sin(2 pi k v / 40)
-constexpr int kTabSNeg = 27;    // -sin
-constexpr int kTabWb = 36;      // rebin Wb^T, 48 x 16 (3 tiles)
-constexpr int kMfmaTableTiles = 39;
+// then lo halves (8 bytes).  N = 40, c0 = 39/2; in-band column j < 19 stands for the frequency
+// k(j) = j (j <= 9) or j - 19 (j >= 10); rows and columns beyond a matrix are zero.
+constexpr int kTabWr = 0;       // W^T, 16 x 48 (3 tiles): W^T[x][u] = exp(-2 pi i (u - c0) x / N), x < 10
+constexpr int kTabWi = 3;
+constexpr int kTabWiNeg = 6;
+constexpr int kTabDr = 9;       // D^T, 48 x 32 (3 x 2 tiles): D^T[v][j] = exp(-2 pi i k(j) v / N)
+constexpr int kTabDi = 15;
+constexpr int kTabDiNeg = 21;
+constexpr int kTabMvr = 27;     // Mv^T, 16 x 16: Mv^T[j][p] = c_j (1/N) sum_v Wb[p][v] exp(2 pi i k(j) v / N),
+constexpr int kTabMvi = 28;     //   j < 10, c_0 = 1, c_j = 2 (the rows of negative frequency folded in)
+constexpr int kTabMviNeg = 29;
+constexpr int kTabMur = 30;     // Mu^T, 32 x 16 (2 tiles): Mu^T[j][q] = (1/N) sum_u Wb[q][u] exp(2 pi i k(j) u / N)
+constexpr int kTabMuiNeg = 32;
+constexpr int kMfmaTableTiles = 34;
 
 bool mfma_shape_supported(int npx, int fft_n, int conv_n, int det_n, int prec);
+// Detector values of items [a.item0, a.total) into a.det_ws (chunks of a.det_ws_items items), each
+// chunk followed by det_noise_kernel (photometry, noise, centroid).
 hipError_t launch_wfs_mfma(int prec, bool lgs, const WfsLaunch& a, const uint2* tables, hipStream_t st);
 
 }  // namespace shw

@@ -1,46 +1,72 @@
-// mfma_kernels.hip - the sub-aperture transforms as DFT-matrix GEMMs on MFMA (precision form).
+// mfma_kernels.hip - the sub-aperture transforms as small DFT GEMMs on MFMA (precision form).
 //
 // Same measurement as the fused kernel (Sec. 4: field, spot by Fourier
-// transform, Gaussian convolution, rebin, noise, centroid), with every
-// transform written as a product of small dense matrices:
-//   F = W e W^T            (centred 40x10 DFT W; e the 10x10 field)
-//   I = |F|^2 / 40^2
-//   X = G I G^T, Y = X . K^, J = Re(conj(G) Y conj(G)^T)   (G the 40-point DFT)
-//   Det = Wb J Wb^T        (area-overlap rebin, 16x40)
-// padded to 48 (three 16-row tiles).  One wavefront owns one sub-aperture
-// and keeps each matrix in registers in the MFMA accumulator layout
-// (lane l, register r of tile (ti, tj) holds X[16 ti + 4 (l / 16) + r][16 tj + l % 16]).
-// That layout is the A-operand layout of the transposed matrix, so every
-// step is R = X^T M with M a constant matrix in the B-operand layout (equal
-// to the accumulator layout), and W e W^T = (e^T W^T)^T W^T needs no
-// transpose through memory.  The constant matrices are split into hi + lo
-// parts in FP64 on the host and staged in LDS; the data operand is split
-// on the fly.  Precision variants:
+// transform, Gaussian convolution, rebin; noise and centroid then run in
+// det_noise_kernel), with every transform a product of small dense matrices
+// on the matrix cores.  With N = 40, e the 10 x 10 field and W the centred
+// 40 x 10 DFT:
+//   F = W e W^T,  I = |F|^2 / N^2                                  (spot)
+//   I^ = D I D^T on the 19 x 19 in-band frequencies k, |k| <= 9     (D: 19 x 40 DFT rows)
+//   J^ = I^ . K^                                                    (sodium kernel; 1 for an NGS)
+//   Det = Re(Mv J^ Mu^T),  M[p][k] = (1/N) sum_v Wb[p][v] e^{2 pi i k v / N}
+// The spot of a 10-pixel field has no spectrum beyond 9 samples from zero
+// (its transform is the field's autocorrelation), so I^ outside the band is
+// zero and the last line equals rebin(Re IDFT(DFT(I) . K^)) exactly.  I is
+// real, so I^ is Hermitian: only the 10 rows of non-negative frequency are
+// formed, and Mv weighs rows 1..9 by 2 to stand for their mirror rows.
+//
+// One wavefront owns one sub-aperture and keeps each matrix in the MFMA
+// accumulator layout (lane l, register r of tile (ti, tj) holds
+// X[16 ti + 4 (l / 16) + r][16 tj + l % 16]), which is the A-operand layout
+// of X^T: every step is Out = In^T M with M a constant matrix in the
+// B-operand layout (tables built on the host in FP64, split into hi + lo
+// there and staged in LDS); the data operand is split on the fly with the
+// packed conversion instructions.  102 16x16x16 products per sub-aperture
+// (12 + 36 for the spot, 18 + 24 for the band spectrum, 8 + 4 for the map),
+// each taken once (BF16) or three times (split variants):
 //   BF16   : A_hi B_hi
 //   BF16X3 : A_hi B_hi + A_hi B_lo + A_lo B_hi (bf16 hi, bf16 of the residual)
 //   FP16X3 : A_hi B_hi + 2^-11 (A_hi B_lo' + A_lo' B_hi) with lo' = fp16(2^11 residual)
-// with FP32 accumulation; the phase reduction and the centroid sums stay FP64.
+// with FP32 accumulation; the phase reduction stays FP64.
 #include <hip/hip_runtime.h>
 
 #include "mfma_internal.h"
-#include "noise.h"
 
 namespace shw {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+typedef __bf16 b2v __attribute__((ext_vector_type(2)));
 typedef short s4 __attribute__((ext_vector_type(4)));
+
+// det_noise_kernel over the items of a (wfs_kernels.hip)
+hipError_t launch_det_noise16(const WfsLaunch& a, hipStream_t st);
 
 namespace {
 
-constexpr int kT = 3;        // 48 = 3 tiles of 16
 constexpr int kWaves = 4;    // sub-apertures per block
+constexpr int kN = 40;
 
-__device__ __forceinline__ short bf16_bits(float x) {
-  const uint32_t u = __float_as_uint(x);
-  return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);  // round to nearest even
+// Two floats to packed halves (round to nearest even), as 32 bits: element 0 in the low half.
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+  const b2v v = __builtin_convertvector((f2v){a, b}, b2v);
+  uint32_t u;
+  __builtin_memcpy(&u, &v, 4);
+  return u;
 }
-__device__ __forceinline__ float bf16_float(short b) { return __uint_as_float(((uint32_t)(uint16_t)b) << 16); }
+__device__ __forceinline__ uint32_t pk_f16(float a, float b) {
+  const h2v v = __builtin_convertvector((f2v){a, b}, h2v);
+  uint32_t u;
+  __builtin_memcpy(&u, &v, 4);
+  return u;
+}
+__device__ __forceinline__ float2 unpk_f16(uint32_t u) {
+  h2v v;
+  __builtin_memcpy(&v, &u, 4);
+  return make_float2((float)v[0], (float)v[1]);
+}
 
 // Data operand, split for the precision variant.
 template <int PREC>
@@ -62,20 +88,28 @@ template <int PREC>
 __device__ __forceinline__ Op<PREC> split(f4 x) {
   Op<PREC> o;
   if constexpr (PREC == kPrecFp16x3) {
+    // below the fp16 normal range the whole value goes to the scaled low part, so that no
+    // subnormal half reaches the matrix unit
+    float h[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      // below the fp16 normal range the whole value goes to the scaled low part, so that
-      // no subnormal half reaches the matrix unit
-      const _Float16 h = fabsf(x[r]) < 6.103515625e-05f ? (_Float16)0.0f : (_Float16)x[r];
-      o.hi[r] = h;
-      o.lo[r] = (_Float16)((x[r] - (float)h) * 2048.0f);
-    }
+    for (int r = 0; r < 4; ++r) h[r] = fabsf(x[r]) < 6.103515625e-05f ? 0.0f : x[r];
+    const uint32_t p0 = pk_f16(h[0], h[1]), p1 = pk_f16(h[2], h[3]);
+    const float2 b0 = unpk_f16(p0), b1 = unpk_f16(p1);
+    const uint32_t l0 = pk_f16((x[0] - b0.x) * 2048.0f, (x[1] - b0.y) * 2048.0f);
+    const uint32_t l1 = pk_f16((x[2] - b1.x) * 2048.0f, (x[3] - b1.y) * 2048.0f);
+    const uint32_t hv[2] = {p0, p1}, lv[2] = {l0, l1};
+    __builtin_memcpy(&o.hi, hv, 8);
+    __builtin_memcpy(&o.lo, lv, 8);
   } else {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const short h = bf16_bits(x[r]);
-      o.hi[r] = h;
-      if constexpr (PREC == kPrecBf16x3) o.lo[r] = bf16_bits(x[r] - bf16_float(h));
+    const uint32_t p0 = pk_bf16(x[0], x[1]), p1 = pk_bf16(x[2], x[3]);
+    const uint32_t hv[2] = {p0, p1};
+    __builtin_memcpy(&o.hi, hv, 8);
+    if constexpr (PREC == kPrecBf16x3) {
+      // the hi halves back as floats: a bf16 is the high 16 bits of its float
+      const float b0 = __uint_as_float(p0 << 16), b1 = __uint_as_float(p0 & 0xFFFF0000u);
+      const float b2 = __uint_as_float(p1 << 16), b3 = __uint_as_float(p1 & 0xFFFF0000u);
+      const uint32_t lv[2] = {pk_bf16(x[0] - b0, x[1] - b1), pk_bf16(x[2] - b2, x[3] - b3)};
+      __builtin_memcpy(&o.lo, lv, 8);
     }
   }
   return o;
@@ -107,8 +141,8 @@ __device__ __forceinline__ f4 acc_value(const Acc<PREC>& a) {
 // acc += A * B for one 16x16x16 step; B comes from an LDS table entry (hi, lo halves).
 template <int PREC>
 __device__ __forceinline__ void mma(Acc<PREC>& acc, const Op<PREC>& a, const uint2* __restrict__ bt) {
+  const uint4 b = *reinterpret_cast<const uint4*>(bt);
   if constexpr (PREC == kPrecFp16x3) {
-    const uint4 b = *reinterpret_cast<const uint4*>(bt);
     h4 bhi, blo;
     __builtin_memcpy(&bhi, &b.x, 8);
     __builtin_memcpy(&blo, &b.z, 8);
@@ -116,7 +150,6 @@ __device__ __forceinline__ void mma(Acc<PREC>& acc, const Op<PREC>& a, const uin
     acc.corr = __builtin_amdgcn_mfma_f32_16x16x16f16(a.hi, blo, acc.corr, 0, 0, 0);
     acc.corr = __builtin_amdgcn_mfma_f32_16x16x16f16(a.lo, bhi, acc.corr, 0, 0, 0);
   } else {
-    const uint4 b = *reinterpret_cast<const uint4*>(bt);
     s4 bhi;
     __builtin_memcpy(&bhi, &b.x, 8);
     acc.c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, bhi, acc.c, 0, 0, 0);
@@ -129,10 +162,23 @@ __device__ __forceinline__ void mma(Acc<PREC>& acc, const Op<PREC>& a, const uin
   }
 }
 
-// Table entry of constant matrix m, tile (b, c), for this lane (16 bytes: 4 hi + 4 lo halves).
-__device__ __forceinline__ const uint2* tab(const uint2* t, int m_off, int tiles_c, int b, int c, int lane) {
-  return t + ((size_t)(m_off + b * tiles_c + c) * 64 + lane) * 2;
+// (cr, ci) += (ar + i ai) (Br + i Bi) for one step: tables Br, Bi and -Bi.
+template <int PREC>
+__device__ __forceinline__ void cmma(Acc<PREC>& cr, Acc<PREC>& ci, const Op<PREC>& ar, const Op<PREC>& ai,
+                                     const uint2* br, const uint2* bi, const uint2* bin) {
+  mma(cr, ar, br);
+  mma(cr, ai, bin);
+  mma(ci, ar, bi);
+  mma(ci, ai, br);
 }
+
+// Table entry of constant tile `tile` for this lane (16 bytes: 4 hi + 4 lo halves).
+__device__ __forceinline__ const uint2* tab(const uint2* t, int tile, int lane) {
+  return t + ((size_t)tile * 64 + lane) * 2;
+}
+
+// Frequency of in-band column j (j < 19): 0..9, then -9..-1.
+__device__ __forceinline__ int band_k(int j) { return j <= 9 ? j : j - 19; }
 
 }  // namespace
 
@@ -143,7 +189,8 @@ __global__ __launch_bounds__(64 * kWaves) void wfs_mfma_kernel(const WfsLaunch a
   for (int e = threadIdx.x; e < kMfmaTableTiles * 64 * 2; e += 64 * kWaves) s_tab[e] = tables[e];
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int64_t item = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: item arithmetic on the scalar unit
+  const int64_t item = a.item0 + (int64_t)blockIdx.x * kWaves + wave;
   if (item >= a.total) return;  // no block barrier below this point
   const int64_t per_frame = (int64_t)a.n_wfs * a.n_valid;
   const int f = (int)(item / per_frame);
@@ -159,262 +206,176 @@ __global__ __launch_bounds__(64 * kWaves) void wfs_mfma_kernel(const WfsLaunch a
   f4 er, ei;
   {
     const float* src = a.opd + (int64_t)f * a.frame_stride + (int64_t)w * a.wfs_stride;
+    // the four samples are loaded before any is used; unlit and padding pixels masked by amplitude
+    float ov[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int y = lr + r, x = lc;
-      float cr = 0.0f, ci = 0.0f;
-      if (y < 10 && x < 10) {
-        const int prow = sa * 10 + y, pcol = sb * 10 + x;
-        const float ay = (float)prow + 0.5f - a.half_n, ax = (float)pcol + 0.5f - a.half_n;
-        const float r2 = ax * ax + ay * ay;
-        if (r2 <= a.r2_outer && r2 >= a.r2_inner) {
-          double wv = (double)src[(int64_t)prow * a.row_pitch + pcol] * a.inv_lambda;
-          wv = __builtin_amdgcn_fract(wv);  // wv - floor(wv), one instruction
-          float sn, cs;
-          sincospif(2.0f * (float)wv, &sn, &cs);
-          cr = cs;
-          ci = sn;
-        }
-      }
-      er[r] = cr;
-      ei[r] = ci;
+      const int prow = sa * 10 + (y < 10 ? y : 0), pcol = sb * 10 + (x < 10 ? x : 0);
+      ov[r] = src[(int64_t)prow * a.row_pitch + pcol];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int y = lr + r, x = lc;
+      const int prow = sa * 10 + y, pcol = sb * 10 + x;
+      const float ay = (float)prow + 0.5f - a.half_n, ax = (float)pcol + 0.5f - a.half_n;
+      const float r2 = ax * ax + ay * ay;
+      const bool lit = y < 10 && x < 10 && r2 <= a.r2_outer && r2 >= a.r2_inner;
+      double wv = (double)ov[r] * a.inv_lambda;
+      wv = __builtin_amdgcn_fract(wv);  // wv - floor(wv), one instruction
+      // hardware sine and cosine take revolutions: exp(2 pi i wv) after the FP64 reduction
+      const float fw = (float)wv;
+      const float amp = lit ? 1.0f : 0.0f;
+      er[r] = amp * __builtin_amdgcn_cosf(fw);
+      ei[r] = amp * __builtin_amdgcn_sinf(fw);
     }
   }
-  // ---------------------------------------------------------------- spot: R1 = e^T W^T (16 x 48), F = R1^T W^T
-  f4 Fr[kT][kT], Fi[kT][kT];
+  // ---------------------------------------------------------------- spot: P1 = e^T W^T (16 x 48), F = P1^T W^T
+  // I = |F|^2 / N^2, split as soon as each tile is formed
+  Op<PREC> Is[3][3];
   {
     const Op<PREC> xr = split<PREC>(er), xi = split<PREC>(ei);
-    f4 R1r[kT], R1i[kT];
+    f4 P1r[3], P1i[3];
 #pragma unroll
-    for (int c = 0; c < kT; ++c) {
+    for (int c = 0; c < 3; ++c) {
       Acc<PREC> ar, ai;
       acc_zero(ar);
       acc_zero(ai);
-      mma(ar, xr, tab(s_tab, kTabWr, kT, 0, c, lane));
-      mma(ar, xi, tab(s_tab, kTabWiNeg, kT, 0, c, lane));
-      mma(ai, xr, tab(s_tab, kTabWi, kT, 0, c, lane));
-      mma(ai, xi, tab(s_tab, kTabWr, kT, 0, c, lane));
-      R1r[c] = acc_value(ar);
-      R1i[c] = acc_value(ai);
+      cmma(ar, ai, xr, xi, tab(s_tab, kTabWr + c, lane), tab(s_tab, kTabWi + c, lane), tab(s_tab, kTabWiNeg + c, lane));
+      P1r[c] = acc_value(ar);
+      P1i[c] = acc_value(ai);
     }
 #pragma unroll
-    for (int ta = 0; ta < kT; ++ta) {
-      const Op<PREC> yr = split<PREC>(R1r[ta]), yi = split<PREC>(R1i[ta]);
+    for (int tv = 0; tv < 3; ++tv) {
+      const Op<PREC> yr = split<PREC>(P1r[tv]), yi = split<PREC>(P1i[tv]);
 #pragma unroll
-      for (int c = 0; c < kT; ++c) {
+      for (int tu = 0; tu < 3; ++tu) {
         Acc<PREC> ar, ai;
         acc_zero(ar);
         acc_zero(ai);
-        mma(ar, yr, tab(s_tab, kTabWr, kT, 0, c, lane));
-        mma(ar, yi, tab(s_tab, kTabWiNeg, kT, 0, c, lane));
-        mma(ai, yr, tab(s_tab, kTabWi, kT, 0, c, lane));
-        mma(ai, yi, tab(s_tab, kTabWr, kT, 0, c, lane));
-        Fr[ta][c] = acc_value(ar);
-        Fi[ta][c] = acc_value(ai);
+        cmma(ar, ai, yr, yi, tab(s_tab, kTabWr + tu, lane), tab(s_tab, kTabWi + tu, lane),
+             tab(s_tab, kTabWiNeg + tu, lane));
+        const f4 fr = acc_value(ar), fi = acc_value(ai);
+        Is[tv][tu] = split<PREC>((fr * fr + fi * fi) * (1.0f / (float)(kN * kN)));
       }
     }
   }
-  // ---------------------------------------------------------------- I = |F|^2 / N^2
-  f4 J[kT][kT];
+  // ---------------------------------------------------------------- band spectrum: P3 = I^T D^T (48 x 16: columns
+  // j < 16 only, the rows of P4 that are used), P4 = P3^T D^T (16 x 32) = I^[k(j1)][k(j2)]
+  f4 Hr[2], Hi[2];
+  {
+    Op<PREC> p3r[3], p3i[3];
 #pragma unroll
-  for (int ta = 0; ta < kT; ++ta)
+    for (int tu = 0; tu < 3; ++tu) {
+      Acc<PREC> ar, ai;
+      acc_zero(ar);
+      acc_zero(ai);
 #pragma unroll
-    for (int tc = 0; tc < kT; ++tc) J[ta][tc] = (Fr[ta][tc] * Fr[ta][tc] + Fi[ta][tc] * Fi[ta][tc]) * (1.0f / 1600.0f);
-
-  if constexpr (LGS) {
-    // T = I^T G^T: Tr = I^T C, Ti = -I^T S     (G = C - i S, symmetric)
-    f4 Tr[kT][kT], Ti[kT][kT];
-    {
-      Op<PREC> in[kT][kT];
-#pragma unroll
-      for (int b = 0; b < kT; ++b)
-#pragma unroll
-        for (int ta = 0; ta < kT; ++ta) in[b][ta] = split<PREC>(J[b][ta]);
-#pragma unroll
-      for (int ta = 0; ta < kT; ++ta)
-#pragma unroll
-        for (int c = 0; c < kT; ++c) {
-          Acc<PREC> ar, ai;
-          acc_zero(ar);
-          acc_zero(ai);
-#pragma unroll
-          for (int b = 0; b < kT; ++b) {
-            mma(ar, in[b][ta], tab(s_tab, kTabC, kT, b, c, lane));
-            mma(ai, in[b][ta], tab(s_tab, kTabSNeg, kT, b, c, lane));
-          }
-          Tr[ta][c] = acc_value(ar);
-          Ti[ta][c] = acc_value(ai);
-        }
+      for (int tv = 0; tv < 3; ++tv) {
+        mma(ar, Is[tv][tu], tab(s_tab, kTabDr + 2 * tv, lane));
+        mma(ai, Is[tv][tu], tab(s_tab, kTabDi + 2 * tv, lane));
+      }
+      p3r[tu] = split<PREC>(acc_value(ar));
+      p3i[tu] = split<PREC>(acc_value(ai));
     }
-    // X = T^T G^T = (Tr^T C + Ti^T S) + i (Ti^T C - Tr^T S); Y = X . K^
-    f4 Yr[kT][kT], Yi[kT][kT];
-    {
-      Op<PREC> tr[kT][kT], ti[kT][kT];
 #pragma unroll
-      for (int b = 0; b < kT; ++b)
+    for (int tj = 0; tj < 2; ++tj) {
+      Acc<PREC> ar, ai;
+      acc_zero(ar);
+      acc_zero(ai);
 #pragma unroll
-        for (int ta = 0; ta < kT; ++ta) {
-          tr[b][ta] = split<PREC>(Tr[b][ta]);
-          ti[b][ta] = split<PREC>(Ti[b][ta]);
-        }
-      const float* kh = a.khat + (int64_t)(w * a.n_valid + i) * 21 * 40;
-#pragma unroll
-      for (int ta = 0; ta < kT; ++ta)
-#pragma unroll
-        for (int c = 0; c < kT; ++c) {
-          Acc<PREC> ar, ai;
-          acc_zero(ar);
-          acc_zero(ai);
-#pragma unroll
-          for (int b = 0; b < kT; ++b) {
-            mma(ar, tr[b][ta], tab(s_tab, kTabC, kT, b, c, lane));
-            mma(ar, ti[b][ta], tab(s_tab, kTabS, kT, b, c, lane));
-            mma(ai, ti[b][ta], tab(s_tab, kTabC, kT, b, c, lane));
-            mma(ai, tr[b][ta], tab(s_tab, kTabSNeg, kT, b, c, lane));
-          }
-          const f4 xr = acc_value(ar), xi = acc_value(ai);
-          // K^(k, l) from the stored half spectrum (rows 0..20), K^(k, l) = K^(-k, -l)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int k = 16 * ta + lr + r, l = 16 * c + lc;
-            float kv = 0.0f;
-            if (k < 40 && l < 40) kv = k <= 20 ? kh[k * 40 + l] : kh[(40 - k) * 40 + (40 - l) % 40];
-            Yr[ta][c][r] = xr[r] * kv;
-            Yi[ta][c][r] = xi[r] * kv;
-          }
-        }
-    }
-    // U = Y^T conj(G)^T = (Yr^T C - Yi^T S) + i (Yr^T S + Yi^T C)
-    f4 Ur[kT][kT], Ui[kT][kT];
-    {
-      Op<PREC> yr[kT][kT], yi[kT][kT];
-#pragma unroll
-      for (int b = 0; b < kT; ++b)
-#pragma unroll
-        for (int ta = 0; ta < kT; ++ta) {
-          yr[b][ta] = split<PREC>(Yr[b][ta]);
-          yi[b][ta] = split<PREC>(Yi[b][ta]);
-        }
-#pragma unroll
-      for (int ta = 0; ta < kT; ++ta)
-#pragma unroll
-        for (int c = 0; c < kT; ++c) {
-          Acc<PREC> ar, ai;
-          acc_zero(ar);
-          acc_zero(ai);
-#pragma unroll
-          for (int b = 0; b < kT; ++b) {
-            mma(ar, yr[b][ta], tab(s_tab, kTabC, kT, b, c, lane));
-            mma(ar, yi[b][ta], tab(s_tab, kTabSNeg, kT, b, c, lane));
-            mma(ai, yr[b][ta], tab(s_tab, kTabS, kT, b, c, lane));
-            mma(ai, yi[b][ta], tab(s_tab, kTabC, kT, b, c, lane));
-          }
-          Ur[ta][c] = acc_value(ar);
-          Ui[ta][c] = acc_value(ai);
-        }
-    }
-    // J = Re(U^T conj(G)^T) = Ur^T C - Ui^T S   (K^ carries the 1/N^2)
-    {
-      Op<PREC> ur[kT][kT], ui[kT][kT];
-#pragma unroll
-      for (int b = 0; b < kT; ++b)
-#pragma unroll
-        for (int ta = 0; ta < kT; ++ta) {
-          ur[b][ta] = split<PREC>(Ur[b][ta]);
-          ui[b][ta] = split<PREC>(Ui[b][ta]);
-        }
-#pragma unroll
-      for (int ta = 0; ta < kT; ++ta)
-#pragma unroll
-        for (int c = 0; c < kT; ++c) {
-          Acc<PREC> ar;
-          acc_zero(ar);
-#pragma unroll
-          for (int b = 0; b < kT; ++b) {
-            mma(ar, ur[b][ta], tab(s_tab, kTabC, kT, b, c, lane));
-            mma(ar, ui[b][ta], tab(s_tab, kTabSNeg, kT, b, c, lane));
-          }
-          J[ta][c] = acc_value(ar);
-        }
+      for (int tu = 0; tu < 3; ++tu)
+        cmma(ar, ai, p3r[tu], p3i[tu], tab(s_tab, kTabDr + 2 * tu + tj, lane), tab(s_tab, kTabDi + 2 * tu + tj, lane),
+             tab(s_tab, kTabDiNeg + 2 * tu + tj, lane));
+      Hr[tj] = acc_value(ar);
+      Hi[tj] = acc_value(ai);
     }
   }
-  // ---------------------------------------------------------------- rebin: V = J^T Wb^T (48 x 16), Det = V^T Wb^T
+  // ---------------------------------------------------------------- J^ = I^ . K^ (rows j1 < 10; other rows and
+  // columns j2 >= 19 meet zero rows of the map tables)
+  if constexpr (LGS) {
+    // rows k = 0..20 of the stored half spectrum, which carries the 1/N^2 of a full inverse
+    // transform; the map tables carry their own 1/N each, so the stored value is scaled by N^2
+    const float* kh = a.khat + (int64_t)(w * a.n_valid + i) * 21 * kN;
+    float kv[2][4];
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j1 = lr + r, j2 = 16 * tj + lc;
+        const bool in = j1 < 10 && j2 < 19;
+        const int col = (band_k(j2) + kN) % kN;
+        kv[tj][r] = in ? (float)(kN * kN) * kh[j1 * kN + col] : 0.0f;
+      }
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        Hr[tj][r] *= kv[tj][r];
+        Hi[tj][r] *= kv[tj][r];
+      }
+  }
+  // ---------------------------------------------------------------- map: P5 = J^^T Mv^T (32 x 16), Det = Re(P5^T Mu^T)
   f4 det;
   {
-    Op<PREC> jo[kT][kT];
+    Op<PREC> p5r[2], p5i[2];
 #pragma unroll
-    for (int b = 0; b < kT; ++b)
-#pragma unroll
-      for (int ta = 0; ta < kT; ++ta) jo[b][ta] = split<PREC>(J[b][ta]);
-    f4 V[kT];
-#pragma unroll
-    for (int ta = 0; ta < kT; ++ta) {
-      Acc<PREC> ar;
+    for (int tj = 0; tj < 2; ++tj) {
+      const Op<PREC> jr = split<PREC>(Hr[tj]), ji = split<PREC>(Hi[tj]);
+      Acc<PREC> ar, ai;
       acc_zero(ar);
-#pragma unroll
-      for (int b = 0; b < kT; ++b) mma(ar, jo[b][ta], tab(s_tab, kTabWb, 1, b, 0, lane));
-      V[ta] = acc_value(ar);
+      acc_zero(ai);
+      cmma(ar, ai, jr, ji, tab(s_tab, kTabMvr, lane), tab(s_tab, kTabMvi, lane), tab(s_tab, kTabMviNeg, lane));
+      p5r[tj] = split<PREC>(acc_value(ar));
+      p5i[tj] = split<PREC>(acc_value(ai));
     }
     Acc<PREC> ad;
     acc_zero(ad);
 #pragma unroll
-    for (int b = 0; b < kT; ++b) mma(ad, split<PREC>(V[b]), tab(s_tab, kTabWb, 1, b, 0, lane));
+    for (int tj = 0; tj < 2; ++tj) {
+      mma(ad, p5r[tj], tab(s_tab, kTabMur + tj, lane));
+      mma(ad, p5i[tj], tab(s_tab, kTabMuiNeg + tj, lane));
+    }
     det = acc_value(ad);
   }
-  // ---------------------------------------------------------------- photometry, noise, centroid (4 pixels per lane)
-  const uint32_t gsub = (uint32_t)(w * a.n_valid + i);
-  const uint32_t frame = a.frame0 + (uint32_t)f;
-  double s0 = 0.0, sx = 0.0, sy = 0.0;
+  // ---------------------------------------------------------------- detector values for det_noise_kernel
+  float* dst = a.det_ws + (item - a.item0) * 256;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int p = lr + r, q = lc, pix = p * 16 + q;
-    float img = det[r];
-    if (a.ph_scale > 0.0f) {
-      const float lam = a.ph_scale * det[r];
-      img = a.noise ? noisy_pixel(lam, a.ron, (uint32_t)pix, 256u, gsub, frame, a.key0, a.key1) : lam;
-    }
-    if (a.images) a.images[item * 256 + pix] = img;
-    const double t = (double)fmaxf(img - a.thr, 0.0f);
-    s0 += t;
-    sx += (double)((float)q - 7.5f) * t;
-    sy += (double)((float)p - 7.5f) * t;
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    s0 += __shfl_xor(s0, off);
-    sx += __shfl_xor(sx, off);
-    sy += __shfl_xor(sy, off);
-  }
-  if (lane == 0) {
-    const int64_t fw = (int64_t)f * a.n_wfs + w;
-    const bool empty = !(s0 > 0.0);
-    a.slopes[(fw * 2) * a.n_valid + i] = empty ? 0.0f : (float)(sx / s0);
-    a.slopes[(fw * 2 + 1) * a.n_valid + i] = empty ? 0.0f : (float)(sy / s0);
-    if (a.flags) a.flags[item] = empty ? 1 : 0;
-  }
+  for (int r = 0; r < 4; ++r) dst[(lr + r) * 16 + lc] = det[r];
 }
 
 bool mfma_shape_supported(int npx, int fft_n, int conv_n, int det_n, int prec) {
   return npx == 10 && fft_n == 40 && conv_n == 40 && det_n == 16 && prec >= kPrecBf16 && prec <= kPrecFp16x3;
 }
 
-hipError_t launch_wfs_mfma(int prec, bool lgs, const WfsLaunch& a, const uint2* tables, hipStream_t st) {
-  const int64_t blocks = (a.total + kWaves - 1) / kWaves;
-  if (blocks <= 0) return hipSuccess;
-  const dim3 g((unsigned)blocks), b(64 * kWaves);
-#define L(P, G)                                                                   \
-  if (prec == P && lgs == G) {                                                    \
-    hipLaunchKernelGGL((wfs_mfma_kernel<P, G>), g, b, 0, st, a, tables);          \
-    return hipGetLastError();                                                     \
+hipError_t launch_wfs_mfma(int prec, bool lgs, const WfsLaunch& a0, const uint2* tables, hipStream_t st) {
+  const int64_t step = a0.det_ws_items;
+  if (!a0.det_ws || step <= 0) return hipErrorInvalidValue;
+  for (int64_t i0 = a0.item0; i0 < a0.total; i0 += step) {
+    WfsLaunch a = a0;
+    a.item0 = i0;
+    a.total = a0.total - i0 < step ? a0.total : i0 + step;
+    const int64_t blocks = (a.total - a.item0 + kWaves - 1) / kWaves;
+    const dim3 g((unsigned)blocks), b(64 * kWaves);
+    bool launched = false;
+#define L(P, G)                                                          \
+  if (!launched && prec == P && lgs == G) {                              \
+    hipLaunchKernelGGL((wfs_mfma_kernel<P, G>), g, b, 0, st, a, tables); \
+    launched = true;                                                     \
   }
-  L(kPrecBf16, true)
-  L(kPrecBf16x3, true)
-  L(kPrecFp16x3, true)
-  L(kPrecBf16, false)
-  L(kPrecBf16x3, false)
-  L(kPrecFp16x3, false)
+    L(kPrecBf16, true)
+    L(kPrecBf16x3, true)
+    L(kPrecFp16x3, true)
+    L(kPrecBf16, false)
+    L(kPrecBf16x3, false)
+    L(kPrecFp16x3, false)
 #undef L
-  return hipErrorInvalidValue;
+    if (!launched) return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_det_noise16(a, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace shw

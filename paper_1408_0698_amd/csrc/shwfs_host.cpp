@@ -255,23 +255,36 @@ static void split_const(double v, int prec, uint16_t* hi, uint16_t* lo) {
 
 static std::vector<uint16_t> mfma_tables(const shw_wfs_config* c, int prec) {
   const double pi = 3.14159265358979323846;
-  const int N = 40, n = 10;
+  const int N = 40, n = 10, nb = 19;
   const double cc = (N - 1) / 2.0;
+  auto band_k = [](int j) { return j <= 9 ? j : j - 19; };
   auto Wm = [&](int comp, int x, int u) -> double {  // W^T[x][u]
     if (x >= n || u >= N) return 0.0;
     const double th = 2.0 * pi * (u - cc) * x / N;
     return comp == 0 ? std::cos(th) : (comp == 1 ? -std::sin(th) : std::sin(th));
   };
-  auto Gm = [&](int comp, int k, int v) -> double {
-    if (k >= N || v >= N) return 0.0;
-    const double th = 2.0 * pi * (double)((k * v) % N) / N;
-    return comp == 0 ? std::cos(th) : (comp == 1 ? std::sin(th) : -std::sin(th));
+  auto Dm = [&](int comp, int v, int j) -> double {  // D^T[v][j] = exp(-2 pi i k(j) v / N)
+    if (v >= N || j >= nb) return 0.0;
+    const double th = 2.0 * pi * (double)(((band_k(j) * v) % N + N) % N) / N;
+    return comp == 0 ? std::cos(th) : (comp == 1 ? -std::sin(th) : std::sin(th));
   };
   const double b = (double)c->conv_n / c->det_n;
-  auto Wb = [&](int k, int p) -> double {  // Wb^T[k][p]
-    if (k >= N || p >= c->det_n) return 0.0;
+  auto Wb = [&](int p, int k) -> double {  // area overlap of input pixel k with detector pixel p
     const double lo = std::max((double)k, b * p), hi = std::min((double)(k + 1), b * (p + 1));
     return hi > lo ? hi - lo : 0.0;
+  };
+  // M^T[j][p] = (1/N) sum_v Wb[p][v] exp(2 pi i k(j) v / N), times c_j (rows j < 10 only) when folded
+  auto Mm = [&](int comp, int j, int p, bool folded) -> double {
+    if (j >= (folded ? 10 : nb) || p >= c->det_n) return 0.0;
+    double s = 0.0;
+    for (int v = 0; v < N; ++v) {
+      const double w = Wb(p, v);
+      if (w == 0.0) continue;
+      const double th = 2.0 * pi * (double)(((band_k(j) * v) % N + N) % N) / N;
+      s += w * (comp == 0 ? std::cos(th) : (comp == 1 ? std::sin(th) : -std::sin(th)));
+    }
+    const double cj = folded && j > 0 ? 2.0 : 1.0;
+    return cj * s / N;
   };
   std::vector<uint16_t> t((size_t)kMfmaTableTiles * 64 * 8, 0);
   auto put = [&](int tile, int lane, int r, double v) {
@@ -289,12 +302,18 @@ static std::vector<uint16_t> mfma_tables(const shw_wfs_config* c, int prec) {
         put(kTabWiNeg + tc, lane, r, Wm(2, kr, 16 * tc + nc));
       }
       for (int tb = 0; tb < 3; ++tb)
-        for (int tc = 0; tc < 3; ++tc) {
-          put(kTabC + tb * 3 + tc, lane, r, Gm(0, 16 * tb + kr, 16 * tc + nc));
-          put(kTabS + tb * 3 + tc, lane, r, Gm(1, 16 * tb + kr, 16 * tc + nc));
-          put(kTabSNeg + tb * 3 + tc, lane, r, Gm(2, 16 * tb + kr, 16 * tc + nc));
+        for (int tc = 0; tc < 2; ++tc) {
+          put(kTabDr + 2 * tb + tc, lane, r, Dm(0, 16 * tb + kr, 16 * tc + nc));
+          put(kTabDi + 2 * tb + tc, lane, r, Dm(1, 16 * tb + kr, 16 * tc + nc));
+          put(kTabDiNeg + 2 * tb + tc, lane, r, Dm(2, 16 * tb + kr, 16 * tc + nc));
         }
-      for (int tb = 0; tb < 3; ++tb) put(kTabWb + tb, lane, r, Wb(16 * tb + kr, nc));
+      put(kTabMvr, lane, r, Mm(0, kr, nc, true));
+      put(kTabMvi, lane, r, Mm(1, kr, nc, true));
+      put(kTabMviNeg, lane, r, Mm(2, kr, nc, true));
+      for (int tb = 0; tb < 2; ++tb) {
+        put(kTabMur + tb, lane, r, Mm(0, 16 * tb + kr, nc, false));
+        put(kTabMuiNeg + tb, lane, r, Mm(2, 16 * tb + kr, nc, false));
+      }
     }
   return t;
 }
@@ -418,7 +437,9 @@ static int plan_create(const shw_wfs_config* cfg, int32_t n_wfs, const shw_lgs_g
     }
     p->bytes += t.size() * sizeof(uint16_t);
   }
-  if (p->prec == SHW_PREC_FP32 && wfs_variant_needs_det_ws(p->shape, wfs_variant_count(p->shape) - 1)) {
+  if (p->prec != SHW_PREC_FP32 ||
+      wfs_variant_needs_det_ws(p->shape, wfs_variant_count(p->shape) - 1)) {
+    // the precision form hands its detector values to det_noise_kernel through this workspace too
     // one chunk holds a frame of every sensor, at least 16384 and at most 65536 items
     int64_t items = (int64_t)n_wfs * p->n_valid;
     items = items < 16384 ? 16384 : (items > 65536 ? 65536 : items);

@@ -1123,6 +1123,19 @@ bool wfs_variant_needs_det_ws(const WfsShape& s, int variant) {
   return s.conv_n == 40 && s.det_n == 16 && variant >= kFirstDetSplit;
 }
 
+// det_noise_kernel for 16 x 16 detectors over the items [a.item0, a.total) of a.det_ws (the MFMA
+// precision form hands its detector values over this way).
+hipError_t launch_det_noise16(const WfsLaunch& a, hipStream_t st) {
+  const int64_t nb = (a.total - a.item0 + 3) / 4;
+  if (nb <= 0) return hipSuccess;
+  switch (a.noise_head) {
+    case 2: hipLaunchKernelGGL((det_noise_kernel<16, 2>), dim3((unsigned)nb), dim3(256), 0, st, a); break;
+    case 6: hipLaunchKernelGGL((det_noise_kernel<16, 6>), dim3((unsigned)nb), dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((det_noise_kernel<16, 4>), dim3((unsigned)nb), dim3(256), 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_wfs_fused(const WfsShape& s, int variant, const WfsLaunch& a, hipStream_t st) {
 #define X(np, fn, cn, dn, lg, sb) \
   if (SHW_SHAPE_MATCH(np, fn, cn, dn, lg, sb)) return launch_one<np, fn, cn, dn, lg, sb>(variant, a, st);
