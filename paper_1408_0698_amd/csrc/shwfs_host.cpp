@@ -437,8 +437,9 @@ static int plan_create(const shw_wfs_config* cfg, int32_t n_wfs, const shw_lgs_g
     }
     p->bytes += t.size() * sizeof(uint16_t);
   }
-  if (p->prec != SHW_PREC_FP32 ||
-      wfs_variant_needs_det_ws(p->shape, wfs_variant_count(p->shape) - 1)) {
+  bool det_ws = p->prec != SHW_PREC_FP32;
+  for (int v = 0; v < wfs_variant_count(p->shape); ++v) det_ws = det_ws || wfs_variant_needs_det_ws(p->shape, v);
+  if (det_ws) {
     // the precision form hands its detector values to det_noise_kernel through this workspace too
     // one chunk holds a frame of every sensor, at least 16384 and at most 65536 items
     int64_t items = (int64_t)n_wfs * p->n_valid;

@@ -173,6 +173,120 @@ __device__ __forceinline__ ItemRef resolve_item(const WfsLaunch& a, int64_t it, 
   return r;
 }
 
+// Noise and centroid of one half of a 16 x 16 detector image held in LDS, by one wavefront: pair
+// block b = 64 half + lane serves pixels b and b + 128 (reading O8's pair blocks), with the
+// per-pixel arithmetic of det_noise_kernel (a HEAD-step lockstep inversion head, then per-wavefront
+// queues for the searches still running and for the rejection sampler).  q_pix and q_val (4 x 128)
+// are this wavefront's queue arrays.  The item's two halves add their FP32 sums into sums[0..2] with
+// LDS atomics and count themselves in sums[3]; the half that completes the item writes the slopes
+// (two partial sums added to zero in either order give the same value).
+constexpr int kHalfPix = 128;
+template <int HEAD>
+__device__ __forceinline__ void noise_half16(const WfsLaunch& a, const ItemRef& ref, int64_t item, uint32_t gsub,
+                                             const float* __restrict__ det, int half, int lane,
+                                             int* __restrict__ q_pix, float* __restrict__ q_val,
+                                             float* __restrict__ sums) {
+  constexpr int DET_N = 16, NJ = 2;
+  constexpr float CD = 0.5f * (float)(DET_N - 1);
+  const bool need_rng = a.noise && a.ph_scale > 0.0f;
+  const int pb = 64 * half + lane;
+  float v[NJ], u[NJ], z[NJ];
+  bool small[NJ];
+  v[0] = det[pb];
+  v[1] = det[pb + kHalfPix];
+  const float scale = a.ph_scale > 0.0f ? a.ph_scale : 1.0f;  // to expected electrons
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    v[j] = scale * v[j];
+    small[j] = need_rng & (v[j] > 0.0f) & (v[j] < kPoissonSplit);
+  }
+  if (need_rng) {
+    const uint4 wd = pair_block((uint32_t)pb, gsub, ref.frame, ref.key0, ref.key1);
+    const float2 zz = read_noise_pair(wd);
+    u[0] = u01(wd.x);
+    z[0] = zz.x;
+    u[1] = u01(wd.y);
+    z[1] = zz.y;
+  } else {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) u[j] = z[j] = 0.0f;
+  }
+  int k[NJ];
+  bool more[NJ];
+  float p0[NJ];
+  poisson_inversion_head<NJ, HEAD>(v, u, small, k, more, p0);
+  float s0 = 0.0f, sx = 0.0f, sy = 0.0f;
+  auto accumulate = [&](int pix, float img) {
+    if (ref.images_it) ref.images_it[pix] = img;
+    const int p = pix / DET_N;
+    const int q = pix - p * DET_N;
+    const float t = fmaxf(img - a.thr, 0.0f);
+    s0 += t;
+    sx = fmaf((float)q - CD, t, sx);
+    sy = fmaf((float)p - CD, t, sy);
+  };
+  auto below = [](uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  };
+  int na = 0, nq = 0;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int pix = pb + kHalfPix * j;
+    const bool big = need_rng && v[j] >= kPoissonSplit;
+    const uint64_t ma = __ballot(more[j]);
+    const uint64_t mb = __ballot(big);
+    if (more[j]) {
+      const int e = na + below(ma);
+      q_pix[e] = pix;
+      q_val[e] = v[j];
+      q_val[kHalfPix + e] = u[j];
+      q_val[2 * kHalfPix + e] = z[j];
+      q_val[3 * kHalfPix + e] = p0[j];
+    } else if (big) {
+      const int e = kHalfPix - 1 - (nq + below(mb));
+      q_pix[e] = pix;
+      q_val[e] = v[j];
+      q_val[2 * kHalfPix + e] = z[j];
+    } else {
+      accumulate(pix, need_rng ? (float)k[j] + a.ron * z[j] : v[j]);
+    }
+    na += __popcll(ma);
+    nq += __popcll(mb);
+  }
+  // the queues are written and read by this wavefront only: order its LDS accesses
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int e = lane; e < na; e += 64) {
+    const int kp = poisson_inversion_from(q_val[e], q_val[kHalfPix + e], q_val[3 * kHalfPix + e]);
+    accumulate(q_pix[e], (float)kp + a.ron * q_val[2 * kHalfPix + e]);
+  }
+  for (int t = lane; t < nq; t += 64) {
+    const int e = kHalfPix - 1 - t;
+    const int pix = q_pix[e];
+    const int kp = poisson_ptrs(q_val[e], (uint32_t)pix, gsub, ref.frame, ref.key0, ref.key1);
+    accumulate(pix, (float)kp + a.ron * q_val[2 * kHalfPix + e]);
+  }
+  // every lane of the wavefront is active here
+  s0 = wave_sum_tree(s0);
+  sx = wave_sum_tree(sx);
+  sy = wave_sum_tree(sy);
+  if (lane == 0) {
+    atomicAdd(&sums[0], s0);
+    atomicAdd(&sums[1], sx);
+    atomicAdd(&sums[2], sy);
+    // LDS operations of one wavefront take effect in order: the other half's sums are in once its
+    // count is
+    if (atomicAdd(&sums[3], 1.0f) == 1.0f) {
+      const float t0 = atomicAdd(&sums[0], 0.0f), tx = atomicAdd(&sums[1], 0.0f), ty = atomicAdd(&sums[2], 0.0f);
+      const bool empty = !(t0 > 0.0f);
+      const float r = __builtin_amdgcn_rcpf(t0);
+      ref.slopes_fw[ref.i] = empty ? 0.0f : tx * r;
+      ref.slopes_fw[a.n_valid + ref.i] = empty ? 0.0f : ty * r;
+      if (a.flags && !a.list) a.flags[item] = empty ? 1 : 0;
+    }
+  }
+}
+
 // LDS floats per item for the given shape.  Split row transforms keep N/2 spectrum rows (rows 0
 // and N/2 packed), whole ones N/2 + 1; the detector-split variants keep no detector stage in LDS.
 // Band-limited variants keep NPX spectrum rows and spread the rebinned detector rows over both planes.
@@ -187,7 +301,7 @@ struct FusedLayout {
   static constexpr int NPIX = DET_N * DET_N;
   static constexpr int DETA = NPIX + 1;                 // detector values, after the queue and its count
   static constexpr int RED = (DETA + NPIX + 1) & ~1;
-  static constexpr int DNEED = DSPLIT ? NPIX + 1 : RED + 6 * CONV_N;
+  static constexpr int DNEED = (DSPLIT || BL) ? NPIX + 1 : RED + 6 * CONV_N;
   static constexpr int PLANE0 = ROWS * ST > DNEED ? ROWS * ST : DNEED;
   static constexpr int PLANE = (PLANE0 + 1) & ~1;
 };
@@ -204,8 +318,9 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   constexpr int HN = CONV_N / 2;             // half length; packed spectrum rows in LDS
   constexpr int ST = CONV_N + 1;             // odd LDS row stride (floats)
   using LY = FusedLayout<NPX, FFT_N, CONV_N, DET_N, SPLIT, DSPLIT, BL>;
-  static_assert(!BL || (LGS && SPLIT && DSPLIT && FFT_N == CONV_N && CONV_N == 4 * NPX),
-                "band-limited path: LGS, split rows, detector split, FFT_N = CONV_N = 4 NPX");
+  static_assert(!BL || (LGS && SPLIT && FFT_N == CONV_N && CONV_N == 4 * NPX),
+                "band-limited path: LGS, split rows, FFT_N = CONV_N = 4 NPX");
+  static_assert(!BL || DSPLIT || DET_N == 16, "band-limited path with noise in the kernel: 16 x 16 detector");
   constexpr int NPIX = LY::NPIX;
   // stage D reuses the imaginary plane: a queue of NPIX pixel indices, its count, then 3 L doubles
   constexpr int QCOUNT = NPIX;
@@ -615,7 +730,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   // ---------------------------------------------------------------- C: rebin
   __syncthreads();  // the planes are free
   int* queue = reinterpret_cast<int*>(im);
-  if (!DSPLIT && l == 0) queue[QCOUNT] = 0;
+  if (!DSPLIT && !BL && l == 0) queue[QCOUNT] = 0;
   // detector row p of the column-rebinned image: plane re, or (BL) rows from DROWS on in plane im
   auto det_row = [&](int p) -> float* {
     return (BL && p >= LY::DROWS) ? im + (p - LY::DROWS) * ST : re + p * ST;
@@ -666,6 +781,53 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
     asm volatile("" : "+v"(sd));
     det_area = a.det_ws + (group * SPB + sd) * NPIX;
   }
+  if constexpr (BL && !DSPLIT) {
+    // noise and centroid in this kernel: the detector values of the block's items go to one LDS
+    // array once every lane has read the planes, then each wavefront takes half images (two
+    // pixels per lane), the block's 2 SPB halves dealt round-robin over its wavefronts
+    float dv[QB];
+    const int p = l / G;
+    const int q0 = QB * (l - p * G);
+    if (active && l < DET_N * G) {
+      const float* row = det_row(p) + (q0 / QB) * KB;
+      float in[KB];
+#pragma unroll
+      for (int t = 0; t < KB; ++t) in[t] = row[t];
+#pragma unroll
+      for (int j = 0; j < QB; ++j) {
+        float det = 0.0f;
+#pragma unroll
+        for (int t = 0; t < KB; ++t) {
+          const float wgt = rebin_weight(CONV_N, DET_N, j, t);
+          if (wgt != 0.0f) det += wgt * in[t];
+        }
+        dv[j] = det;
+      }
+    }
+    __syncthreads();  // every lane has read the planes
+    constexpr int NW = SPB * L / 64;
+    static_assert(SPB * NPIX + 4 * SPB <= SPB * PLANE && NW * 5 * kHalfPix <= SPB * PLANE, "noise stage LDS");
+    float* s_det = s_re;                  // [SPB][NPIX]
+    float* s_sums = s_re + SPB * NPIX;    // [SPB][4]: sums of t, x t, y t and the halves counted
+    if (active && l < DET_N * G) {
+#pragma unroll
+      for (int j = 0; j < QB; ++j) s_det[s * NPIX + p * DET_N + q0 + j] = dv[j];
+    }
+    if (tid < 4 * SPB) s_sums[tid] = 0.0f;
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: item arithmetic on the scalar unit
+    int* q_pix = reinterpret_cast<int*>(s_im) + wave * 5 * kHalfPix;
+    float* q_val = s_im + wave * 5 * kHalfPix + kHalfPix;
+    for (int hh = wave; hh < 2 * SPB; hh += NW) {
+      const int si = hh >> 1;
+      const int64_t it2 = a.item0 + group * SPB + si;
+      if (it2 >= a.total) continue;  // uniform over the wavefront
+      const ItemRef r2 = resolve_item(a, it2, frame_base, NPIX);
+      noise_half16<4>(a, r2, it2, (uint32_t)(r2.w * a.n_valid + r2.i), s_det + si * NPIX, hh & 1, tid & 63, q_pix,
+                      q_val, s_sums + 4 * si);
+    }
+    return;
+  } else {
   if (active && l < DET_N * G) {
     const int p = l / G;
     const int q0 = QB * (l - p * G);
@@ -749,6 +911,7 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
     slopes_fw[i] = empty ? 0.0f : centroid_ratio(tx, t0);
     slopes_fw[a.n_valid + i] = empty ? 0.0f : centroid_ratio(ty, t0);
     if (a.flags && !a.list) a.flags[item] = empty ? 1 : 0;
+  }
   }
 }
 
@@ -994,9 +1157,9 @@ static hipError_t launch_variant(const WfsLaunch& a0, hipStream_t st) {
 // waves-per-EU target, persistent grid, noise in the fused kernel or after it).  Variants
 // from kFirstDetSplit on end the fused kernel at the detector.
 constexpr int kTunedVariants = 11;
-// Band-limited variants (11: persistent, 5 waves per EU; 12: one-shot, 6 waves per EU), for LGS shapes with
-// FFT_N = CONV_N.
-constexpr int kBandLimitedVariants = 2;
+// Band-limited variants (11: persistent, 5 waves per EU; 12: one-shot, 7 waves per EU; 13: as 12 with noise
+// and centroid in the same kernel), for LGS shapes with FFT_N = CONV_N.
+constexpr int kBandLimitedVariants = 3;
 template <int NPX, int FFT_N, int CONV_N, bool LGS>
 constexpr bool band_limited_ok() {
   return LGS && FFT_N == CONV_N && CONV_N == 4 * NPX;
@@ -1041,9 +1204,11 @@ static hipError_t launch_one(int variant, const WfsLaunch& a, hipStream_t st) {
       case 10: return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 1, true, true, false, true>(a, st);
       case 11:
       case 12:
+      case 13:
         if constexpr (band_limited_ok<NPX, FFT_N, CONV_N, LGS>()) {
           if (variant == 11) return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 5, true, true, false, true, true>(a, st);
-          return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 7, false, true, false, true, true>(a, st);
+          if (variant == 12) return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 7, false, true, false, true, true>(a, st);
+          return launch_variant<NPX, FFT_N, CONV_N, DET_N, LGS, SPB, 7, false, true, false, false, true>(a, st);
         }
         return hipErrorInvalidValue;
       default: return hipErrorInvalidValue;
@@ -1080,7 +1245,7 @@ bool wfs_shape_supported(const WfsShape& s) {
 int wfs_variant_count(const WfsShape& s) {
   if (!wfs_shape_supported(s)) return 0;
   const bool bl = s.lgs && s.fft_n == s.conv_n && s.conv_n == 4 * s.npx;
-  if (s.sub) return kSubVariants + (bl ? kBandLimitedVariants : 0);
+  if (s.sub) return kSubVariants + (bl ? 2 : 0);
   if (!(s.conv_n == 40 && s.det_n == 16)) return 1;
   return kTunedVariants + (bl ? kBandLimitedVariants : 0);
 }
@@ -1094,7 +1259,7 @@ bool wfs_variant_params(const WfsShape& s, int v, int32_t* out) {
   };
   static constexpr Row kTuned[] = {{0, 1, 0, 0}, {0, 4, 0, 0}, {1, 1, 0, 0}, {1, 4, 0, 0}, {0, 1, 1, 0},
                                    {0, 4, 1, 0}, {0, 1, 0, 1}, {0, 4, 1, 1}, {1, 1, 0, 1}, {1, 4, 1, 1},
-                                   {1, 1, 1, 1}, {2, 5, 1, 1}, {2, 7, 0, 1}};
+                                   {1, 1, 1, 1}, {2, 5, 1, 1}, {2, 7, 0, 1}, {2, 7, 0, 0}};
   static constexpr Row kSub[] = {{0, 1, 0, 0}, {1, 1, 0, 0}, {1, 4, 1, 1}, {2, 5, 0, 1}, {2, 6, 1, 1}};
   Row r{0, 1, 0, 0};
   if (s.sub) r = kSub[v];
@@ -1120,7 +1285,7 @@ int wfs_default_variant(const WfsShape& s) {
 
 bool wfs_variant_needs_det_ws(const WfsShape& s, int variant) {
   if (s.sub) return variant >= 2;
-  return s.conv_n == 40 && s.det_n == 16 && variant >= kFirstDetSplit;
+  return s.conv_n == 40 && s.det_n == 16 && variant >= kFirstDetSplit && variant != kTunedVariants + 2;
 }
 
 // det_noise_kernel for 16 x 16 detectors over the items [a.item0, a.total) of a.det_ws (the MFMA

@@ -27,13 +27,16 @@ def _plan(cfg, n_wfs):
 # one complex row), so across the two families the noise-free images agree to FP32 rounding only.
 WHOLE_ROWS = (0, 1, 4, 5, 6, 7)
 SPLIT_ROWS = (2, 3, 8, 9, 10)
-BAND_LIMITED = (11, 12)   # the column spectrum from autocorrelations: another rounding family
+BAND_LIMITED = (11, 12, 13)   # the column spectrum from autocorrelations: another rounding family
 # Variants 6-12 take noise and centroid in the separate detector kernel, whose centroid sums are
-# FP32 per lane and a 64-lane tree (variants 0-5: FP64 sums in the fused kernel).  Their images
-# equal those of their row family bitwise; their slopes differ from the FP64 sums' by the FP32
-# rounding of the sums, at most about 20 * 2^-24 of (|sum x t| + |slope| sum t) / sum t, a few
-# 1e-5 detector pixels.
-DETECTOR_KERNEL = (6, 7, 8, 9, 10, 11, 12)
+# FP32 per lane and a 64-lane tree (variants 0-5: FP64 sums in the fused kernel; variant 13: FP32
+# sums over two pixels per lane and a tree per half image, the two halves added in the fused
+# kernel).  Their images equal those of their row family bitwise; their slopes differ between
+# arrangements by the FP32 rounding of the sums, at most about 20 * 2^-24 of
+# (|sum x t| + |slope| sum t) / sum t, a few 1e-5 detector pixels.
+CENTROID_ARRANGEMENT = {v: "fp64" for v in range(6)}
+CENTROID_ARRANGEMENT.update({v: "detector kernel" for v in range(6, 13)})
+CENTROID_ARRANGEMENT[13] = "half images"
 SUM_TOL_PX = 1e-4
 
 
@@ -42,7 +45,7 @@ def _assert_same(torch, got, ref, v, w, images=True):
     centroid in the same kernel, else within SUM_TOL_PX."""
     if images:
         assert torch.equal(got[1], ref[1]), (v, w)
-    if (v in DETECTOR_KERNEL) == (w in DETECTOR_KERNEL):
+    if CENTROID_ARRANGEMENT[v] == CENTROID_ARRANGEMENT[w]:
         assert torch.equal(got[0], ref[0]), (v, w)
     else:
         assert (got[0] - ref[0]).abs().max().item() < SUM_TOL_PX, (v, w)
@@ -63,9 +66,9 @@ def _measure_variants(torch, plan, opd, variants, images=True, **kw):
 def test_variants_agree(torch_dev):
     cfg = G.CFG1.replace(pupil_n=170, n_subap=17)   # 220 valid: ragged last group
     plan = _plan(cfg, 3)
-    assert plan.n_variants == 13
+    assert plan.n_variants == 14
     opd = torch_dev.from_numpy(S.lgs39m_opd(3, 3, pupil_n=170)).cuda()
-    out = _measure_variants(torch_dev, plan, opd, range(13), seed=7, frame0=40)
+    out = _measure_variants(torch_dev, plan, opd, range(14), seed=7, frame0=40)
     for fam in (WHOLE_ROWS, SPLIT_ROWS, BAND_LIMITED):
         for v in fam[1:]:
             _assert_same(torch_dev, out[v], out[fam[0]], v, fam[0])
@@ -83,7 +86,7 @@ def test_persistent_variant_covers_many_groups(torch_dev):
     detector-split variants run the 4 frames in chunks of their workspace."""
     plan = _plan(G.CFG1, 6)
     opd = torch_dev.from_numpy(S.lgs39m_opd(4, 6)).cuda()
-    out = _measure_variants(torch_dev, plan, opd, range(13), images=False, seed=3, frame0=0)
+    out = _measure_variants(torch_dev, plan, opd, range(14), images=False, seed=3, frame0=0)
     for fam in (WHOLE_ROWS, SPLIT_ROWS, BAND_LIMITED):
         for v in fam[1:]:
             _assert_same(torch_dev, out[v], out[fam[0]], v, fam[0], images=False)
@@ -107,7 +110,8 @@ def test_autotune_selects_a_variant(torch_dev, tmp_path, monkeypatch):
     if rec["params"]["noise_kernel"]:
         assert len(rec["ms_per_noise_head"]) == 3
     forms = [plan.variant_params(v)["convolution"] for v in range(plan.n_variants)]
-    assert forms[11] == forms[12] == "band_limited" and forms[0] == "whole_rows" and forms[2] == "split_rows"
+    assert forms[11] == forms[12] == forms[13] == "band_limited" and forms[0] == "whole_rows" and forms[2] == "split_rows"
+    assert plan.variant_params(13)["noise_kernel"] == 0 and plan.variant_params(12)["noise_kernel"] == 1
 
 
 def test_noise_head_changes_no_count(torch_dev):

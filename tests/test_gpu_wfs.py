@@ -98,7 +98,7 @@ def test_noise_free_parity(torch_dev, cfg, n_wfs, nf):
     assert np.array_equal(got["flags"].astype(bool), want["empty"])
 
 
-@pytest.mark.parametrize("variant", [0, 2, 9, 11, 12])
+@pytest.mark.parametrize("variant", [0, 2, 9, 11, 12, 13])
 def test_launch_variant_parity(torch_dev, variant):
     """Every row-transform family (whole, split, band-limited) against the oracle, noise off and on."""
     cfg = small_lgs(13, flags=0)
