@@ -522,6 +522,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--noise-head", type=int, default=0, choices=(0, 2, 4, 6),
                     help="with --no-autotune: the noise kernel's inversion head (default: the plan's, 4)")
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="with --no-autotune: the launch variant (default: the plan's)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before timing, run 5 plain device copies of this many MB (profiler counter scale)")
     args = ap.parse_args()
@@ -557,6 +559,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.variant >= 0:
+        plan.set_variant(args.variant)
     variant = plan.variant
     if args.noise_head:
         plan.set_noise_head(args.noise_head)
