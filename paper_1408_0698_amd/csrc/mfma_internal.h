@@ -12,10 +12,10 @@ constexpr int kPrecBf16 = 1;
 constexpr int kPrecBf16x3 = 2;
 constexpr int kPrecFp16x3 = 3;
 
-// Constant matrices, in 16x16 tiles, in B-operand lane order: entry (tile, lane) holds the
-// four values M[16 b + 4 (lane / 16) + r][16 c + lane % 16], r = 0..3, as hi halves (8 bytes)
-// then lo halves (8 bytes).  N = 40, c0 = 39/2; in-band column j < 19 stands for the frequency
-// k(j) = j (j <= 9) or j - 19 (j >= 10); rows and columns beyond a matrix are zero.
+// Constant matrices, in 16x16 tiles, in B-operand lane order: lane `lane` of a tile owns the
+// four values M[16 b + 4 (lane / 16) + r][16 c + lane % 16], r = 0..3, each split into a hi and
+// a lo half.  N = 40, c0 = 39/2; in-band column j < 19 stands for the frequency k(j) = j (j <= 9)
+// or j - 19 (j >= 10); rows and columns beyond a matrix are zero.
 constexpr int kTabWr = 0;       // W^T, 16 x 48 (3 tiles): W^T[x][u] = exp(-2 pi i (u - c0) x / N), x < 10
 constexpr int kTabWi = 3;
 constexpr int kTabWiNeg = 6;
@@ -29,9 +29,20 @@ constexpr int kTabMur = 30;     // Mu^T, 32 x 16 (2 tiles): Mu^T[j][q] = (1/N) s
 constexpr int kTabMuiNeg = 32;
 constexpr int kMfmaTableTiles = 34;
 
+// The table the kernels read holds ready B operands of the 16x16x32 products: operand `op` of
+// lane `lane` is the 16-byte entry op * 64 + lane, the 4 halves of one tile part followed by the
+// 4 halves of another, so that each operand is one LDS read into consecutive registers.
+// [A|B] hi = (A hi, B hi); a hi operand is always followed by its lo operand.
+constexpr int kOpW = 0;      // + 4 c (c < 3): [Wr|WiNeg] hi, lo; [Wi|Wr] hi, lo of column tile c
+constexpr int kOpD = 12;     // + 4 t (t = 2 tb + tc < 6): [Dr|DiNeg] hi, lo; [Di|Dr] hi, lo
+constexpr int kOpDre = 36;   // + tv (tv < 3): (Dr lo, Dr hi) of tile 2 tv; + 3 + tv: (Di lo, Di hi)
+constexpr int kOpMv = 42;    // [Mvr|MviNeg] hi, lo; [Mvi|Mvr] hi, lo
+constexpr int kOpMu = 46;    // + 2 tb (tb < 2): [Mur|MuiNeg] hi, lo
+constexpr int kMfmaOps = 50;
+
 bool mfma_shape_supported(int npx, int fft_n, int conv_n, int det_n, int prec);
 // Detector values of items [a.item0, a.total) into a.det_ws (chunks of a.det_ws_items items), each
 // chunk followed by det_noise_kernel (photometry, noise, centroid).
-hipError_t launch_wfs_mfma(int prec, bool lgs, const WfsLaunch& a, const uint2* tables, hipStream_t st);
+hipError_t launch_wfs_mfma(int prec, bool lgs, const WfsLaunch& a, const uint4* ops, hipStream_t st);
 
 }  // namespace shw

@@ -40,13 +40,15 @@ typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef _Float16 h2v __attribute__((ext_vector_type(2)));
 typedef __bf16 b2v __attribute__((ext_vector_type(2)));
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 
 // det_noise_kernel over the items of a (wfs_kernels.hip)
 hipError_t launch_det_noise16(const WfsLaunch& a, hipStream_t st);
 
 namespace {
 
-constexpr int kWaves = 4;    // sub-apertures per block
+constexpr int kWaves = 8;    // sub-apertures per block
 constexpr int kN = 40;
 
 // Two floats to packed halves (round to nearest even), as 32 bits: element 0 in the low half.
@@ -68,50 +70,88 @@ __device__ __forceinline__ float2 unpk_f16(uint32_t u) {
   return make_float2((float)v[0], (float)v[1]);
 }
 
-// Data operand, split for the precision variant.
+// Operands.  A complex data tile is one group of 8 halves per lane for each precision part,
+// [re(4) | im(4)], and a real tile one group [hi(4) | lo(4)] (4 VGPRs each), so that every
+// 16x16x32 product reads its A operand from contiguous registers.  A 16x16x32 step sums over 32
+// values of k; two 16x16x16 products with the same output tile become one such step when their
+// k runs are put side by side in both operands: lane group g holds k = 4 g .. 4 g + 3 of the
+// first product in elements 0..3 and of the second in elements 4..7, for A and B alike (any
+// common order of k leaves the sum unchanged).
 template <int PREC>
-struct Op;
+struct Cx;
 template <>
-struct Op<kPrecBf16> {
-  s4 hi;
+struct Cx<kPrecBf16> {
+  uint4 hi;  // [re | im], bf16
 };
 template <>
-struct Op<kPrecBf16x3> {
-  s4 hi, lo;
+struct Cx<kPrecBf16x3> {
+  uint4 hi, lo;  // [re_hi | im_hi], [re_lo | im_lo], bf16; lo = bf16 of the residual
 };
 template <>
-struct Op<kPrecFp16x3> {
-  h4 hi, lo;
+struct Cx<kPrecFp16x3> {
+  uint4 hi, lo;  // fp16; lo = fp16 of 2^11 x the residual
+};
+template <int PREC>
+struct Re;
+template <>
+struct Re<kPrecBf16> {
+  uint2 hi;
+};
+template <>
+struct Re<kPrecBf16x3> {
+  uint4 hl;  // [hi | lo]
+};
+template <>
+struct Re<kPrecFp16x3> {
+  uint4 hl;
 };
 
+// x split into 4 packed hi halves (h) and 4 packed lo halves (l) for the precision variant.
 template <int PREC>
-__device__ __forceinline__ Op<PREC> split(f4 x) {
-  Op<PREC> o;
+__device__ __forceinline__ void split4(f4 x, uint2& h, uint2& l) {
   if constexpr (PREC == kPrecFp16x3) {
     // below the fp16 normal range the whole value goes to the scaled low part, so that no
     // subnormal half reaches the matrix unit
-    float h[4];
+    float v[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) h[r] = fabsf(x[r]) < 6.103515625e-05f ? 0.0f : x[r];
-    const uint32_t p0 = pk_f16(h[0], h[1]), p1 = pk_f16(h[2], h[3]);
+    for (int r = 0; r < 4; ++r) v[r] = fabsf(x[r]) < 6.103515625e-05f ? 0.0f : x[r];
+    const uint32_t p0 = pk_f16(v[0], v[1]), p1 = pk_f16(v[2], v[3]);
     const float2 b0 = unpk_f16(p0), b1 = unpk_f16(p1);
-    const uint32_t l0 = pk_f16((x[0] - b0.x) * 2048.0f, (x[1] - b0.y) * 2048.0f);
-    const uint32_t l1 = pk_f16((x[2] - b1.x) * 2048.0f, (x[3] - b1.y) * 2048.0f);
-    const uint32_t hv[2] = {p0, p1}, lv[2] = {l0, l1};
-    __builtin_memcpy(&o.hi, hv, 8);
-    __builtin_memcpy(&o.lo, lv, 8);
+    h = make_uint2(p0, p1);
+    l = make_uint2(pk_f16((x[0] - b0.x) * 2048.0f, (x[1] - b0.y) * 2048.0f),
+                   pk_f16((x[2] - b1.x) * 2048.0f, (x[3] - b1.y) * 2048.0f));
   } else {
     const uint32_t p0 = pk_bf16(x[0], x[1]), p1 = pk_bf16(x[2], x[3]);
-    const uint32_t hv[2] = {p0, p1};
-    __builtin_memcpy(&o.hi, hv, 8);
+    h = make_uint2(p0, p1);
     if constexpr (PREC == kPrecBf16x3) {
       // the hi halves back as floats: a bf16 is the high 16 bits of its float
       const float b0 = __uint_as_float(p0 << 16), b1 = __uint_as_float(p0 & 0xFFFF0000u);
       const float b2 = __uint_as_float(p1 << 16), b3 = __uint_as_float(p1 & 0xFFFF0000u);
-      const uint32_t lv[2] = {pk_bf16(x[0] - b0, x[1] - b1), pk_bf16(x[2] - b2, x[3] - b3)};
-      __builtin_memcpy(&o.lo, lv, 8);
+      l = make_uint2(pk_bf16(x[0] - b0, x[1] - b1), pk_bf16(x[2] - b2, x[3] - b3));
     }
   }
+}
+
+template <int PREC>
+__device__ __forceinline__ Cx<PREC> split_cx(f4 re, f4 im) {
+  uint2 rh, rl, ih, il;
+  split4<PREC>(re, rh, rl);
+  split4<PREC>(im, ih, il);
+  Cx<PREC> o;
+  o.hi = make_uint4(rh.x, rh.y, ih.x, ih.y);
+  if constexpr (PREC != kPrecBf16) o.lo = make_uint4(rl.x, rl.y, il.x, il.y);
+  return o;
+}
+
+template <int PREC>
+__device__ __forceinline__ Re<PREC> split_re(f4 x) {
+  uint2 h, l;
+  split4<PREC>(x, h, l);
+  Re<PREC> o;
+  if constexpr (PREC == kPrecBf16)
+    o.hi = h;
+  else
+    o.hl = make_uint4(h.x, h.y, l.x, l.y);
   return o;
 }
 
@@ -138,44 +178,89 @@ __device__ __forceinline__ f4 acc_value(const Acc<PREC>& a) {
     return a.c;
 }
 
-// acc += A * B for one 16x16x16 step; B comes from an LDS table entry (hi, lo halves).
-template <int PREC>
-__device__ __forceinline__ void mma(Acc<PREC>& acc, const Op<PREC>& a, const uint2* __restrict__ bt) {
-  const uint4 b = *reinterpret_cast<const uint4*>(bt);
-  if constexpr (PREC == kPrecFp16x3) {
-    h4 bhi, blo;
-    __builtin_memcpy(&bhi, &b.x, 8);
-    __builtin_memcpy(&blo, &b.z, 8);
-    acc.c = __builtin_amdgcn_mfma_f32_16x16x16f16(a.hi, bhi, acc.c, 0, 0, 0);
-    acc.corr = __builtin_amdgcn_mfma_f32_16x16x16f16(a.hi, blo, acc.corr, 0, 0, 0);
-    acc.corr = __builtin_amdgcn_mfma_f32_16x16x16f16(a.lo, bhi, acc.corr, 0, 0, 0);
+// One 16x16x32 step (A, B: 8 halves each) and one 16x16x16 step (4 halves each).
+template <bool F16>
+__device__ __forceinline__ f4 k32(f4 c, uint4 a, uint4 b) {
+  if constexpr (F16) {
+    h8v av, bv;
+    __builtin_memcpy(&av, &a, 16);
+    __builtin_memcpy(&bv, &b, 16);
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, c, 0, 0, 0);
   } else {
-    s4 bhi;
-    __builtin_memcpy(&bhi, &b.x, 8);
-    acc.c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, bhi, acc.c, 0, 0, 0);
-    if constexpr (PREC == kPrecBf16x3) {
-      s4 blo;
-      __builtin_memcpy(&blo, &b.z, 8);
-      acc.c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, blo, acc.c, 0, 0, 0);
-      acc.c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.lo, bhi, acc.c, 0, 0, 0);
-    }
+    b8v av, bv;
+    __builtin_memcpy(&av, &a, 16);
+    __builtin_memcpy(&bv, &b, 16);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+  }
+}
+template <bool F16>
+__device__ __forceinline__ f4 k16(f4 c, uint2 a, uint2 b) {
+  if constexpr (F16) {
+    h4 av, bv;
+    __builtin_memcpy(&av, &a, 8);
+    __builtin_memcpy(&bv, &b, 8);
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(av, bv, c, 0, 0, 0);
+  } else {
+    s4 av, bv;
+    __builtin_memcpy(&av, &a, 8);
+    __builtin_memcpy(&bv, &b, 8);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
   }
 }
 
-// (cr, ci) += (ar + i ai) (Br + i Bi) for one step: tables Br, Bi and -Bi.
+// acc += x.re T1 + x.im T2 for constant tiles T1, T2: o points at this lane's [T1|T2] hi
+// operand, whose lo operand is 64 entries on.
 template <int PREC>
-__device__ __forceinline__ void cmma(Acc<PREC>& cr, Acc<PREC>& ci, const Op<PREC>& ar, const Op<PREC>& ai,
-                                     const uint2* br, const uint2* bi, const uint2* bin) {
-  mma(cr, ar, br);
-  mma(cr, ai, bin);
-  mma(ci, ar, bi);
-  mma(ci, ai, br);
+__device__ __forceinline__ void cx_mac(Acc<PREC>& acc, const Cx<PREC>& x, const uint4* o) {
+  constexpr bool F16 = PREC == kPrecFp16x3;
+  const uint4 bh = o[0];
+  acc.c = k32<F16>(acc.c, x.hi, bh);
+  if constexpr (PREC == kPrecBf16x3) {
+    acc.c = k32<F16>(acc.c, x.hi, o[64]);  // hi x lo
+    acc.c = k32<F16>(acc.c, x.lo, bh);     // lo x hi
+  } else if constexpr (PREC == kPrecFp16x3) {
+    acc.corr = k32<F16>(acc.corr, x.hi, o[64]);
+    acc.corr = k32<F16>(acc.corr, x.lo, bh);
+  }
 }
 
-// Table entry of constant tile `tile` for this lane (16 bytes: 4 hi + 4 lo halves).
-__device__ __forceinline__ const uint2* tab(const uint2* t, int tile, int lane) {
-  return t + ((size_t)tile * 64 + lane) * 2;
+// acc + h += x T for a real data tile x and constant tile T: o points at this lane's (T lo, T hi).
+// The 16x16x16 (hi x hi) products go to their own accumulator h: a chain that alternates
+// 16x16x32 and 16x16x16 steps on one accumulator gave wrong sums.
+template <int PREC>
+__device__ __forceinline__ void re_mac(Acc<PREC>& acc, f4& h, const Re<PREC>& x, const uint4* o) {
+  constexpr bool F16 = PREC == kPrecFp16x3;
+  const uint4 b = o[0];
+  const uint2 bh = make_uint2(b.z, b.w);
+  if constexpr (PREC == kPrecBf16) {
+    h = k16<F16>(h, x.hi, bh);
+  } else {
+    h = k16<F16>(h, make_uint2(x.hl.x, x.hl.y), bh);  // hi x hi
+    if constexpr (PREC == kPrecBf16x3)
+      acc.c = k32<F16>(acc.c, x.hl, b);  // hi x lo + lo x hi
+    else
+      acc.corr = k32<F16>(acc.corr, x.hl, b);
+  }
 }
+
+// Value of a real-operand product: its 16x16x32 accumulator plus its 16x16x16 accumulator.
+template <int PREC>
+__device__ __forceinline__ f4 re_value(const Acc<PREC>& acc, f4 h) {
+  if constexpr (PREC == kPrecBf16)
+    return h;
+  else if constexpr (PREC == kPrecBf16x3)
+    return acc.c + h;
+  else
+    return h + acc.corr * (1.0f / 2048.0f);
+}
+
+// Scheduling fence between steps: without it the compiler issues the operand reads of every
+// later step at once, and the live operands (and copies into aligned register quads) cost
+// spills and about 170 moves per sub-aperture.
+__device__ __forceinline__ void step_fence() { __builtin_amdgcn_sched_barrier(0); }
+
+// This lane's entry of constant operand `op`.
+__device__ __forceinline__ const uint4* opnd(const uint4* t, int op, int lane) { return t + op * 64 + lane; }
 
 // Frequency of in-band column j (j < 19): 0..9, then -9..-1.
 __device__ __forceinline__ int band_k(int j) { return j <= 9 ? j : j - 19; }
@@ -183,10 +268,10 @@ __device__ __forceinline__ int band_k(int j) { return j <= 9 ? j : j - 19; }
 }  // namespace
 
 template <int PREC, bool LGS>
-__global__ __launch_bounds__(64 * kWaves) void wfs_mfma_kernel(const WfsLaunch a, const uint2* __restrict__ tables) {
-  __shared__ uint2 s_tab[kMfmaTableTiles * 64 * 2];
-  // stage the constant tables (hi, lo per lane and tile) in LDS
-  for (int e = threadIdx.x; e < kMfmaTableTiles * 64 * 2; e += 64 * kWaves) s_tab[e] = tables[e];
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))) void wfs_mfma_kernel(const WfsLaunch a, const uint4* __restrict__ ops) {
+  __shared__ uint4 s_tab[kMfmaOps * 64];
+  // stage the constant operands in LDS
+  for (int e = threadIdx.x; e < kMfmaOps * 64; e += 64 * kWaves) s_tab[e] = ops[e];
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: item arithmetic on the scalar unit
@@ -232,31 +317,34 @@ __global__ __launch_bounds__(64 * kWaves) void wfs_mfma_kernel(const WfsLaunch a
   }
   // ---------------------------------------------------------------- spot: P1 = e^T W^T (16 x 48), F = P1^T W^T
   // I = |F|^2 / N^2, split as soon as each tile is formed
-  Op<PREC> Is[3][3];
+  Re<PREC> Is[3][3];
   {
-    const Op<PREC> xr = split<PREC>(er), xi = split<PREC>(ei);
+    const Cx<PREC> x = split_cx<PREC>(er, ei);
     f4 P1r[3], P1i[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+      step_fence();
       Acc<PREC> ar, ai;
       acc_zero(ar);
       acc_zero(ai);
-      cmma(ar, ai, xr, xi, tab(s_tab, kTabWr + c, lane), tab(s_tab, kTabWi + c, lane), tab(s_tab, kTabWiNeg + c, lane));
+      cx_mac(ar, x, opnd(s_tab, kOpW + 4 * c, lane));
+      cx_mac(ai, x, opnd(s_tab, kOpW + 4 * c + 2, lane));
       P1r[c] = acc_value(ar);
       P1i[c] = acc_value(ai);
     }
 #pragma unroll
     for (int tv = 0; tv < 3; ++tv) {
-      const Op<PREC> yr = split<PREC>(P1r[tv]), yi = split<PREC>(P1i[tv]);
+      step_fence();
+      const Cx<PREC> y = split_cx<PREC>(P1r[tv], P1i[tv]);
 #pragma unroll
       for (int tu = 0; tu < 3; ++tu) {
         Acc<PREC> ar, ai;
         acc_zero(ar);
         acc_zero(ai);
-        cmma(ar, ai, yr, yi, tab(s_tab, kTabWr + tu, lane), tab(s_tab, kTabWi + tu, lane),
-             tab(s_tab, kTabWiNeg + tu, lane));
+        cx_mac(ar, y, opnd(s_tab, kOpW + 4 * tu, lane));
+        cx_mac(ai, y, opnd(s_tab, kOpW + 4 * tu + 2, lane));
         const f4 fr = acc_value(ar), fi = acc_value(ai);
-        Is[tv][tu] = split<PREC>((fr * fr + fi * fi) * (1.0f / (float)(kN * kN)));
+        Is[tv][tu] = split_re<PREC>((fr * fr + fi * fi) * (1.0f / (float)(kN * kN)));
       }
     }
   }
@@ -264,29 +352,32 @@ __global__ __launch_bounds__(64 * kWaves) void wfs_mfma_kernel(const WfsLaunch a
   // j < 16 only, the rows of P4 that are used), P4 = P3^T D^T (16 x 32) = I^[k(j1)][k(j2)]
   f4 Hr[2], Hi[2];
   {
-    Op<PREC> p3r[3], p3i[3];
+    Cx<PREC> p3[3];
 #pragma unroll
     for (int tu = 0; tu < 3; ++tu) {
+      step_fence();
       Acc<PREC> ar, ai;
       acc_zero(ar);
       acc_zero(ai);
+      f4 hr = {0.f, 0.f, 0.f, 0.f}, hi = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int tv = 0; tv < 3; ++tv) {
-        mma(ar, Is[tv][tu], tab(s_tab, kTabDr + 2 * tv, lane));
-        mma(ai, Is[tv][tu], tab(s_tab, kTabDi + 2 * tv, lane));
+        re_mac(ar, hr, Is[tv][tu], opnd(s_tab, kOpDre + tv, lane));
+        re_mac(ai, hi, Is[tv][tu], opnd(s_tab, kOpDre + 3 + tv, lane));
       }
-      p3r[tu] = split<PREC>(acc_value(ar));
-      p3i[tu] = split<PREC>(acc_value(ai));
+      p3[tu] = split_cx<PREC>(re_value(ar, hr), re_value(ai, hi));
     }
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj) {
+      step_fence();
       Acc<PREC> ar, ai;
       acc_zero(ar);
       acc_zero(ai);
 #pragma unroll
-      for (int tu = 0; tu < 3; ++tu)
-        cmma(ar, ai, p3r[tu], p3i[tu], tab(s_tab, kTabDr + 2 * tu + tj, lane), tab(s_tab, kTabDi + 2 * tu + tj, lane),
-             tab(s_tab, kTabDiNeg + 2 * tu + tj, lane));
+      for (int tu = 0; tu < 3; ++tu) {
+        cx_mac(ar, p3[tu], opnd(s_tab, kOpD + 4 * (2 * tu + tj), lane));
+        cx_mac(ai, p3[tu], opnd(s_tab, kOpD + 4 * (2 * tu + tj) + 2, lane));
+      }
       Hr[tj] = acc_value(ar);
       Hi[tj] = acc_value(ai);
     }
@@ -318,24 +409,22 @@ __global__ __launch_bounds__(64 * kWaves) void wfs_mfma_kernel(const WfsLaunch a
   // ---------------------------------------------------------------- map: P5 = J^^T Mv^T (32 x 16), Det = Re(P5^T Mu^T)
   f4 det;
   {
-    Op<PREC> p5r[2], p5i[2];
+    Cx<PREC> p5[2];
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj) {
-      const Op<PREC> jr = split<PREC>(Hr[tj]), ji = split<PREC>(Hi[tj]);
+      step_fence();
+      const Cx<PREC> jv = split_cx<PREC>(Hr[tj], Hi[tj]);
       Acc<PREC> ar, ai;
       acc_zero(ar);
       acc_zero(ai);
-      cmma(ar, ai, jr, ji, tab(s_tab, kTabMvr, lane), tab(s_tab, kTabMvi, lane), tab(s_tab, kTabMviNeg, lane));
-      p5r[tj] = split<PREC>(acc_value(ar));
-      p5i[tj] = split<PREC>(acc_value(ai));
+      cx_mac(ar, jv, opnd(s_tab, kOpMv, lane));
+      cx_mac(ai, jv, opnd(s_tab, kOpMv + 2, lane));
+      p5[tj] = split_cx<PREC>(acc_value(ar), acc_value(ai));
     }
     Acc<PREC> ad;
     acc_zero(ad);
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj) {
-      mma(ad, p5r[tj], tab(s_tab, kTabMur + tj, lane));
-      mma(ad, p5i[tj], tab(s_tab, kTabMuiNeg + tj, lane));
-    }
+    for (int tj = 0; tj < 2; ++tj) cx_mac(ad, p5[tj], opnd(s_tab, kOpMu + 2 * tj, lane));
     det = acc_value(ad);
   }
   // ---------------------------------------------------------------- detector values for det_noise_kernel
@@ -348,7 +437,7 @@ bool mfma_shape_supported(int npx, int fft_n, int conv_n, int det_n, int prec) {
   return npx == 10 && fft_n == 40 && conv_n == 40 && det_n == 16 && prec >= kPrecBf16 && prec <= kPrecFp16x3;
 }
 
-hipError_t launch_wfs_mfma(int prec, bool lgs, const WfsLaunch& a0, const uint2* tables, hipStream_t st) {
+hipError_t launch_wfs_mfma(int prec, bool lgs, const WfsLaunch& a0, const uint4* ops, hipStream_t st) {
   const int64_t step = a0.det_ws_items;
   if (!a0.det_ws || step <= 0) return hipErrorInvalidValue;
   for (int64_t i0 = a0.item0; i0 < a0.total; i0 += step) {
@@ -360,7 +449,7 @@ hipError_t launch_wfs_mfma(int prec, bool lgs, const WfsLaunch& a0, const uint2*
     bool launched = false;
 #define L(P, G)                                                          \
   if (!launched && prec == P && lgs == G) {                              \
-    hipLaunchKernelGGL((wfs_mfma_kernel<P, G>), g, b, 0, st, a, tables); \
+    hipLaunchKernelGGL((wfs_mfma_kernel<P, G>), g, b, 0, st, a, ops); \
     launched = true;                                                     \
   }
     L(kPrecBf16, true)

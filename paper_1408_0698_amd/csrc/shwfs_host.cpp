@@ -71,7 +71,7 @@ struct shw_wfs_plan {
   int32_t variant = 0;
   int32_t noise_head = 4;        // lockstep inversion steps of det_noise_kernel: 2, 4 or 6
   int32_t prec = 0;              // SHW_PREC_*: 0 = FP32 register FFTs, else MFMA DFT GEMMs
-  uint2* d_mfma_tab = nullptr;   // constant matrices of the MFMA variant
+  uint4* d_mfma_tab = nullptr;   // constant operands of the MFMA variant
   FrameWork* d_list = nullptr;   // work list of sh_wfs_measure_batch
   int32_t list_cap = 0;
   // pinned host staging of the work lists: kListRing slots of list_cap entries, each reusable once
@@ -286,12 +286,13 @@ static std::vector<uint16_t> mfma_tables(const shw_wfs_config* c, int prec) {
     const double cj = folded && j > 0 ? 2.0 : 1.0;
     return cj * s / N;
   };
-  std::vector<uint16_t> t((size_t)kMfmaTableTiles * 64 * 8, 0);
+  // tiles: part (0 hi, 1 lo) of tile `tile` for lane `lane` = 4 halves at ((tile * 2 + part) * 64 + lane) * 4
+  std::vector<uint16_t> t((size_t)kMfmaTableTiles * 2 * 64 * 4, 0);
   auto put = [&](int tile, int lane, int r, double v) {
     uint16_t h, l;
     split_const(v, prec, &h, &l);
-    t[((size_t)tile * 64 + lane) * 8 + r] = h;
-    t[((size_t)tile * 64 + lane) * 8 + 4 + r] = l;
+    t[(((size_t)tile * 2 + 0) * 64 + lane) * 4 + r] = h;
+    t[(((size_t)tile * 2 + 1) * 64 + lane) * 4 + r] = l;
   };
   for (int lane = 0; lane < 64; ++lane)
     for (int r = 0; r < 4; ++r) {
@@ -315,7 +316,36 @@ static std::vector<uint16_t> mfma_tables(const shw_wfs_config* c, int prec) {
         put(kTabMuiNeg + tb, lane, r, Mm(2, 16 * tb + kr, nc, false));
       }
     }
-  return t;
+  // operands: (tile a, part pa) then (tile b, part pb), 8 halves per lane
+  std::vector<uint16_t> o((size_t)kMfmaOps * 64 * 8, 0);
+  auto op = [&](int idx, int a, int pa, int b, int pb) {
+    for (int lane = 0; lane < 64; ++lane)
+      for (int r = 0; r < 4; ++r) {
+        o[((size_t)idx * 64 + lane) * 8 + r] = t[(((size_t)a * 2 + pa) * 64 + lane) * 4 + r];
+        o[((size_t)idx * 64 + lane) * 8 + 4 + r] = t[(((size_t)b * 2 + pb) * 64 + lane) * 4 + r];
+      }
+  };
+  // a complex pair [A|B]: hi operand then lo operand
+  auto pair = [&](int idx, int a, int b) {
+    op(idx, a, 0, b, 0);
+    op(idx + 1, a, 1, b, 1);
+  };
+  for (int c = 0; c < 3; ++c) {
+    pair(kOpW + 4 * c, kTabWr + c, kTabWiNeg + c);
+    pair(kOpW + 4 * c + 2, kTabWi + c, kTabWr + c);
+  }
+  for (int tt = 0; tt < 6; ++tt) {
+    pair(kOpD + 4 * tt, kTabDr + tt, kTabDiNeg + tt);
+    pair(kOpD + 4 * tt + 2, kTabDi + tt, kTabDr + tt);
+  }
+  for (int tv = 0; tv < 3; ++tv) {
+    op(kOpDre + tv, kTabDr + 2 * tv, 1, kTabDr + 2 * tv, 0);
+    op(kOpDre + 3 + tv, kTabDi + 2 * tv, 1, kTabDi + 2 * tv, 0);
+  }
+  pair(kOpMv, kTabMvr, kTabMviNeg);
+  pair(kOpMv + 2, kTabMvi, kTabMvr);
+  for (int tb = 0; tb < 2; ++tb) pair(kOpMu + 2 * tb, kTabMur + tb, kTabMuiNeg + tb);
+  return o;
 }
 
 // ---------------------------------------------------------------- plan
