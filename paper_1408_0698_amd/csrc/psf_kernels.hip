@@ -21,7 +21,7 @@
 // values instead of 40, which keeps the kernels free of register spills.
 //
 // Row pass: 4 rows per block of 320 lanes; each lane of a pair computes half
-// of the row's phases and swaps them with its partner.  The intermediate is
+// of the row's phases (all its OPD loads issued first) and swaps them with its partner.  The intermediate is
 // stored in column blocks of 8: element (frame f, row y, column u) of T sits
 // at ((f * M/8 + u/8) * pupil_n + y) * 8 + u % 8, so that rows write whole
 // 64-byte runs and the 8 columns of a column block are one contiguous region.
@@ -30,6 +30,9 @@
 // 20 outputs, so no barrier), one read-modify-write of the accumulator per
 // call; the on-axis sample of each frame is the Strehl ratio.  A 4-waves-per-
 // SIMD register target (128 VGPRs, a few spilled) lets 3 blocks share a CU.
+// Both passes have a form for pupil_n = M/2 (the Nyquist-sampled PSF), where
+// every sample of the pruned transforms lies in the pupil grid, so its loads
+// need no bounds masks.
 #include <hip/hip_runtime.h>
 
 #include "psf_internal.h"
@@ -69,11 +72,12 @@ __device__ __forceinline__ void line_transform(const float2 (&v)[kNZ], float2 (&
   // four-step twiddle W_M^(n2 k1), k1 = 2k + h: exact every 4 steps, products of W_M^(2 n2) between
   {
     const int n2 = q;
-    const float sr = -(float)((2 * n2) % kM) / (float)kM;
+    constexpr float kInvM = 1.0f / (float)kM;
+    const float sr = -(float)(2 * n2) * kInvM;  // 2 n2 < M
     const float2 step = make_float2(__builtin_amdgcn_cosf(sr), __builtin_amdgcn_sinf(sr));
 #pragma unroll
     for (int b = 0; b < kNZ / 4; ++b) {
-      const float rev = -(float)((n2 * (8 * b + h)) % kM) / (float)kM;
+      const float rev = -(float)(n2 * (8 * b + h)) * kInvM;  // n2 (8 b + h) < M
       float2 t = make_float2(__builtin_amdgcn_cosf(rev), __builtin_amdgcn_sinf(rev));
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -110,6 +114,8 @@ __device__ __forceinline__ void line_transform(const float2 (&v)[kNZ], float2 (&
 
 }  // namespace
 
+// FULL: pupil_n = M / 2, so every sample 40 n1 + q (n1 < 20) lies inside the grid.
+template <bool FULL>
 __global__ __launch_bounds__(kLines * kP) void psf_rows_kernel(const PsfLaunch a, int64_t f0, int nf, int64_t nrows,
                                                                float2* __restrict__ T) {
   __shared__ float s_pl[kLines * kQ * kST];
@@ -128,22 +134,25 @@ __global__ __launch_bounds__(kLines * kP) void psf_rows_kernel(const PsfLaunch a
     const float* src = a.opd + star * a.star_stride + (f0 + fl) * a.frame_stride + (int64_t)y * a.row_pitch;
     const float by = (float)y + 0.5f - a.half_n;
     const float by2 = by * by;
+    // every load is issued before any is used (at a clamped address), and the samples outside
+    // the pupil, the annulus or the last block's rows are masked afterwards
+    float ov[kNZ / 2];
+#pragma unroll
+    for (int i = 0; i < kNZ / 2; ++i) ov[i] = src[FULL ? kQ * (2 * i + h) + q : min(kQ * (2 * i + h) + q, a.pupil_n - 1)];
 #pragma unroll
     for (int i = 0; i < kNZ / 2; ++i) {
       const int n1 = 2 * i + h;
       const int x = kQ * n1 + q;
-      float2 e = make_float2(0.0f, 0.0f);
-      if (active && x < a.pupil_n) {
-        const float bx = (float)x + 0.5f - a.half_n;
-        const float r2 = bx * bx + by2;
-        if (r2 <= a.r2_outer && r2 >= a.r2_inner) {
-          double wv = (double)src[x] * a.inv_lambda + 0.5 * (double)(x + y);
-          wv = __builtin_amdgcn_fract(wv);  // wv - floor(wv), one instruction
-          // hardware sine and cosine take revolutions: exp(2 pi i wv) after the FP64 reduction
-          const float fw = (float)wv;
-          e = make_float2(__builtin_amdgcn_cosf(fw), __builtin_amdgcn_sinf(fw));
-        }
-      }
+      const float bx = (float)x + 0.5f - a.half_n;
+      const float r2 = bx * bx + by2;
+      const bool lit = active & (FULL || x < a.pupil_n) & (r2 <= a.r2_outer) & (r2 >= a.r2_inner);
+      double wv = (double)ov[i] * a.inv_lambda + 0.5 * (double)(x + y);
+      wv = __builtin_amdgcn_fract(wv);  // wv - floor(wv), one instruction
+      // hardware sine and cosine take revolutions: exp(2 pi i wv) after the FP64 reduction
+      const float fw = (float)wv;
+      // a select, not a product with a 0/1 amplitude: samples outside the pupil may hold anything
+      const float cw = __builtin_amdgcn_cosf(fw), sw = __builtin_amdgcn_sinf(fw);
+      const float2 e = make_float2(lit ? cw : 0.0f, lit ? sw : 0.0f);
       const float2 o = pair_swap(e);  // the partner's sample 2 i + (1 - h)
       v[2 * i] = h ? o : e;
       v[2 * i + 1] = h ? e : o;
@@ -152,13 +161,18 @@ __global__ __launch_bounds__(kLines * kP) void psf_rows_kernel(const PsfLaunch a
   float2 x[kNZ];
   line_transform(v, x, pl, q, h);
   if (active) {
+    // column q + 40 (c + 20 h): its column block advances by 5 per c and its place in the block
+    // stays q % 8, so the outputs are 40 pupil_n elements apart
+    float2* dst = T + t_index(sf, a.pupil_n, y, q + kQ * kNZ * h);
+    const int64_t step = (int64_t)(kQ / kCB) * a.pupil_n * kCB;
 #pragma unroll
-    for (int c = 0; c < kNZ; ++c) T[t_index(sf, a.pupil_n, y, q + kQ * (c + kNZ * h))] = x[c];
+    for (int c = 0; c < kNZ; ++c) dst[c * step] = x[c];
   }
 }
 
 // Column pass.  The two halves of a column block (4 columns each) go to blocks 8 apart in launch
 // order, which the dispatcher places on the same XCD, so each 64-byte run is fetched into one L2.
+template <bool FULL>
 __global__ __launch_bounds__(kLines * kP) __attribute__((amdgpu_waves_per_eu(4))) void psf_cols_kernel(const PsfLaunch a, int64_t f0, int nf,
                                                                const float2* __restrict__ T, float* __restrict__ acc,
                                                                float* __restrict__ strehl) {
@@ -179,12 +193,12 @@ __global__ __launch_bounds__(kLines * kP) __attribute__((amdgpu_waves_per_eu(4))
   for (int c = 0; c < kNZ; ++c) sum[q + kQ * (c + kNZ * h)] = 0.0f;
   for (int fl = 0; fl < nf; ++fl) {
     const int64_t sf = (int64_t)star * nf + fl;
+    // rows 40 n1 + q of column u, 40 x 8 elements apart; with FULL every row is inside the pupil
+    const float2* src = T + t_index(sf, a.pupil_n, q, u);
     float2 v[kNZ];
 #pragma unroll
-    for (int n1 = 0; n1 < kNZ; ++n1) {
-      const int yy = kQ * n1 + q;
-      v[n1] = yy < a.pupil_n ? T[t_index(sf, a.pupil_n, yy, u)] : make_float2(0.0f, 0.0f);
-    }
+    for (int n1 = 0; n1 < kNZ; ++n1)
+      v[n1] = FULL || kQ * n1 + q < a.pupil_n ? src[n1 * kQ * kCB] : make_float2(0.0f, 0.0f);
     float2 x[kNZ];
     line_transform(v, x, pl, q, h);
 #pragma unroll
@@ -208,12 +222,19 @@ hipError_t launch_psf_chunk(const PsfLaunch& a, int n_stars, int64_t f0, int nf,
                             float* strehl, hipStream_t st) {
   const int64_t nrows = (int64_t)n_stars * nf * a.pupil_n;
   const int64_t rb = (nrows + kLines - 1) / kLines;
-  hipLaunchKernelGGL(psf_rows_kernel, dim3((unsigned)rb), dim3(kLines * kP), 0, st, a, f0, nf, nrows, T);
+  const bool full = a.pupil_n == kM / 2;
+  if (full)
+    hipLaunchKernelGGL(psf_rows_kernel<true>, dim3((unsigned)rb), dim3(kLines * kP), 0, st, a, f0, nf, nrows, T);
+  else
+    hipLaunchKernelGGL(psf_rows_kernel<false>, dim3((unsigned)rb), dim3(kLines * kP), 0, st, a, f0, nf, nrows, T);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   static_assert((kM / kLines) % 16 == 0, "column blocks pair up 8 apart");
-  hipLaunchKernelGGL(psf_cols_kernel, dim3((unsigned)(n_stars * (kM / kLines))), dim3(kLines * kP), 0, st, a, f0, nf,
-                     (const float2*)T, acc, strehl);
+  const dim3 cg((unsigned)(n_stars * (kM / kLines)));
+  if (full)
+    hipLaunchKernelGGL(psf_cols_kernel<true>, cg, dim3(kLines * kP), 0, st, a, f0, nf, (const float2*)T, acc, strehl);
+  else
+    hipLaunchKernelGGL(psf_cols_kernel<false>, cg, dim3(kLines * kP), 0, st, a, f0, nf, (const float2*)T, acc, strehl);
   return hipGetLastError();
 }
 
