@@ -616,7 +616,7 @@ def main():
                 "frac": fp32 / PEAK_FP32_TFLOPS,
                 "traffic": ctr["hbm_bytes_per_frame"] * B,
                 "flops": "executed FP32 (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F32, FMA = 2) per frame, "
-                         "counters in profiles/wfs_measure_lgs39m.md",
+                         "counters in profiles/wfs_measure_lgs39m_valu.md",
                 "fp64_tflops": ctr["fp64_flop_per_frame"] * B / launch_s / 1e12,
                 "valu_issue_frac": ctr["valu_lane_ops_per_frame"] * B / launch_s / PEAK_VALU_LANE_OPS,
                 "nominal_tflops": nominal,
