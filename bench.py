@@ -357,13 +357,15 @@ def ex_psf_extras(stream):
         for s_ in range(1, 9):
             acc[s_].copy_(acc[0])
         radii = [2.0 * (k + 1) for k in range(20)]
-        ms_ee = _time(lambda k: plans[0].encircled_energy(acc, radii, stream=stream), 5, stream)
+        # the first call grows the plan's workspaces: outside the timed calls
         ee = plans[0].encircled_energy(acc, radii, stream=stream)
+        ms_ee = _time(lambda k: plans[0].encircled_energy(acc, radii, stream=stream), 5, stream)
 
         def poly_step(k):
             poly.zero_()
             shwfs.polychromatic_psf(plans, (0.5, 0.2, 0.3), opd, poly, stream=stream)
 
+        poly_step(0)
         ms_poly = _time(poly_step, 2, stream)
     out["ee_9psf_20radii_ms"] = ms_ee
     out["ee_GBps"] = 9 * 1600 * 1600 * 4 / (ms_ee * 1e-3) / 1e9
