@@ -115,3 +115,33 @@ def test_batch_call_on_mfma_plan_is_refused_and_harmless(torch_dev, reference):
     plan.measure(d, sl2)
     torch_dev.cuda.synchronize()
     assert torch_dev.equal(sl1, sl2)
+
+
+@pytest.mark.parametrize("name", ["bf16x3", "fp16x3"])
+def test_full_lgs_frame_sampled(torch_dev, name):
+    """The split variants on the full 6-LGS 80x80 frame (the shape the precision extra of the bench
+    times); the oracle recomputes a sample of sub-apertures of every sensor.  Noise off for both;
+    noise on for fp16 hi+lo, whose expected electrons are within the 1e-5 that the count comparison
+    accepts at a Poisson tie (bf16 hi+lo reaches about 1e-5 of a spot's peak, more than that for
+    its faint pixels, so its counts may differ at ties the check cannot explain)."""
+    from tests.test_gpu_wfs import assert_images_close, assert_slopes_close, check_noisy, run_gpu, screen_opd
+    base = G.CFG1
+    launch = G.launch_positions(base, 6)
+    opd = screen_opd(base, 1, 6)
+    quiet_cfg = base.replace(flags=VARIANTS[name] << 4)
+    noisy_cfg = base.replace(flags=base.flags | (VARIANTS[name] << 4))
+    quiet = run_gpu(torch_dev, quiet_cfg, 6, launch, opd, frame0=3)
+    sens_q = OW.Sensor(base.replace(flags=0), 6, launch)
+    sens_n = OW.Sensor(base, 6, launch)
+    rng = np.random.default_rng(12)
+    sub = np.unique(np.concatenate([rng.choice(sens_q.n_valid, 50, replace=False), [0, sens_q.n_valid - 1]]))
+    want_q = sens_q.measure(opd, frame0=3, subset=sub)
+    assert_images_close(quiet["images"][:, :, sub], want_q["images"])
+    assert_slopes_close(quiet["slopes"][..., sub], want_q["slopes"])
+    if name != "fp16x3":
+        return
+    noisy = run_gpu(torch_dev, noisy_cfg, 6, launch, opd, seed=G.NOISE_SEED, frame0=3)
+    sens_n._khat = sens_q._khat
+    want_n = sens_n.measure(opd, seed=G.NOISE_SEED, frame0=3, subset=sub)
+    g = dict(images=noisy["images"][:, :, sub], slopes=noisy["slopes"][..., sub])
+    check_noisy(noisy_cfg, 6, launch, g, want_n, G.NOISE_SEED, 3, lambda w: w * sens_n.n_valid + sub)
