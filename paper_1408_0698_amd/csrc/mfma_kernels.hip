@@ -27,7 +27,10 @@
 //   BF16   : A_hi B_hi
 //   BF16X3 : A_hi B_hi + A_hi B_lo + A_lo B_hi (bf16 hi, bf16 of the residual)
 //   FP16X3 : A_hi B_hi + 2^-11 (A_hi B_lo' + A_lo' B_hi) with lo' = fp16(2^11 residual)
-// with FP32 accumulation; the phase reduction stays FP64.
+// with FP32 accumulation; the phase reduction stays FP64.  The products run
+// as 16x16x32 steps, two 16x16x16 products side by side along k (the
+// full-rate form of gfx950's matrix cores), from a table of ready B operands
+// that the host builds and each block stages in LDS once.
 #include <hip/hip_runtime.h>
 
 #include "mfma_internal.h"
