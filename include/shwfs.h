@@ -261,10 +261,13 @@ int shw_wfs_plan_destroy(shw_wfs_plan* plan);
  * FP32 sums in the second kernel: slopes within 1e-4 pixel of each other);
  * the row-transform families differ by FP32 rounding (about 1e-7 of an
  * image).  Band-limited variants
- * (LGS with fft_n = conv_n = 4 * sub-aperture pixels: 11 and 12, sodium
+ * (LGS with fft_n = conv_n = 4 * sub-aperture pixels: 11, 12 and 13, sodium
  * plans 3 and 4) compute the column spectrum of the spot from
  * autocorrelations of the row transforms and filter only the rows inside
- * the spot's band.  New plans start on the fastest measured variant: 12 for
+ * the spot's band; 13 (16 x 16 detector) takes noise and centroid in the
+ * fused kernel, with the same per-pixel noise and FP32 sums as the second
+ * kernel, and keeps no detector workspace.  New plans start on the fastest
+ * measured variant: 12 for
  * band-limited 40-point shapes, 9 for the other 40-point shapes, 4 for
  * band-limited sodium plans, 2 for the other sodium plans, 0 otherwise.
  * shw_wfs_plan_autotune times every variant on the given inputs
