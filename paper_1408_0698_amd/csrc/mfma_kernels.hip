@@ -214,17 +214,20 @@ __device__ __forceinline__ f4 k16(f4 c, uint2 a, uint2 b) {
 // acc += x.re T1 + x.im T2 for constant tiles T1, T2: o points at this lane's [T1|T2] hi
 // operand, whose lo operand is 64 entries on.
 template <int PREC>
-__device__ __forceinline__ void cx_mac(Acc<PREC>& acc, const Cx<PREC>& x, const uint4* o) {
+__device__ __forceinline__ void cx_mac(Acc<PREC>& acc, const Cx<PREC>& x, uint4 bh, uint4 bl) {
   constexpr bool F16 = PREC == kPrecFp16x3;
-  const uint4 bh = o[0];
   acc.c = k32<F16>(acc.c, x.hi, bh);
   if constexpr (PREC == kPrecBf16x3) {
-    acc.c = k32<F16>(acc.c, x.hi, o[64]);  // hi x lo
-    acc.c = k32<F16>(acc.c, x.lo, bh);     // lo x hi
+    acc.c = k32<F16>(acc.c, x.hi, bl);  // hi x lo
+    acc.c = k32<F16>(acc.c, x.lo, bh);  // lo x hi
   } else if constexpr (PREC == kPrecFp16x3) {
-    acc.corr = k32<F16>(acc.corr, x.hi, o[64]);
+    acc.corr = k32<F16>(acc.corr, x.hi, bl);
     acc.corr = k32<F16>(acc.corr, x.lo, bh);
   }
+}
+template <int PREC>
+__device__ __forceinline__ void cx_mac(Acc<PREC>& acc, const Cx<PREC>& x, const uint4* o) {
+  cx_mac(acc, x, o[0], PREC == kPrecBf16 ? o[0] : o[64]);
 }
 
 // acc + h += x T for a real data tile x and constant tile T: o points at this lane's (T lo, T hi).
@@ -335,17 +338,23 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))
       P1r[c] = acc_value(ar);
       P1i[c] = acc_value(ai);
     }
+    Cx<PREC> y[3];
 #pragma unroll
-    for (int tv = 0; tv < 3; ++tv) {
+    for (int tv = 0; tv < 3; ++tv) y[tv] = split_cx<PREC>(P1r[tv], P1i[tv]);
+#pragma unroll
+    for (int tu = 0; tu < 3; ++tu) {
       step_fence();
-      const Cx<PREC> y = split_cx<PREC>(P1r[tv], P1i[tv]);
+      // the four operands of column tile tu, read once for the three row tiles
+      const uint4* ow = opnd(s_tab, kOpW + 4 * tu, lane);
+      const uint4 rh = ow[0], rl = PREC == kPrecBf16 ? rh : ow[64];
+      const uint4 ih = ow[128], il = PREC == kPrecBf16 ? ih : ow[192];
 #pragma unroll
-      for (int tu = 0; tu < 3; ++tu) {
+      for (int tv = 0; tv < 3; ++tv) {
         Acc<PREC> ar, ai;
         acc_zero(ar);
         acc_zero(ai);
-        cx_mac(ar, y, opnd(s_tab, kOpW + 4 * tu, lane));
-        cx_mac(ai, y, opnd(s_tab, kOpW + 4 * tu + 2, lane));
+        cx_mac(ar, y[tv], rh, rl);
+        cx_mac(ai, y[tv], ih, il);
         const f4 fr = acc_value(ar), fi = acc_value(ai);
         Is[tv][tu] = split_re<PREC>((fr * fr + fi * fi) * (1.0f / (float)(kN * kN)));
       }
