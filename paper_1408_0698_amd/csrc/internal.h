@@ -21,6 +21,10 @@ struct WfsLaunch {
   int64_t row_pitch, wfs_stride, frame_stride;
   const int32_t* valid_idx;  // [n_valid] row-major sub-aperture index
   const float* khat;         // [n_wfs * n_valid][conv_n/2 + 1][conv_n] (LGS) or null
+  // band-limited shapes (conv_n = fft_n = 4 npx): the in-band part of K^ that those variants read,
+  // [n_wfs * n_valid][npx][2 npx - 1], row k < npx holding columns 0 .. npx-1 then
+  // conv_n - npx + 1 .. conv_n - 1 (the frequencies 0 .. npx-1 and -(npx-1) .. -1); else null
+  const float* khat_band;
   float* slopes;             // [items / n_valid][2][n_valid]
   float* images;             // nullable [items][det_n][det_n]
   uint8_t* flags;            // nullable [items]
@@ -96,5 +100,9 @@ hipError_t launch_counter_add(uint64_t* d_counter, uint64_t inc, hipStream_t st)
 // Kernel spectra: params [n][3] = (sigma_par, sigma_perp, psi) in conv-grid
 // pixels / radians (device, FP64); out [n][conv_n/2+1][conv_n] FP32, scaled by 1/conv_n^2.
 hipError_t launch_lgs_spectra(int conv_n, const double* d_params, int64_t n, float* d_out, hipStream_t st);
+
+// In-band copy of the kernel spectra for the band-limited variants (layout of WfsLaunch::khat_band)
+// from khat [n][conv_n/2+1][conv_n]; conv_n = 4 npx.
+hipError_t launch_khat_band(int conv_n, int npx, int64_t n, const float* d_khat, float* d_band, hipStream_t st);
 
 }  // namespace shw

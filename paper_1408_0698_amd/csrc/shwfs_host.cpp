@@ -66,6 +66,7 @@ struct shw_wfs_plan {
   int device = 0;
   int32_t* d_valid = nullptr;
   float* d_khat = nullptr;
+  float* d_khat_band = nullptr;  // in-band K^ rows of the band-limited variants, or null
   size_t bytes = 0;
   std::vector<int32_t> valid;
   int32_t variant = 0;
@@ -357,6 +358,7 @@ extern "C" int shw_wfs_plan_destroy(shw_wfs_plan* p) {
   if (cur != p->device) (void)hipSetDevice(p->device);
   if (p->d_valid) (void)hipFree(p->d_valid);
   if (p->d_khat) (void)hipFree(p->d_khat);
+  if (p->d_khat_band) (void)hipFree(p->d_khat_band);
   if (p->d_T) (void)hipFree(p->d_T);
   for (int k = 0; k < kListRing; ++k) {
     if (p->ring_pending[k]) (void)hipEventSynchronize(p->ring_ev[k]);  // uploads out of the host ring done
@@ -518,13 +520,19 @@ static int plan_create(const shw_wfs_config* cfg, int32_t n_wfs, const shw_lgs_g
     if (e == hipSuccess) e = hipMemcpy(d_params, params.data(), sizeof(double) * params.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&p->d_khat, sizeof(float) * (size_t)n * H * cfg->conv_n);
     if (e == hipSuccess) e = launch_lgs_spectra(cfg->conv_n, d_params, n, p->d_khat, nullptr);
+    // the band-limited variants read only the in-band part of K^, kept as a compact copy
+    const int npx = p->npx;
+    const bool band = cfg->fft_n == cfg->conv_n && cfg->conv_n == 4 * npx;
+    const size_t band_floats = band ? (size_t)n * npx * (2 * npx - 1) : 0;
+    if (e == hipSuccess && band) e = hipMalloc(&p->d_khat_band, sizeof(float) * band_floats);
+    if (e == hipSuccess && band) e = launch_khat_band(cfg->conv_n, npx, n, p->d_khat, p->d_khat_band, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (d_params) (void)hipFree(d_params);
     if (e != hipSuccess) {
       shw_wfs_plan_destroy(p);
       return hip_fail(e, "kernel spectra");
     }
-    p->bytes += sizeof(float) * (size_t)n * H * cfg->conv_n;
+    p->bytes += sizeof(float) * ((size_t)n * H * cfg->conv_n + band_floats);
   }
   *out = p;
   return ok();
@@ -569,6 +577,7 @@ static WfsLaunch base_launch(const shw_wfs_plan* p) {
   WfsLaunch a{};
   a.valid_idx = p->d_valid;
   a.khat = p->d_khat;
+  a.khat_band = p->d_khat_band;
   a.n_valid = p->n_valid;
   a.n_wfs = p->n_wfs;
   a.n_subap = c.n_subap;

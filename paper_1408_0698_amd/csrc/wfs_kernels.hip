@@ -580,12 +580,15 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
 #pragma unroll
           for (int t = 0; t < M4; ++t) xq[t] = make_float2(re[r4 * ST + 4 * t + q], im[r4 * ST + 4 * t + q]);
           RegFFT<M4, -1>::run(xq);
-          // K^ row r4 at samples c and c + 3N/4, all read before the first is used
+          // K^ row r4 at samples c and c + 3N/4 (sample 3N/4 is outside the band), from the
+          // in-band copy: 2 NPX - 1 values per row, all read before the first is used
+          constexpr int KB = 2 * NPX - 1;
+          const float* kb = a.khat_band + ((int64_t)(w * a.n_valid + i) * NPX + r4) * KB;
           float k0[M4], k3[M4];
 #pragma unroll
           for (int c = 0; c < M4; ++c) {
-            k0[c] = kh_item[r4 * CONV_N + c];
-            k3[c] = c > 0 ? kh_item[r4 * CONV_N + 3 * M4 + c] : 0.0f;  // sample 3N/4 is outside the band
+            k0[c] = kb[c];
+            k3[c] = c > 0 ? kb[NPX - 1 + c] : 0.0f;
           }
           // sample c + 3N/4 is S3 = sum_q i^q v_q (v_q = W_N^(q c) X_q[c]); the lane's share of its
           // filtered value, conj(i^q) K3 S3, is K3 (d + i ps(d)) on even lanes and K3 (d - i ps(d))
@@ -1391,6 +1394,28 @@ __global__ __launch_bounds__(256) void lgs_spectra_kernel(const double* __restri
     }
     out[idx * H * CN + e] = (float)(acc * scale);
   }
+}
+
+// One thread per in-band value: band[item][k][j] = khat[item][k][j < npx ? j : conv_n - 2 npx + 1 + j].
+__global__ __launch_bounds__(256) void khat_band_kernel(int conv_n, int npx, int64_t total, const float* __restrict__ khat,
+                                                        float* __restrict__ band) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const int kb = 2 * npx - 1;
+  const int64_t item = e / ((int64_t)npx * kb);
+  const int rem = (int)(e - item * npx * kb);
+  const int k = rem / kb, j = rem - k * kb;
+  const int col = j < npx ? j : conv_n - 2 * npx + 1 + j;
+  band[e] = khat[(item * (conv_n / 2 + 1) + k) * conv_n + col];
+}
+
+hipError_t launch_khat_band(int conv_n, int npx, int64_t n, const float* d_khat, float* d_band, hipStream_t st) {
+  if (conv_n != 4 * npx || !d_khat || !d_band) return hipErrorInvalidValue;
+  const int64_t total = n * npx * (2 * npx - 1);
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(khat_band_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, conv_n, npx, total,
+                     d_khat, d_band);
+  return hipGetLastError();
 }
 
 hipError_t launch_lgs_spectra(int conv_n, const double* d_params, int64_t n, float* d_out, hipStream_t st) {
