@@ -265,11 +265,11 @@ int shw_wfs_plan_destroy(shw_wfs_plan* plan);
  * plans 3 and 4) compute the column spectrum of the spot from
  * autocorrelations of the row transforms and filter only the rows inside
  * the spot's band; 13 (16 x 16 detector) takes noise and centroid in the
- * fused kernel, with the same per-pixel noise and FP32 sums as the second
- * kernel, and keeps no detector workspace.  New plans start on the fastest
- * measured variant: 12 for
- * band-limited 40-point shapes, 9 for the other 40-point shapes, 4 for
- * band-limited sodium plans, 2 for the other sodium plans, 0 otherwise.
+ * fused kernel with the second kernel's code (inversion head 4: the same
+ * images and slopes as 12 at that head) and keeps no detector workspace.
+ * New plans start on the fastest measured variant: 13 for band-limited
+ * 40-point shapes, 9 for the other 40-point shapes, 4 for band-limited
+ * sodium plans, 2 for the other sodium plans, 0 otherwise.
  * shw_wfs_plan_autotune times every variant on the given inputs
  * (reps launches each after two warm-up launches, HIP events on the stream;
  * synchronous), selects the fastest and returns its index in *best and the

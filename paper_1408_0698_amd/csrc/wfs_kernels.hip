@@ -173,48 +173,80 @@ __device__ __forceinline__ ItemRef resolve_item(const WfsLaunch& a, int64_t it, 
   return r;
 }
 
-// Noise and centroid of one half of a 16 x 16 detector image held in LDS, by one wavefront: pair
-// block b = 64 half + lane serves pixels b and b + 128 (reading O8's pair blocks), with the
-// per-pixel arithmetic of det_noise_kernel (a HEAD-step lockstep inversion head, then per-wavefront
-// queues for the searches still running and for the rejection sampler).  q_pix and q_val (4 x 128)
-// are this wavefront's queue arrays.  The item's two halves add their FP32 sums into sums[0..2] with
-// LDS atomics and count themselves in sums[3]; the half that completes the item writes the slopes
-// (two partial sums added to zero in either order give the same value).
-constexpr int kHalfPix = 128;
-template <int HEAD>
-__device__ __forceinline__ void noise_half16(const WfsLaunch& a, const ItemRef& ref, int64_t item, uint32_t gsub,
-                                             const float* __restrict__ det, int half, int lane,
-                                             int* __restrict__ q_pix, float* __restrict__ q_val,
-                                             float* __restrict__ sums) {
-  constexpr int DET_N = 16, NJ = 2;
+// Stage D for one item by one wavefront: photometry, Poisson + read noise, threshold and centre of
+// gravity of the item's DET_N x DET_N detector values at det (global or LDS); each lane takes
+// pixels l, l + 64, ...  q_pix [NPIX] and q_val [3][NPIX] are the wavefront's own queue arrays in
+// LDS.  The per-pixel noise is keyed by pixel, sub-aperture and frame (reading O8), so every
+// caller gives the same images; the centroid sums are FP32 (per lane, then a tree over the lanes)
+// instead of FP64, which moves a slope by a few 1e-5 detector pixels at most.
+template <int DET_N, int HEAD>
+__device__ __forceinline__ void noise_image(const WfsLaunch& a, const ItemRef& ref, int64_t item,
+                                            const float* __restrict__ det, int lane, int* __restrict__ q_pix,
+                                            float* __restrict__ q_val) {
+  constexpr int NPIX = DET_N * DET_N;
   constexpr float CD = 0.5f * (float)(DET_N - 1);
+  const uint32_t gsub = (uint32_t)(ref.w * a.n_valid + ref.i);
   const bool need_rng = a.noise && a.ph_scale > 0.0f;
-  const int pb = 64 * half + lane;
+  constexpr int NJ = (NPIX + 63) / 64;
+  // pair blocks serve pixels b and b + h; when h is a whole number of 64-pixel rounds
+  // (n = 128 m), pixel lane + 64 j pairs with lane + 64 (j + NJ / 2) of the same lane, which
+  // then draws one block for both
+  constexpr int PH = (NPIX + 1) / 2;
+  constexpr bool PAIRED = NJ % 2 == 0 && PH == 64 * (NJ / 2);
   float v[NJ], u[NJ], z[NJ];
   bool small[NJ];
-  v[0] = det[pb];
-  v[1] = det[pb + kHalfPix];
+  // all loads first, then branch-free tests (short-circuit tests would put a branch, and so a
+  // wait for the load, between consecutive loads)
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int pix = lane + 64 * j;
+    v[j] = pix < NPIX ? det[pix] : 0.0f;
+  }
   const float scale = a.ph_scale > 0.0f ? a.ph_scale : 1.0f;  // to expected electrons
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     v[j] = scale * v[j];
-    small[j] = need_rng & (v[j] > 0.0f) & (v[j] < kPoissonSplit);
+    small[j] = need_rng & (lane + 64 * j < NPIX) & (v[j] > 0.0f) & (v[j] < kPoissonSplit);
   }
   if (need_rng) {
-    const uint4 wd = pair_block((uint32_t)pb, gsub, ref.frame, ref.key0, ref.key1);
-    const float2 zz = read_noise_pair(wd);
-    u[0] = u01(wd.x);
-    z[0] = zz.x;
-    u[1] = u01(wd.y);
-    z[1] = zz.y;
+    if constexpr (PAIRED) {
+#pragma unroll
+      for (int j = 0; j < NJ / 2; ++j) {
+        const uint4 w = pair_block((uint32_t)(lane + 64 * j), gsub, ref.frame, ref.key0, ref.key1);
+        const float2 zz = read_noise_pair(w);
+        u[j] = u01(w.x);
+        z[j] = zz.x;
+        u[j + NJ / 2] = u01(w.y);
+        z[j + NJ / 2] = zz.y;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int pix = lane + 64 * j;
+        const bool second = pix >= PH;
+        const uint4 w = pair_block((uint32_t)(second ? pix - PH : pix), gsub, ref.frame, ref.key0, ref.key1);
+        const float2 zz = read_noise_pair(w);
+        u[j] = u01(second ? w.y : w.x);
+        z[j] = second ? zz.y : zz.x;
+      }
+    }
   } else {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) u[j] = z[j] = 0.0f;
   }
+  // Inversions: HEAD lockstep steps for the lane's pixels (most means are small and end there);
+  // the ones still searching go to queue A and restart one per lane, so that the lane's long
+  // searches do not hold its other pixels.  Means >= kPoissonSplit go to queue B (rejection sampler).  Both
+  // queues share the LDS arrays: A from the front, B from the back.  HEAD changes which pixels reach
+  // queue A, not their counts (the same steps either way).  Queue A restarts from exp(-mean),
+  // recomputed (the same value the head started from).
   int k[NJ];
   bool more[NJ];
   float p0[NJ];
   poisson_inversion_head<NJ, HEAD>(v, u, small, k, more, p0);
+  // centroid sums: FP32 over the lane's few pixels, then the 64-lane tree (wave_sum_tree); with
+  // at most a dozen terms per lane the sums are exact to about 20 * 2^-24 of their magnitudes,
+  // a few 1e-5 detector pixels at most in a slope
   float s0 = 0.0f, sx = 0.0f, sy = 0.0f;
   auto accumulate = [&](int pix, float img) {
     if (ref.images_it) ref.images_it[pix] = img;
@@ -225,29 +257,30 @@ __device__ __forceinline__ void noise_half16(const WfsLaunch& a, const ItemRef& 
     sx = fmaf((float)q - CD, t, sx);
     sy = fmaf((float)p - CD, t, sy);
   };
+  // set bits of a wavefront mask in the lanes below this one (the hardware's masked bit count)
   auto below = [](uint64_t m) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
   };
   int na = 0, nq = 0;
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
-    const int pix = pb + kHalfPix * j;
-    const bool big = need_rng && v[j] >= kPoissonSplit;
+    const int pix = lane + 64 * j;
+    const bool in = pix < NPIX;
+    const bool big = need_rng && in && v[j] >= kPoissonSplit;
     const uint64_t ma = __ballot(more[j]);
     const uint64_t mb = __ballot(big);
     if (more[j]) {
       const int e = na + below(ma);
       q_pix[e] = pix;
       q_val[e] = v[j];
-      q_val[kHalfPix + e] = u[j];
-      q_val[2 * kHalfPix + e] = z[j];
-      q_val[3 * kHalfPix + e] = p0[j];
+      q_val[NPIX + e] = u[j];
+      q_val[2 * NPIX + e] = z[j];
     } else if (big) {
-      const int e = kHalfPix - 1 - (nq + below(mb));
+      const int e = NPIX - 1 - (nq + below(mb));
       q_pix[e] = pix;
       q_val[e] = v[j];
-      q_val[2 * kHalfPix + e] = z[j];
-    } else {
+      q_val[2 * NPIX + e] = z[j];
+    } else if (in) {
       accumulate(pix, need_rng ? (float)k[j] + a.ron * z[j] : v[j]);
     }
     na += __popcll(ma);
@@ -257,33 +290,30 @@ __device__ __forceinline__ void noise_half16(const WfsLaunch& a, const ItemRef& 
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
   for (int e = lane; e < na; e += 64) {
-    const int kp = poisson_inversion_from(q_val[e], q_val[kHalfPix + e], q_val[3 * kHalfPix + e]);
-    accumulate(q_pix[e], (float)kp + a.ron * q_val[2 * kHalfPix + e]);
+    const float lam = q_val[e];
+    const int kp = poisson_inversion_from(lam, q_val[NPIX + e], exp_neg(lam));
+    accumulate(q_pix[e], (float)kp + a.ron * q_val[2 * NPIX + e]);
   }
   for (int t = lane; t < nq; t += 64) {
-    const int e = kHalfPix - 1 - t;
+    const int e = NPIX - 1 - t;
     const int pix = q_pix[e];
     const int kp = poisson_ptrs(q_val[e], (uint32_t)pix, gsub, ref.frame, ref.key0, ref.key1);
-    accumulate(pix, (float)kp + a.ron * q_val[2 * kHalfPix + e]);
+    accumulate(pix, (float)kp + a.ron * q_val[2 * NPIX + e]);
   }
-  // every lane of the wavefront is active here
+  // the queue arrays are reused by the wavefront's next item: its reads end before those writes
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  // every lane of the wavefront is active here; the sums of non-negative terms are zero only
+  // when every term is
   s0 = wave_sum_tree(s0);
   sx = wave_sum_tree(sx);
   sy = wave_sum_tree(sy);
   if (lane == 0) {
-    atomicAdd(&sums[0], s0);
-    atomicAdd(&sums[1], sx);
-    atomicAdd(&sums[2], sy);
-    // LDS operations of one wavefront take effect in order: the other half's sums are in once its
-    // count is
-    if (atomicAdd(&sums[3], 1.0f) == 1.0f) {
-      const float t0 = atomicAdd(&sums[0], 0.0f), tx = atomicAdd(&sums[1], 0.0f), ty = atomicAdd(&sums[2], 0.0f);
-      const bool empty = !(t0 > 0.0f);
-      const float r = __builtin_amdgcn_rcpf(t0);
-      ref.slopes_fw[ref.i] = empty ? 0.0f : tx * r;
-      ref.slopes_fw[a.n_valid + ref.i] = empty ? 0.0f : ty * r;
-      if (a.flags && !a.list) a.flags[item] = empty ? 1 : 0;
-    }
+    const bool empty = !(s0 > 0.0f);
+    const float r = __builtin_amdgcn_rcpf(s0);
+    ref.slopes_fw[ref.i] = empty ? 0.0f : sx * r;
+    ref.slopes_fw[a.n_valid + ref.i] = empty ? 0.0f : sy * r;
+    if (a.flags && !a.list) a.flags[item] = empty ? 1 : 0;
   }
 }
 
@@ -786,8 +816,9 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
   }
   if constexpr (BL && !DSPLIT) {
     // noise and centroid in this kernel: the detector values of the block's items go to one LDS
-    // array once every lane has read the planes, then each wavefront takes half images (two
-    // pixels per lane), the block's 2 SPB halves dealt round-robin over its wavefronts
+    // array once every lane has read the planes; then wavefronts 0 .. SPB/2 - 1 take two whole
+    // images each (noise_image, as det_noise_kernel), and the last wavefront leaves (its
+    // registers go to other blocks; nothing after this stage waits for it)
     float dv[QB];
     const int p = l / G;
     const int q0 = QB * (l - p * G);
@@ -809,25 +840,26 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
     }
     __syncthreads();  // every lane has read the planes
     constexpr int NW = SPB * L / 64;
-    static_assert(SPB * NPIX + 4 * SPB <= SPB * PLANE && NW * 5 * kHalfPix <= SPB * PLANE, "noise stage LDS");
-    float* s_det = s_re;                  // [SPB][NPIX]
-    float* s_sums = s_re + SPB * NPIX;    // [SPB][4]: sums of t, x t, y t and the halves counted
+    static_assert(SPB == 2 * (NW - 1), "two images for each wavefront but the last");
+    // LDS: the detector values [SPB][NPIX] and one queue (NPIX + 3 NPIX words) per working
+    // wavefront: three in the imaginary plane, the fourth after the detector values
+    constexpr int QW = 4 * NPIX;
+    static_assert(SPB * NPIX + QW <= SPB * PLANE && (NW - 2) * QW <= SPB * PLANE && NW - 1 == 4, "noise stage LDS");
+    float* s_det = s_re;
     if (active && l < DET_N * G) {
 #pragma unroll
       for (int j = 0; j < QB; ++j) s_det[s * NPIX + p * DET_N + q0 + j] = dv[j];
     }
-    if (tid < 4 * SPB) s_sums[tid] = 0.0f;
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: item arithmetic on the scalar unit
-    int* q_pix = reinterpret_cast<int*>(s_im) + wave * 5 * kHalfPix;
-    float* q_val = s_im + wave * 5 * kHalfPix + kHalfPix;
-    for (int hh = wave; hh < 2 * SPB; hh += NW) {
-      const int si = hh >> 1;
+    if (wave == NW - 1) return;
+    float* qbase = wave < NW - 2 ? s_im + wave * QW : s_re + SPB * NPIX;
+#pragma unroll 1
+    for (int si = 2 * wave; si < 2 * wave + 2; ++si) {
       const int64_t it2 = a.item0 + group * SPB + si;
-      if (it2 >= a.total) continue;  // uniform over the wavefront
+      if (it2 >= a.total) break;  // uniform over the wavefront
       const ItemRef r2 = resolve_item(a, it2, frame_base, NPIX);
-      noise_half16<4>(a, r2, it2, (uint32_t)(r2.w * a.n_valid + r2.i), s_det + si * NPIX, hh & 1, tid & 63, q_pix,
-                      q_val, s_sums + 4 * si);
+      noise_image<DET_N, 4>(a, r2, it2, s_det + si * NPIX, tid & 63, reinterpret_cast<int*>(qbase), qbase + NPIX);
     }
     return;
   } else {
@@ -924,6 +956,8 @@ template <int NPX, int FFT_N, int CONV_N, int DET_N, bool LGS, int SPB, int WPE,
           bool DSPLIT, bool BL>
 __global__ __launch_bounds__(SPB * CONV_N) __attribute__((amdgpu_waves_per_eu(WPE))) void wfs_fused_kernel(
     const WfsLaunch a) {
+  // with noise in the band-limited kernel a wavefront leaves before the others: one group only
+  static_assert(!(BL && !DSPLIT && PERSIST), "band-limited noise stage: one-shot grid");
   using LY = FusedLayout<NPX, FFT_N, CONV_N, DET_N, SPLIT, DSPLIT, BL>;
   __shared__ __align__(16) float s_re[SPB * LY::PLANE];
   __shared__ __align__(16) float s_im[SPB * LY::PLANE];
@@ -958,20 +992,13 @@ __global__ __launch_bounds__(SPB * CONV_N) __attribute__((amdgpu_waves_per_eu(WP
   }
 }
 
-// Stage D of the detector-split variants: one wavefront per item, each lane takes pixels
-// l, l + 64, ... of the item's detector values in det_ws.  The same per-pixel noise (keyed by
-// pixel, sub-aperture and frame) and threshold as the fused stage, so the same images; the
-// centroid sums are FP32 (per lane, then a tree over the lanes) instead of FP64, which moves a
-// slope by a few 1e-5 detector pixels at most.
+// Stage D of the detector-split variants: one wavefront per item over the detector values the
+// fused kernel left in det_ws (noise_image).
 template <int DET_N, int HEAD>
 __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   constexpr int NPIX = DET_N * DET_N;
-  constexpr float CD = 0.5f * (float)(DET_N - 1);
-  // per-wavefront pixel queues: long inversions (pixel, mean, uniform, read-noise deviate,
-  // exp(-mean)) from the front, means >= kPoissonSplit for the rejection sampler (pixel, mean,
-  // read-noise deviate) from the back, so that each runs once for up to 64 pixels
   __shared__ int q_pix[4][NPIX];
-  __shared__ float q_val[4][4][NPIX];
+  __shared__ float q_val[4][3 * NPIX];
   // device frame counter (graph replay): *frame0_dev plus the launch's offset a.frame0
   const uint32_t frame_base = a.frame0_dev ? (uint32_t)*a.frame0_dev + a.frame0 : a.frame0;
   const int lane = threadIdx.x & 63;
@@ -979,133 +1006,7 @@ __global__ __launch_bounds__(256) void det_noise_kernel(const WfsLaunch a) {
   const int64_t item = a.item0 + (int64_t)blockIdx.x * 4 + wave;
   if (item >= a.total) return;  // whole wavefronts leave together; no block barrier below
   const ItemRef ref = resolve_item(a, item, frame_base, NPIX);
-  const float* det = a.det_ws + (item - a.item0) * NPIX;
-  const uint32_t gsub = (uint32_t)(ref.w * a.n_valid + ref.i);
-  const bool need_rng = a.noise && a.ph_scale > 0.0f;
-  constexpr int NJ = (NPIX + 63) / 64;
-  // pair blocks serve pixels b and b + h; when h is a whole number of 64-pixel rounds
-  // (n = 128 m), pixel lane + 64 j pairs with lane + 64 (j + NJ / 2) of the same lane, which
-  // then draws one block for both
-  constexpr int PH = (NPIX + 1) / 2;
-  constexpr bool PAIRED = NJ % 2 == 0 && PH == 64 * (NJ / 2);
-  float v[NJ], u[NJ], z[NJ];
-  bool small[NJ];
-  // all loads first, then branch-free tests (short-circuit tests would put a branch, and so a
-  // wait for the load, between consecutive loads)
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int pix = lane + 64 * j;
-    v[j] = pix < NPIX ? det[pix] : 0.0f;
-  }
-  const float scale = a.ph_scale > 0.0f ? a.ph_scale : 1.0f;  // to expected electrons
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    v[j] = scale * v[j];
-    small[j] = need_rng & (lane + 64 * j < NPIX) & (v[j] > 0.0f) & (v[j] < kPoissonSplit);
-  }
-  if (need_rng) {
-    if constexpr (PAIRED) {
-#pragma unroll
-      for (int j = 0; j < NJ / 2; ++j) {
-        const uint4 w = pair_block((uint32_t)(lane + 64 * j), gsub, ref.frame, ref.key0, ref.key1);
-        const float2 zz = read_noise_pair(w);
-        u[j] = u01(w.x);
-        z[j] = zz.x;
-        u[j + NJ / 2] = u01(w.y);
-        z[j + NJ / 2] = zz.y;
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const int pix = lane + 64 * j;
-        const bool second = pix >= PH;
-        const uint4 w = pair_block((uint32_t)(second ? pix - PH : pix), gsub, ref.frame, ref.key0, ref.key1);
-        const float2 zz = read_noise_pair(w);
-        u[j] = u01(second ? w.y : w.x);
-        z[j] = second ? zz.y : zz.x;
-      }
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) u[j] = z[j] = 0.0f;
-  }
-  // Inversions: HEAD lockstep steps for the lane's pixels (most means are small and end there);
-  // the ones still searching go to queue A and restart one per lane, so that the lane's long
-  // searches do not hold its other pixels.  Means >= kPoissonSplit go to queue B (rejection sampler).  Both
-  // queues share the LDS arrays: A from the front, B from the back.  HEAD changes which pixels reach
-  // queue A, not their counts (the same steps either way).
-  int k[NJ];
-  bool more[NJ];
-  float p0[NJ];
-  poisson_inversion_head<NJ, HEAD>(v, u, small, k, more, p0);
-  // centroid sums: FP32 over the lane's few pixels, then the 64-lane tree (wave_sum_tree); with
-  // at most a dozen terms per lane the sums are exact to about 20 * 2^-24 of their magnitudes,
-  // a few 1e-5 detector pixels at most in a slope
-  float s0 = 0.0f, sx = 0.0f, sy = 0.0f;
-  auto accumulate = [&](int pix, float img) {
-    if (ref.images_it) ref.images_it[pix] = img;
-    const int p = pix / DET_N;
-    const int q = pix - p * DET_N;
-    const float t = fmaxf(img - a.thr, 0.0f);
-    s0 += t;
-    sx = fmaf((float)q - CD, t, sx);
-    sy = fmaf((float)p - CD, t, sy);
-  };
-  // set bits of a wavefront mask in the lanes below this one (the hardware's masked bit count)
-  auto below = [](uint64_t m) {
-    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-  };
-  int na = 0, nq = 0;
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int pix = lane + 64 * j;
-    const bool in = pix < NPIX;
-    const bool big = need_rng && in && v[j] >= kPoissonSplit;
-    const uint64_t ma = __ballot(more[j]);
-    const uint64_t mb = __ballot(big);
-    if (more[j]) {
-      const int e = na + below(ma);
-      q_pix[wave][e] = pix;
-      q_val[wave][0][e] = v[j];
-      q_val[wave][1][e] = u[j];
-      q_val[wave][2][e] = z[j];
-      q_val[wave][3][e] = p0[j];
-    } else if (big) {
-      const int e = NPIX - 1 - (nq + below(mb));
-      q_pix[wave][e] = pix;
-      q_val[wave][0][e] = v[j];
-      q_val[wave][2][e] = z[j];
-    } else if (in) {
-      accumulate(pix, need_rng ? (float)k[j] + a.ron * z[j] : v[j]);
-    }
-    na += __popcll(ma);
-    nq += __popcll(mb);
-  }
-  // the queues are written and read by this wavefront only: order its LDS accesses
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  for (int e = lane; e < na; e += 64) {
-    const int kp = poisson_inversion_from(q_val[wave][0][e], q_val[wave][1][e], q_val[wave][3][e]);
-    accumulate(q_pix[wave][e], (float)kp + a.ron * q_val[wave][2][e]);
-  }
-  for (int t = lane; t < nq; t += 64) {
-    const int e = NPIX - 1 - t;
-    const int pix = q_pix[wave][e];
-    const int kp = poisson_ptrs(q_val[wave][0][e], (uint32_t)pix, gsub, ref.frame, ref.key0, ref.key1);
-    accumulate(pix, (float)kp + a.ron * q_val[wave][2][e]);
-  }
-  // every lane of the wavefront is active here; the sums of non-negative terms are zero only
-  // when every term is
-  s0 = wave_sum_tree(s0);
-  sx = wave_sum_tree(sx);
-  sy = wave_sum_tree(sy);
-  if (lane == 0) {
-    const bool empty = !(s0 > 0.0f);
-    const float r = __builtin_amdgcn_rcpf(s0);
-    ref.slopes_fw[ref.i] = empty ? 0.0f : sx * r;
-    ref.slopes_fw[a.n_valid + ref.i] = empty ? 0.0f : sy * r;
-    if (a.flags && !a.list) a.flags[item] = empty ? 1 : 0;
-  }
+  noise_image<DET_N, HEAD>(a, ref, item, a.det_ws + (item - a.item0) * NPIX, lane, q_pix[wave], q_val[wave]);
 }
 
 // Items per block: the smallest count whose lanes fill whole 64-wide waves, at least 256 lanes.
@@ -1161,7 +1062,7 @@ static hipError_t launch_variant(const WfsLaunch& a0, hipStream_t st) {
 // from kFirstDetSplit on end the fused kernel at the detector.
 constexpr int kTunedVariants = 11;
 // Band-limited variants (11: persistent, 5 waves per EU; 12: one-shot, 7 waves per EU; 13: as 12 with noise
-// and centroid in the same kernel), for LGS shapes with FFT_N = CONV_N.
+// and centroid in the same kernel, inversion head 4), for LGS shapes with FFT_N = CONV_N.
 constexpr int kBandLimitedVariants = 3;
 template <int NPX, int FFT_N, int CONV_N, bool LGS>
 constexpr bool band_limited_ok() {
@@ -1278,12 +1179,13 @@ bool wfs_variant_params(const WfsShape& s, int v, int32_t* out) {
 
 int wfs_default_variant(const WfsShape& s) {
   // measured on the 6-LGS frame, with and without noise and sub-layers: the band-limited kernel
-  // where the shape allows it (one-shot; persistent with sub-layers), else split rows + detector
-  // split + persistent grid
+  // where the shape allows it (one-shot, noise in the same kernel: as fast as with the separate
+  // noise kernel and 40 instead of 101 MB per frame; persistent with sub-layers), else split
+  // rows + detector split + persistent grid
   const bool bl = s.lgs && s.fft_n == s.conv_n && s.conv_n == 4 * s.npx;
   if (s.sub) return bl ? 4 : 2;
   if (!(s.conv_n == 40 && s.det_n == 16)) return 0;
-  return bl ? 12 : 9;
+  return bl ? kTunedVariants + 2 : 9;
 }
 
 bool wfs_variant_needs_det_ws(const WfsShape& s, int variant) {

@@ -29,14 +29,13 @@ WHOLE_ROWS = (0, 1, 4, 5, 6, 7)
 SPLIT_ROWS = (2, 3, 8, 9, 10)
 BAND_LIMITED = (11, 12, 13)   # the column spectrum from autocorrelations: another rounding family
 # Variants 6-12 take noise and centroid in the separate detector kernel, whose centroid sums are
-# FP32 per lane and a 64-lane tree (variants 0-5: FP64 sums in the fused kernel; variant 13: FP32
-# sums over two pixels per lane and a tree per half image, the two halves added in the fused
-# kernel).  Their images equal those of their row family bitwise; their slopes differ between
+# FP32 per lane and a 64-lane tree (variants 0-5: FP64 sums in the fused kernel); variant 13 runs
+# the same per-image noise and centroid code inside the fused kernel (with the default inversion
+# head of 4).  Their images equal those of their row family bitwise; their slopes differ between
 # arrangements by the FP32 rounding of the sums, at most about 20 * 2^-24 of
 # (|sum x t| + |slope| sum t) / sum t, a few 1e-5 detector pixels.
 CENTROID_ARRANGEMENT = {v: "fp64" for v in range(6)}
-CENTROID_ARRANGEMENT.update({v: "detector kernel" for v in range(6, 13)})
-CENTROID_ARRANGEMENT[13] = "half images"
+CENTROID_ARRANGEMENT.update({v: "detector kernel" for v in range(6, 14)})
 SUM_TOL_PX = 1e-4
 
 
@@ -204,13 +203,14 @@ def test_multi_step_graph_replays_consecutive_frames(torch_dev):
 
 
 def test_detector_split_work_list_equals_single_calls(torch_dev):
-    """A work list of three frames, run with each detector-split variant, equals per-frame calls of the
-    first detector-split variant of the same row-transform family."""
+    """A work list of three frames, run with each detector-split variant (and variant 13, whose
+    in-kernel noise stage is the detector kernel's code), equals per-frame calls of the first
+    detector-split variant of the same row-transform family."""
     from paper_1408_0698_amd import shwfs
     cfg = G.CFG1.replace(pupil_n=130, n_subap=13)
     plan = _plan(cfg, 6)
     opd = torch_dev.from_numpy(S.lgs39m_opd(3, 6, pupil_n=130)).cuda()
-    for fam_ref, variants in ((6, (6, 7)), (8, (8, 9, 10)), (11, (11, 12))):
+    for fam_ref, variants in ((6, (6, 7)), (8, (8, 9, 10)), (11, (11, 12, 13))):
         plan.set_variant(fam_ref)
         ref = []
         for f in range(3):
