@@ -621,6 +621,10 @@ def main():
                          "counters in profiles/wfs_measure_lgs39m_valu.md",
                 "fp64_tflops": ctr["fp64_flop_per_frame"] * B / launch_s / 1e12,
                 "valu_issue_frac": ctr["valu_lane_ops_per_frame"] * B / launch_s / PEAK_VALU_LANE_OPS,
+                "valu_issue_note": "VALU lane operations per frame from the committed counters (another run) over "
+                                   "this run's launch time, against 256 CU x 4 SIMD x 16 lanes x 2.4 GHz (one wave64 "
+                                   "instruction per SIMD every 4 cycles); about 1 means the kernels run at the issue "
+                                   "limit, to the few per cent the two runs differ by",
                 "nominal_tflops": nominal,
                 "nominal_note": "3 x 5 N^2 log2 N^2 per sub-aperture (three full 40x40 transforms); the "
                                 "band-limited kernels execute fewer operations",
