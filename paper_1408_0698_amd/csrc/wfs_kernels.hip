@@ -854,7 +854,9 @@ __device__ __forceinline__ void wfs_fused_group(const WfsLaunch& a, int64_t grou
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: item arithmetic on the scalar unit
     if (wave == NW - 1) return;
     float* qbase = wave < NW - 2 ? s_im + wave * QW : s_re + SPB * NPIX;
-#pragma unroll 1
+    // unrolled: the rolled loop kept its uniform values live across both images and spilled
+    // 25 scalar registers
+#pragma unroll
     for (int si = 2 * wave; si < 2 * wave + 2; ++si) {
       const int64_t it2 = a.item0 + group * SPB + si;
       if (it2 >= a.total) break;  // uniform over the wavefront
