@@ -19,9 +19,10 @@ struct PsfLaunch {
 
 bool psf_size_supported(int fft_m, int pupil_n);
 
-// Row and column passes over frames [f0, f0 + nf) of stars [0, n_stars); T holds
-// n_stars * nf * pupil_n * fft_m complex.
-hipError_t launch_psf_chunk(const PsfLaunch& a, int n_stars, int64_t f0, int nf, float2* T, float* acc,
-                            float* strehl, hipStream_t st);
+// Row pass over frames [f0, f0 + nf) of stars [0, n_stars) into T (n_stars * nf * pupil_n * fft_m
+// complex), and the column pass that reads T and adds the frames' PSFs to the accumulators.
+hipError_t launch_psf_rows(const PsfLaunch& a, int n_stars, int64_t f0, int nf, float2* T, hipStream_t st);
+hipError_t launch_psf_cols(const PsfLaunch& a, int n_stars, int64_t f0, int nf, const float2* T, float* acc,
+                           float* strehl, hipStream_t st);
 
 }  // namespace shw

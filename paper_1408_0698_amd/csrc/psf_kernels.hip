@@ -25,10 +25,14 @@
 // stored in column blocks of 8: element (frame f, row y, column u) of T sits
 // at ((f * M/8 + u/8) * pupil_n + y) * 8 + u % 8, so that rows write whole
 // 64-byte runs and the 8 columns of a column block are one contiguous region.
-// Column pass: 4 columns per block, the two halves of a column block launched
-// 8 blocks apart (the same XCD), frames accumulated in LDS (each lane owns its
-// 20 outputs, so no barrier), one read-modify-write of the accumulator per
-// call; the on-axis sample of each frame is the Strehl ratio.  A 4-waves-per-
+// Column pass: 4 columns per block; the 8 blocks of a 32-column group (one
+// 128-byte line of every accumulator row, and four column blocks of the
+// intermediate) are launched 8 apart, so the dispatcher places them on one
+// XCD and its L2 merges their reads of the intermediate and their writes of
+// the accumulator.  Frames are accumulated in LDS (each lane owns its 20
+// outputs, so no barrier), then one read-modify-write of the accumulator per
+// call, 16 bytes (the block's 4 columns) per row; the on-axis sample of each
+// frame is the Strehl ratio.  A 4-waves-per-
 // SIMD register target (128 VGPRs, a few spilled) lets 3 blocks share a CU.
 // Both passes have a form for pupil_n = M/2 (the Nyquist-sampled PSF), where
 // every sample of the pruned transforms lies in the pupil grid, so its loads
@@ -49,6 +53,7 @@ constexpr int kP = 2 * kQ;        // lanes per line
 constexpr int kLines = 4;         // lines per block
 constexpr int kST = kQ + 1;       // odd LDS stride
 constexpr int kCB = 8;            // columns per block of the intermediate
+constexpr int kGroupCols = 32;    // columns per 128-byte accumulator line (8 column-pass blocks)
 
 // Offset of element (star-frame sf, row y, column u) of the intermediate.
 __device__ __forceinline__ int64_t t_index(int64_t sf, int pupil_n, int y, int u) {
@@ -170,12 +175,12 @@ __global__ __launch_bounds__(kLines * kP) void psf_rows_kernel(const PsfLaunch a
   }
 }
 
-// Column pass.  The two halves of a column block (4 columns each) go to blocks 8 apart in launch
-// order, which the dispatcher places on the same XCD, so each 64-byte run is fetched into one L2.
+// Column pass.  Block b = 64 j + 8 m + x takes columns 4 m .. 4 m + 3 of the 32-column group
+// g = 8 j + x (groups past the last one leave at once).
 template <bool FULL>
 __global__ __launch_bounds__(kLines * kP) __attribute__((amdgpu_waves_per_eu(4))) void psf_cols_kernel(const PsfLaunch a, int64_t f0, int nf,
-                                                               const float2* __restrict__ T, float* __restrict__ acc,
-                                                               float* __restrict__ strehl) {
+                                                               int n_groups, const float2* __restrict__ T,
+                                                               float* __restrict__ acc, float* __restrict__ strehl) {
   __shared__ float s_pl[kLines * kQ * kST];
   // per-line sums over the frames: lane (q, h) owns entries q + 40 (c + 20 h), c < 20 (no barrier)
   __shared__ float s_sum[kLines][kM];
@@ -183,10 +188,13 @@ __global__ __launch_bounds__(kLines * kP) __attribute__((amdgpu_waves_per_eu(4))
   const int line = tid / kP, j = tid - line * kP;
   const int q = j >> 1, h = j & 1;
   const int b = blockIdx.x;
-  const int group = (b >> 4) * 8 + (b & 7);  // column block of 8 over all stars
-  const int half = (b >> 3) & 1;
-  const int star = group / (kM / kCB);
-  const int u = (group - star * (kM / kCB)) * kCB + half * kLines + line;  // column of this star
+  const int m = (b >> 3) & 7;
+  const int g = (b >> 6) * 8 + (b & 7);
+  if (g >= n_groups) return;  // the whole block
+  constexpr int kGroups = kM / kGroupCols;
+  const int star = g / kGroups;
+  const int u0 = (g - star * kGroups) * kGroupCols + m * kLines;  // first column of the block
+  const int u = u0 + line;
   float* pl = s_pl + line * kQ * kST;
   float* sum = s_sum[line];
 #pragma unroll
@@ -209,32 +217,49 @@ __global__ __launch_bounds__(kLines * kP) __attribute__((amdgpu_waves_per_eu(4))
       if (strehl && u == kM / 2 && q == 0 && h == 1 && c == 0) strehl[(int64_t)star * a.n_frames + f0 + fl] = p;
     }
   }
-#pragma unroll
-  for (int c = 0; c < kNZ; ++c) {
-    const int vv = q + kQ * (c + kNZ * h);
-    acc[star * a.acc_stride + (int64_t)vv * kM + u] += sum[vv];
+  __syncthreads();  // every line's sums are in LDS
+  // accumulator rows v, columns u0 .. u0 + 3: one 16-byte read-modify-write per row when the
+  // accumulator allows it (u0 is a multiple of 4), else four 4-byte ones
+  float* ac = acc + star * a.acc_stride + u0;
+  if ((reinterpret_cast<uintptr_t>(ac) & 15) == 0) {
+    for (int vv = tid; vv < kM; vv += kLines * kP) {
+      float4* pa = reinterpret_cast<float4*>(ac + (int64_t)vv * kM);
+      float4 o = *pa;
+      o.x += s_sum[0][vv];
+      o.y += s_sum[1][vv];
+      o.z += s_sum[2][vv];
+      o.w += s_sum[3][vv];
+      *pa = o;
+    }
+  } else {
+    for (int e = tid; e < kM * kLines; e += kLines * kP) {
+      const int vv = e >> 2, l = e & 3;
+      ac[(int64_t)vv * kM + l] += s_sum[l][vv];
+    }
   }
 }
 
 bool psf_size_supported(int fft_m, int pupil_n) { return fft_m == kM && pupil_n >= 1 && pupil_n <= kM / 2; }
 
-hipError_t launch_psf_chunk(const PsfLaunch& a, int n_stars, int64_t f0, int nf, float2* T, float* acc,
-                            float* strehl, hipStream_t st) {
+hipError_t launch_psf_rows(const PsfLaunch& a, int n_stars, int64_t f0, int nf, float2* T, hipStream_t st) {
   const int64_t nrows = (int64_t)n_stars * nf * a.pupil_n;
   const int64_t rb = (nrows + kLines - 1) / kLines;
-  const bool full = a.pupil_n == kM / 2;
-  if (full)
+  if (a.pupil_n == kM / 2)
     hipLaunchKernelGGL(psf_rows_kernel<true>, dim3((unsigned)rb), dim3(kLines * kP), 0, st, a, f0, nf, nrows, T);
   else
     hipLaunchKernelGGL(psf_rows_kernel<false>, dim3((unsigned)rb), dim3(kLines * kP), 0, st, a, f0, nf, nrows, T);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  static_assert((kM / kLines) % 16 == 0, "column blocks pair up 8 apart");
-  const dim3 cg((unsigned)(n_stars * (kM / kLines)));
-  if (full)
-    hipLaunchKernelGGL(psf_cols_kernel<true>, cg, dim3(kLines * kP), 0, st, a, f0, nf, (const float2*)T, acc, strehl);
+  return hipGetLastError();
+}
+
+hipError_t launch_psf_cols(const PsfLaunch& a, int n_stars, int64_t f0, int nf, const float2* T, float* acc,
+                           float* strehl, hipStream_t st) {
+  static_assert(kGroupCols == 8 * kLines && kM % kGroupCols == 0, "8 blocks per 32-column group");
+  const int n_groups = n_stars * (kM / kGroupCols);
+  const dim3 cg((unsigned)(((n_groups + 7) / 8) * 64));
+  if (a.pupil_n == kM / 2)
+    hipLaunchKernelGGL(psf_cols_kernel<true>, cg, dim3(kLines * kP), 0, st, a, f0, nf, n_groups, T, acc, strehl);
   else
-    hipLaunchKernelGGL(psf_cols_kernel<false>, cg, dim3(kLines * kP), 0, st, a, f0, nf, (const float2*)T, acc, strehl);
+    hipLaunchKernelGGL(psf_cols_kernel<false>, cg, dim3(kLines * kP), 0, st, a, f0, nf, n_groups, T, acc, strehl);
   return hipGetLastError();
 }
 

@@ -872,7 +872,8 @@ static int psf_impl(shw_psf_plan* p, const float* d_opd_m, int64_t row_pitch, in
   a.inv_norm = (float)(1.0 / ((double)p->lit * (double)p->lit));
   for (int32_t f0 = 0; f0 < n_frames; f0 += k) {
     const int nf = n_frames - f0 < k ? n_frames - f0 : k;
-    hipError_t e = launch_psf_chunk(a, n_stars, f0, nf, p->d_work, d_psf_acc, d_strehl, (hipStream_t)stream);
+    hipError_t e = launch_psf_rows(a, n_stars, f0, nf, p->d_work, (hipStream_t)stream);
+    if (e == hipSuccess) e = launch_psf_cols(a, n_stars, f0, nf, p->d_work, d_psf_acc, d_strehl, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "psf launch");
   }
   return ok();

@@ -132,3 +132,25 @@ def test_star_batch_equals_single_calls(torch_dev):
     want, want_sr = OP.psf_accumulate(cfg, opd[1])
     assert np.abs(acc[1].cpu().numpy() - want).max() <= TOL * want.max()
     assert np.abs(sr[1].cpu().numpy() - want_sr).max() <= TOL * want_sr.max()
+
+
+def test_unaligned_accumulators_equal_aligned(torch_dev):
+    """Accumulators at a 4-byte offset, with a star stride that is not a multiple of 4 floats (the
+    column pass then updates them 4 bytes at a time): bitwise the same sums as 16-byte aligned ones."""
+    cfg = G.PsfConfig(pupil_n=96, pupil_dx_m=39.0 / 96)
+    m = cfg.fft_m
+    opd = np.stack([_opd(2, 96, 0.2, seed=s) for s in (4, 5)])
+    plan = _plan(cfg)
+    d = torch_dev.from_numpy(opd).cuda()
+    aligned = torch_dev.full((2, m, m), 0.5, device="cuda")
+    plan.accumulate_stars(d, aligned)
+    stride = m * m + 3
+    buf = torch_dev.full((1 + 2 * stride,), 0.5, device="cuda")
+    odd = buf[1:].as_strided((2, m, m), (stride, m, 1))
+    plan.accumulate_stars(d, odd)
+    torch_dev.cuda.synchronize()
+    assert np.array_equal(odd.cpu().numpy(), aligned.cpu().numpy())
+    # the floats between the two accumulators are untouched
+    assert np.all(buf[1 + m * m:1 + stride].cpu().numpy() == 0.5)
+    want, _ = OP.psf_accumulate(cfg, opd[0])
+    assert np.abs(aligned[0].cpu().numpy() - 0.5 - want).max() <= TOL * want.max()
