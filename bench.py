@@ -24,8 +24,10 @@ if ROOT not in sys.path:
 # (the convention's count; the band-limited kernels execute fewer operations, see COUNTERS)
 FLOP_PER_SUBAP_NOMINAL = 3 * 5 * 40 * 40 * math.log2(40 * 40)
 PEAK_FP32_TFLOPS = 157.3
-# VALU issue capacity: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles, 2.4 GHz
-PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# VALU issue slots: 256 CUs x 4 SIMDs, one wave64 slot per SIMD every 4 cycles at 2.4 GHz; two FP32
+# instructions of different wavefronts can share a slot (dual issue, counted by SQ_ACTIVE_INST_VALU2),
+# which is how the FP32 vector peak (157.3 TFLOP/s = 2 FMA slots' worth) is reached
+PEAK_VALU_SLOTS = 256 * 4 * 2.4e9 / 4
 # launch variants of the 40-point shapes whose measurement is two kernels (fused stages up to the
 # detector, then noise and centroid); the roofline time covers both
 DETECTOR_SPLIT_VARIANTS = (6, 7, 8, 9, 10, 11, 12)
@@ -620,11 +622,13 @@ def main():
                 "flops": "executed FP32 (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F32, FMA = 2) per frame, "
                          "counters in profiles/wfs_measure_lgs39m_valu.md",
                 "fp64_tflops": ctr["fp64_flop_per_frame"] * B / launch_s / 1e12,
-                "valu_issue_frac": ctr["valu_lane_ops_per_frame"] * B / launch_s / PEAK_VALU_LANE_OPS,
-                "valu_issue_note": "VALU lane operations per frame from the committed counters (another run) over "
-                                   "this run's launch time, against 256 CU x 4 SIMD x 16 lanes x 2.4 GHz (one wave64 "
-                                   "instruction per SIMD every 4 cycles); about 1 means the kernels run at the issue "
-                                   "limit, to the few per cent the two runs differ by",
+                "valu_slot_frac": (ctr["valu_issue_slots_per_frame"] * B / launch_s / PEAK_VALU_SLOTS
+                                   if "valu_issue_slots_per_frame" in ctr else None),
+                "valu_slot_note": "VALU issue slots per frame (wave instructions less the dual-issued ones, "
+                                  "SQ_INSTS_VALU - SQ_ACTIVE_INST_VALU2, from the committed counters of another "
+                                  "run) over this run's launch time, against 256 CU x 4 SIMD x 2.4 GHz / 4 cycles; "
+                                  "a stream of independent FP32 FMAs at full occupancy reaches about 0.75 by this "
+                                  "measure",
                 "nominal_tflops": nominal,
                 "nominal_note": "3 x 5 N^2 log2 N^2 per sub-aperture (three full 40x40 transforms); the "
                                 "band-limited kernels execute fewer operations",

@@ -33,7 +33,7 @@
 // outputs, so no barrier), then one read-modify-write of the accumulator per
 // call, 16 bytes (the block's 4 columns) per row; the on-axis sample of each
 // frame is the Strehl ratio.  A 4-waves-per-
-// SIMD register target (128 VGPRs, a few spilled) lets 3 blocks share a CU.
+// SIMD register target (128 VGPRs) lets 3 blocks share a CU.
 // Both passes have a form for pupil_n = M/2 (the Nyquist-sampled PSF), where
 // every sample of the pruned transforms lies in the pupil grid, so its loads
 // need no bounds masks.
