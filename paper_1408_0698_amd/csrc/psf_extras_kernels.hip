@@ -22,74 +22,135 @@ __device__ __forceinline__ int isqrt_floor(double q) {
   return w;
 }
 
-// Pass 1: block (g, s) takes rows g, g + G, ... of PSF s.  For a row at dv from the centre, the
-// pixels within radius r form the run |u - c| <= w, w = floor(sqrt(r^2 - dv^2)): the row's share
-// is a difference of its FP64 prefix sums.  Thread k < n_r keeps radius k's sum over the block's
-// rows, thread n_r the rows' totals.
+// Pass 1: block (g, s) takes rows g, g + G, ... of PSF s, one row per wavefront at a time.  For a
+// row at dv from the centre, the pixels within radius r form the run |u - c| <= w, w =
+// floor(sqrt(r^2 - dv^2)), whose share is pre(hi + 1) - pre(lo) of the row's FP64 prefix sums
+// pre.  The wavefront stages the row in LDS with coalesced loads; lane l sums its run of R
+// consecutive pixels (R a multiple of 8, 64 R >= M) in chunks of 8, a scan over the lanes gives the
+// runs' offsets, and the lanes write pre at every 8th pixel; a prefix is then one of those plus at
+// most 7 staged pixels.  Lane k < n_r keeps radius k's sum over the wavefront's rows, every lane
+// the rows' total; the block's wavefronts are added in a fixed order at the end.
+// LDS per wavefront: 65 doubles (the end), the row (pixel u at u + u/32, so that the lanes' runs
+// start in different banks), and pre at every 8th pixel (ceil(M/8) doubles).
+__device__ __forceinline__ void ee_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__host__ __device__ constexpr int ee_row_slot(int u) { return u + (u >> 5); }
+
+__host__ __device__ constexpr size_t ee_wave_lds(int m) {
+  return 65 * sizeof(double) + (size_t)((ee_row_slot(m) + 3) & ~3) * sizeof(float) +
+         (size_t)((m + 7) / 8) * sizeof(double);
+}
+
+constexpr int kEeMaxChunks = 8;  // chunks of 8 pixels per lane: 64 x 64 >= M for M <= 4096
+static_assert(kMaxRadii <= 64, "one lane per radius, entry n_r of the 65-double areas for the total");
+
 __global__ __launch_bounds__(256) void ee_rows_kernel(const EeLaunch a) {
-  __shared__ double pre[4096 + 1];
-  __shared__ double part[256];
-  const int g = blockIdx.x, s = blockIdx.y, M = a.m, c = M / 2;
+  extern __shared__ __align__(16) unsigned char ee_smem[];
+  const int M = a.m, c = M / 2;
+  const int R = ((M + 511) / 512) * 8;  // pixels per lane, a multiple of 8
+  const int nw = blockDim.x >> 6, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = blockIdx.x, s = blockIdx.y;
+  unsigned char* mine = ee_smem + (size_t)wave * ee_wave_lds(M);
+  double* fin = reinterpret_cast<double*>(mine);
+  float* srow = reinterpret_cast<float*>(mine + 65 * sizeof(double));
+  double* pre8 =
+      reinterpret_cast<double*>(mine + 65 * sizeof(double) + (size_t)((ee_row_slot(M) + 3) & ~3) * sizeof(float));
   const float* P = a.psf + s * a.psf_stride;
-  const int per = (M + 255) / 256;  // consecutive pixels per thread
-  double acc = 0.0;
-  for (int v = g; v < M; v += kEeGroups) {
+  const int u0 = lane * R;
+  double acc = 0.0, tot = 0.0;
+  for (int v = g + wave * kEeGroups; v < M; v += nw * kEeGroups) {
     const float* row = P + (int64_t)v * M;
-    // thread-local run sums, then an exclusive scan of the 256 run sums in a fixed order
-    const int u0 = threadIdx.x * per;
+    for (int u = lane; u < M; u += 64) srow[ee_row_slot(u)] = row[u];
+    ee_wave_sync();
+    double ch[kEeMaxChunks];
     double run = 0.0;
-    for (int q = 0; q < per; ++q)
-      if (u0 + q < M) run += (double)row[u0 + q];
-    part[threadIdx.x] = run;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-      const double add = threadIdx.x >= off ? part[threadIdx.x - off] : 0.0;
-      __syncthreads();
-      part[threadIdx.x] += add;
-      __syncthreads();
-    }
-    // pre[u + 1] = sum of row[0 .. u]
-    double x = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0.0;
-    if (threadIdx.x == 0) pre[0] = 0.0;
-    for (int q = 0; q < per; ++q)
-      if (u0 + q < M) {
-        x += (double)row[u0 + q];
-        pre[u0 + q + 1] = x;
+#pragma unroll
+    for (int i = 0; i < kEeMaxChunks; ++i) {
+      const int k = u0 + 8 * i;
+      double cs = 0.0;
+      if (8 * i < R && k < M) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (k + t < M) cs += (double)srow[ee_row_slot(k + t)];
       }
-    __syncthreads();
-    const double dv = (double)(v - c);
-    if (threadIdx.x < a.n_r) {
-      const double rem = a.r2[threadIdx.x] - dv * dv;
+      ch[i] = cs;
+      run += cs;
+    }
+    double inc = run;  // inclusive scan over the lanes, the same tree for every row
+    for (int off = 1; off < 64; off <<= 1) {
+      const double t = __shfl_up(inc, off);
+      if (lane >= off) inc += t;
+    }
+    const double row_tot = __shfl(inc, 63);
+    double x = inc - run;  // pre at the lane's chunk starts
+#pragma unroll
+    for (int i = 0; i < kEeMaxChunks; ++i) {
+      const int k = u0 + 8 * i;
+      if (8 * i < R && k < M) pre8[k >> 3] = x;
+      x += ch[i];
+    }
+    ee_wave_sync();
+    tot += row_tot;
+    if (lane < a.n_r) {
+      const double dv = (double)(v - c);
+      const double rem = a.r2[lane] - dv * dv;
       if (rem >= 0.0) {
         const int w = isqrt_floor(rem);
         const int lo = c - w < 0 ? 0 : c - w;
         const int hi = c + w > M - 1 ? M - 1 : c + w;
-        acc += pre[hi + 1] - pre[lo];
+        auto prefix = [&](int p) -> double {  // pre(p), 0 <= p <= M
+          if (p == M) return row_tot;
+          const int k = p & ~7;
+          double y = pre8[k >> 3];
+#pragma unroll
+          for (int t = 0; t < 7; ++t)
+            if (k + t < p) y += (double)srow[ee_row_slot(k + t)];
+          return y;
+        };
+        acc += prefix(hi + 1) - prefix(lo);
       }
-    } else if (threadIdx.x == a.n_r) {
-      acc += pre[M];
     }
-    __syncthreads();  // pre and part are rewritten by the next row
+    ee_wave_sync();  // the staged row and pre8 are rewritten for the next row
   }
-  if (threadIdx.x <= a.n_r) a.ws[((int64_t)s * kEeGroups + g) * (a.n_r + 1) + threadIdx.x] = acc;
+  // the wavefronts' sums in LDS, then added in wavefront order
+  if (lane < a.n_r) fin[lane] = acc;
+  if (lane == 0) fin[a.n_r] = tot;
+  __syncthreads();
+  if ((int)threadIdx.x <= a.n_r) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += reinterpret_cast<const double*>(ee_smem + (size_t)w * ee_wave_lds(M))[threadIdx.x];
+    a.ws[((int64_t)s * kEeGroups + g) * (a.n_r + 1) + threadIdx.x] = t;
+  }
 }
 
-// Pass 2: the groups of PSF s added in order; ee = inside / total.
-__global__ __launch_bounds__(64) void ee_final_kernel(const EeLaunch a) {
-  const int s = blockIdx.x, k = threadIdx.x;
-  if (k >= a.n_r) return;
+// Pass 2: block s adds the groups of PSF s and divides by the total.  Wavefront w takes entries
+// k = w, w + 4, ... <= n_r; lane l adds groups l, l + 64, ... in order, then a fixed tree over
+// the lanes.
+__global__ __launch_bounds__(256) void ee_final_kernel(const EeLaunch a) {
+  __shared__ double s_tot[kMaxRadii + 1];
+  const int s = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double* w = a.ws + (int64_t)s * kEeGroups * (a.n_r + 1);
-  double in = 0.0, tot = 0.0;
-  for (int g = 0; g < kEeGroups; ++g) {
-    in += w[g * (a.n_r + 1) + k];
-    tot += w[g * (a.n_r + 1) + a.n_r];
+  for (int k = wave; k <= a.n_r; k += 4) {
+    double x = 0.0;
+    for (int gi = lane; gi < kEeGroups; gi += 64) x += w[gi * (a.n_r + 1) + k];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    if (lane == 0) s_tot[k] = x;
   }
-  a.ee[(int64_t)s * a.n_r + k] = tot > 0.0 ? in / tot : 0.0;
+  __syncthreads();
+  if ((int)threadIdx.x < a.n_r) {
+    const double tot = s_tot[a.n_r], in = s_tot[threadIdx.x];
+    a.ee[(int64_t)s * a.n_r + threadIdx.x] = tot > 0.0 ? in / tot : 0.0;
+  }
 }
 
 hipError_t launch_encircled_energy(const EeLaunch& a, hipStream_t st) {
-  hipLaunchKernelGGL(ee_rows_kernel, dim3(kEeGroups, (unsigned)a.n_psf), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(ee_final_kernel, dim3((unsigned)a.n_psf), dim3(64), 0, st, a);
+  // 4 wavefronts per block when their LDS fits in 64 KB (M <= 3100 or so), else 2 (M <= 4096)
+  const int nw = 4 * ee_wave_lds(a.m) <= 65536 ? 4 : 2;
+  hipLaunchKernelGGL(ee_rows_kernel, dim3(kEeGroups, (unsigned)a.n_psf), dim3(64 * nw), nw * ee_wave_lds(a.m), st, a);
+  hipLaunchKernelGGL(ee_final_kernel, dim3((unsigned)a.n_psf), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
