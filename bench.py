@@ -512,6 +512,50 @@ def served(duration_s=30.0, warm_s=2.0):
     return main, sweep, knee
 
 
+# (name, VALU instructions per iteration of the probe's loop)
+VALU_PROBE_KINDS = (("fp32 fma", 16), ("fp32 add", 16), ("dpp move", 16), ("sine", 16), ("fp64 fma", 16),
+                    ("64-bit integer multiply-add + xor", 32))
+
+
+def valu_probe(blocks=2048, iters=2048, reps=5):
+    """Issue cost of VALU instruction kinds (lib/libshw_probe.so): 8 independent chains per lane,
+    blocks of 256 lanes (2048 blocks: 8 wavefronts on every SIMD of 256 CUs; the FMA probe also at
+    2 and 1 wavefronts per SIMD).  Cycles per wave64 instruction per SIMD at 2.4 GHz from the launch
+    time (HIP events, mean of `reps` launches)."""
+    import ctypes
+
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1408_0698_amd", "lib", "libshw_probe.so"))
+    lib.shw_probe_valu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    lib.shw_probe_valu.restype = ctypes.c_int
+    torch.cuda.set_device(0)
+    out = torch.zeros(blocks * 256, device="cuda")
+    st = torch.cuda.current_stream()
+    runs = [(kind, name, per_iter, blocks) for kind, (name, per_iter) in enumerate(VALU_PROBE_KINDS)]
+    runs += [(0, VALU_PROBE_KINDS[0][0], VALU_PROBE_KINDS[0][1], b) for b in (blocks // 4, blocks // 8)]
+    res = []
+    for kind, name, per_iter, nb in runs:
+        def launch():
+            rc = lib.shw_probe_valu(kind, nb, iters, ctypes.c_void_p(out.data_ptr()),
+                                    ctypes.c_void_p(st.cuda_stream))
+            if rc != 0:
+                raise RuntimeError(f"shw_probe_valu({kind}) returned {rc}")
+        launch()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            launch()
+        e1.record(st)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        waves_per_simd = nb * 4 / (256 * 4)
+        res.append({"probe": name, "blocks": nb, "waves_per_simd": waves_per_simd, "ms": ms,
+                    "wave_instructions": nb * 4 * iters * per_iter,
+                    "cycles_per_wave_instruction_per_simd_at_2.4GHz":
+                        ms * 1e-3 * 2.4e9 / (waves_per_simd * iters * per_iter)})
+    return {"valu_probe": res, "lanes_per_block": 256, "iters": iters}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -530,11 +574,16 @@ def main():
                     help="with --no-autotune: the launch variant (default: the plan's)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before timing, run 5 plain device copies of this many MB (profiler counter scale)")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="only time the VALU issue probes (calibration of the roofline's issue model) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note",
               file=sys.stderr)
         sys.exit(2)
+    if args.valu_probe:
+        print(json.dumps(valu_probe()))
+        return
 
     import numpy as np
     import torch
@@ -628,7 +677,7 @@ def main():
                                   "SQ_INSTS_VALU - SQ_ACTIVE_INST_VALU2, from the committed counters of another "
                                   "run) over this run's launch time, against 256 CU x 4 SIMD x 2.4 GHz / 4 cycles; "
                                   "a stream of independent FP32 FMAs at full occupancy reaches about 0.75 by this "
-                                  "measure",
+                                  "measure (bench.py --valu-probe, profiles/valu_issue_probe.md)",
                 "nominal_tflops": nominal,
                 "nominal_note": "3 x 5 N^2 log2 N^2 per sub-aperture (three full 40x40 transforms); the "
                                 "band-limited kernels execute fewer operations",

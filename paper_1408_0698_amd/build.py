@@ -3,7 +3,8 @@
     python -m paper_1408_0698_amd.build
 
 Objects go to paper_1408_0698_amd/_build/, the library to
-paper_1408_0698_amd/lib/libshwfs.so.
+paper_1408_0698_amd/lib/libshwfs.so; the VALU issue probe (measurement only) to
+paper_1408_0698_amd/lib/libshw_probe.so.
 """
 from __future__ import annotations
 
@@ -19,6 +20,9 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libshwfs.so")
+# calibration kernels of the roofline's VALU issue model (bench.py --valu-probe); not part of libshwfs
+PROBE_SRC = os.path.join(CSRC, "probe", "valu_issue_probe.hip")
+PROBE_LIB = os.path.join(LIBDIR, "libshw_probe.so")
 ARCH = os.environ.get("SHW_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for every HIP translation unit.
@@ -64,8 +68,14 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [hipcc(), *HIPFLAGS, "-shared", "-x", "hip", PROBE_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"probe build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {PROBE_LIB}")
     return LIB
 
 
