@@ -272,8 +272,11 @@ int shw_wfs_plan_destroy(shw_wfs_plan* plan);
  * sodium plans, 2 for the other sodium plans, 0 otherwise.
  * shw_wfs_plan_autotune times every variant on the given inputs
  * (reps launches each after two warm-up launches, HIP events on the stream;
- * synchronous), selects the fastest and returns its index in *best and the
- * per-variant milliseconds per launch in ms (nullable, n entries).
+ * synchronous), selects the fastest, except that the plan's starting variant
+ * above is kept when it is within 2 % of the fastest (launch times vary by a
+ * few per cent between runs; for band-limited shapes it is the form with the
+ * least HBM traffic), and returns its index in *best and the per-variant
+ * milliseconds per launch in ms (nullable, n entries).
  */
 int shw_wfs_plan_variant_count(const shw_wfs_plan* plan, int32_t* n);
 int shw_wfs_plan_set_variant(shw_wfs_plan* plan, int32_t variant);
