@@ -277,7 +277,8 @@ class WfsPlan:
         return best.value, list(ms)
 
     def autotune(self, opd, slopes, reps=20, stream=None):
-        """Time every launch variant on these inputs; select the fastest.  Returns (best, [ms per launch])."""
+        """Time every launch variant on these inputs; select the fastest (the plan's default when it is
+        within 2 % of the fastest).  Returns (best, [ms per launch])."""
         n = self.n_variants
         ms = (C.c_float * n)()
         best = C.c_int32(-1)

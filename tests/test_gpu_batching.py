@@ -99,7 +99,12 @@ def test_autotune_selects_a_variant(torch_dev, tmp_path, monkeypatch):
     sl = torch_dev.zeros((1, 6, 2, plan.n_valid), device="cuda")
     rec = autotune.tuned_variant(plan, opd, sl, "gfx950", reps=3)
     assert 0 <= rec["variant"] < plan.n_variants and len(rec["ms_per_launch"]) == plan.n_variants
-    assert min(rec["ms_per_launch"]) == rec["ms_per_launch"][rec["variant"]]
+    # the fastest, except that the plan's default (13 for this band-limited shape) is kept within 2 %
+    ms, fastest = rec["ms_per_launch"], min(rec["ms_per_launch"])
+    if ms[13] <= 1.02 * fastest * (1 - 1e-6):
+        assert rec["variant"] == 13, ms
+    elif ms[13] > 1.02 * fastest * (1 + 1e-6):
+        assert ms[rec["variant"]] == fastest, ms
     rec2 = autotune.tuned_variant(plan, opd, sl, "gfx950")
     assert rec2["variant"] == rec["variant"] and rec2["noise_head"] == rec["noise_head"]
     # the record names the parameters of the chosen variant, and the head search ran for a
