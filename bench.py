@@ -692,7 +692,7 @@ def main():
                 "kernel": f"sh_wfs_measure launch variant {variant}: {kernels}",
                 "avg_launch_ms": avg_launch_ms}
     out = {
-        "metric": "SH-WFS frames/s (6 LGS, 80x80 subaps)",
+        "metric": "SH-WFS frames/s (6 LGS, 80x80 subaps) + p50/p99 latency; % FP32/HBM roofline",
         "value": value,
         "unit": "frames/s",
         "n_gpus": 1,
