@@ -213,3 +213,20 @@ def test_geometry_and_psf_extras_argument_checks():
     assert s._lib.psf_resample_accumulate(1, fake, 1.0, C.c_float(1.0), C.c_void_p(0x9000), None) == s.E_INVALID
     assert s._lib.psf_resample_accumulate(64, fake, 0.0, C.c_float(1.0), C.c_void_p(0x90000), None) == s.E_INVALID
     assert s._lib.psf_resample_accumulate(64, fake, 1.0, C.c_float(1.0), C.c_void_p(0x1100), None) == s.E_INVALID
+
+
+def test_issue_probe_library_is_separate_and_checks_arguments():
+    """The VALU issue probe (bench.py --valu-probe) is its own library, not part of the boundary:
+    it exports its two entry points, libshwfs does not, and bad sizes are refused on the host."""
+    probe = C.CDLL(os.path.join(ROOT, "paper_1408_0698_amd", "lib", "libshw_probe.so"))
+    probe.shw_probe_valu.restype = C.c_int
+    probe.shw_probe_valu.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+    probe.shw_probe_valu_kinds.restype = C.c_int
+    assert probe.shw_probe_valu_kinds() == 6
+    buf = (C.c_float * 256)()
+    assert probe.shw_probe_valu(0, 0, 16, C.cast(buf, C.c_void_p), None) == -1      # no blocks
+    assert probe.shw_probe_valu(0, 1, 0, C.cast(buf, C.c_void_p), None) == -1      # no iterations
+    assert probe.shw_probe_valu(0, 1, 16, None, None) == -1                       # no output
+    assert probe.shw_probe_valu(6, 1, 16, C.cast(buf, C.c_void_p), None) == -1    # no such kind
+    lib = C.CDLL(os.path.join(ROOT, "paper_1408_0698_amd", "lib", "libshwfs.so"))
+    assert not hasattr(lib, "shw_probe_valu")
