@@ -363,7 +363,7 @@ def ex_psf_extras(stream):
         radii = [2.0 * (k + 1) for k in range(20)]
         # the first call grows the plan's workspaces: outside the timed calls
         ee = plans[0].encircled_energy(acc, radii, stream=stream)
-        ms_ee = _time(lambda k: plans[0].encircled_energy(acc, radii, stream=stream), 5, stream)
+        ms_ee = _time(lambda k: plans[0].encircled_energy(acc, radii, out=ee, stream=stream), 20, stream)
 
         def poly_step(k):
             poly.zero_()
