@@ -536,17 +536,17 @@ def valu_probe(blocks=2048, iters=2048, reps=5):
     runs = [(kind, name, per_iter, blocks) for kind, (name, per_iter) in enumerate(VALU_PROBE_KINDS)]
     runs += [(0, VALU_PROBE_KINDS[0][0], VALU_PROBE_KINDS[0][1], b) for b in (blocks // 4, blocks // 8)]
     res = []
+    def launch(kind, nb):
+        rc = lib.shw_probe_valu(kind, nb, iters, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st.cuda_stream))
+        if rc != 0:
+            raise RuntimeError(f"shw_probe_valu({kind}) returned {rc}")
+
     for kind, name, per_iter, nb in runs:
-        def launch():
-            rc = lib.shw_probe_valu(kind, nb, iters, ctypes.c_void_p(out.data_ptr()),
-                                    ctypes.c_void_p(st.cuda_stream))
-            if rc != 0:
-                raise RuntimeError(f"shw_probe_valu({kind}) returned {rc}")
-        launch()
+        launch(kind, nb)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(st)
         for _ in range(reps):
-            launch()
+            launch(kind, nb)
         e1.record(st)
         e1.synchronize()
         ms = e0.elapsed_time(e1) / reps
